@@ -1,0 +1,150 @@
+"""Benchmark of the fused coupled-LBM cathode step on one MI355X.
+
+Workload: the 4096x1024 FP32 cathode (per-cell porosity U[0.4, 0.8],
+Kozeny-Carman permeability, Re 50, 0.5 V, 343 K).  A step is one time step
+of the whole coupled update (stream, boundary columns, macros, MRT flow
+collision with porous drag, CL reaction, two scalar collisions) over the
+whole lattice.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_LU_POPS = 19 * 4 * 2  # 19 FP32 populations read and written per lattice update
+BYTES_PER_LU_PHI = 4            # per-cell porosity read
+COUNTERS = os.path.join(ROOT, "profiles", "step2d_4096x1024_fp32_counters.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for fn in ("lbm_device.hpp", "lbm_kernels2d.hpp"):
+        with open(os.path.join(ROOT, "paper_2103_01444_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(per_launch_cells: int):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None
+    if the kernel source changed since they were taken."""
+    if not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as f:
+        c = json.load(f)
+    if c.get("kernel_source_hash") != kernel_source_hash() or c.get("cells") != per_launch_cells:
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, phi, target_s: float = 15.0):
+    """The FP64 oracle on the host cores, timed on a bounded sample: whole
+    4096x1024 lattice, as many steps as fit in about target_s seconds."""
+    import torch
+
+    from oracle import lbm2d as L
+    m = L.Model(L.geometry_from_workload(w), L.Params.from_workload(w), phi=torch.as_tensor(phi))
+    s = m.initial_state()
+    t0 = time.perf_counter()
+    s = m.step(s)
+    first = time.perf_counter() - t0
+    n = max(1, min(20, int(target_s / max(first, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    for _ in range(n):
+        s = m.step(s)
+    dt = time.perf_counter() - t0
+    cells = w["nx"] * w["ny"]
+    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, full {w['nx']}x{w['ny']} lattice, {n} steps after 1 untimed "
+                      f"({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2103_01444_amd import Cathode
+
+    w = W.cathode2d_4096x1024()
+    phi = W.porosity_field(w)
+    print(f"bench: {w['name']} fp32, warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    sim = Cathode.from_workload(w, phi=phi)
+    sim.step(args.warmup)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    stream = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    e1.record(stream)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    obs = sim.observables()
+    cells = w["nx"] * w["ny"]
+    mlups = cells * args.steps / (wall) / 1e6
+    launch_s = ev_ms / 1e3 / args.steps  # one kernel launch per step
+    bytes_per_launch = cells * (BYTES_PER_LU_POPS + BYTES_PER_LU_PHI)
+    achieved = bytes_per_launch / launch_s / 1e9
+    traffic = measured_traffic(cells)
+    print(f"bench: {mlups:.1f} MLUPS, kernel avg {launch_s * 1e6:.2f} us, {achieved:.0f} GB/s, "
+          f"I = {obs['current_density']:.4e} A/cm2", file=sys.stderr, flush=True)
+    if not np.isfinite(obs["current_density"]):
+        raise SystemExit("non-finite result")
+
+    line = {
+        "metric": "coupled-LBM MLUPS, % of HBM BW peak; batched sweep and adjoint vs plain, 1 GPU",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded porosity field)",
+        "config": {"workload": w["name"], "nx": w["nx"], "ny": w["ny"],
+                   "layers": [w["ny_channel"], w["ny_gdl"], w["ny_cl"]], "Re": w["Re"], "V_op": w["V_op"],
+                   "T_in_K": w["T_in"], "porosity": "per-cell U[0.4,0.8], seed 21030144"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "kernel": {"name": "k_step<float, MAT_PHI>", "avg_launch_us": round(launch_s * 1e6, 3),
+                   "algorithmic_bytes_per_launch": bytes_per_launch,
+                   "bytes_per_lattice_update": BYTES_PER_LU_POPS + BYTES_PER_LU_PHI},
+        "observables": {"current_density_A_cm2": obs["current_density"], "T_max_K": obs["T_max"],
+                        "o2_utilisation": obs["o2_utilisation"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, phi)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

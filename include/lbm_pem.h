@@ -1,0 +1,208 @@
+/*
+ * lbm_pem.h -- C ABI of the MI355X coupled lattice-Boltzmann PEM-cathode solver.
+ *
+ * The library advances the coupled model of Jithin, Siddharth, Das and De,
+ * "Simulation of coupled heat and mass transport with reaction in PEM fuel
+ * cell cathode using lattice Boltzmann method":
+ *   - D2Q9 multiple-relaxation-time flow with Darcy-Forchheimer drag in the
+ *     porous gas diffusion layer (GDL) and catalyst layer (CL)  (Section 2.1,
+ *     Eqs. 1-8);
+ *   - D2Q5 multiple-relaxation-time temperature and O2 lattices advected by
+ *     the flow velocity  (Section 2.2, Eqs. 9-11);
+ *   - Tafel oxygen-reduction sink and reaction heat in the CL (Section 4,
+ *     Eqs. 12-17), Bruggeman diffusivity (Eq. 18), mixture thermal
+ *     diffusivity (Eq. 19);
+ *   - half-way bounce-back walls, a parabolic velocity / Dirichlet T and O2
+ *     inlet over the channel rows and a zero-pressure, zero-gradient outlet
+ *     (Section 4 boundary conditions).
+ * One call of lbm_step performs, per time step and per lattice node, the
+ * pull-streaming, the boundary columns, the macroscopic fields, the flow
+ * collision, the reaction and both scalar collisions in one kernel pass.
+ *
+ * Conventions
+ *   Lattice: x = 0 .. nx-1 from inlet to outlet, y = 0 .. ny-1 from the
+ *   channel-side wall through the GDL to the CL.  Rows [0, ny_channel) are
+ *   the clear gas channel, the next ny_gdl rows the GDL, the last ny_cl rows
+ *   the CL.  Lattice units dx = dt = 1 inside; physical scales follow from
+ *   lbm_params (dx from the GDL thickness, dt from the O2 diffusivity).
+ *   Per-cell arrays are dense, row-major [ny][nx] (x fastest), in the
+ *   context precision (float for precision 32, double for 64), in device
+ *   memory.
+ *   State: after n steps the context holds the post-collision populations
+ *   of step n.  "Fields" and "observables" are evaluated on the
+ *   pre-collision populations obtained by streaming that state and applying
+ *   the boundary columns (what step n+1 starts from).
+ *   Populations (lbm_get_populations / lbm_set_populations) are 19 dense
+ *   planes [19][ny][nx]: planes 0-8 the D2Q9 flow populations in the order
+ *   e = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1) (Eq. 2),
+ *   planes 9-13 the D2Q5 temperature-rise populations (theta = T - T_in, K),
+ *   planes 14-18 the D2Q5 O2 populations (c = C / C_ref), D2Q5 order as the
+ *   first five D2Q9 vectors (Eq. 9).
+ *
+ * Ownership: the caller owns all device memory.  lbm_create receives a
+ * device workspace of at least lbm_workspace_bytes() bytes that must stay
+ * alive and untouched until lbm_destroy; the library never allocates or
+ * frees device memory.  The library owns only the opaque host context.
+ * Threading: one host thread per context.  Every call enqueues work on the
+ * HIP stream given to lbm_create; calls documented "synchronous" wait for it.
+ * Errors: every call returns an lbm_status; nothing aborts or throws across
+ * the ABI.  Device errors of asynchronous calls surface at the next
+ * synchronous call as LBM_ERR_DEVICE.  lbm_last_error() gives a message.
+ */
+#ifndef LBM_PEM_H
+#define LBM_PEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbm_status {
+  LBM_OK = 0,
+  LBM_ERR_INVALID_ARG = 1,     /* null pointer, bad size, inconsistent geometry */
+  LBM_ERR_UNSTABLE_PARAMS = 2, /* parameters outside the scheme's stability / positivity range */
+  LBM_ERR_DEVICE = 3,          /* a HIP runtime or kernel error */
+  LBM_ERR_NONFINITE = 4,       /* a reduced observable is NaN or infinite */
+  LBM_ERR_STATE = 5            /* call out of order (e.g. step before set_params) */
+} lbm_status;
+
+/* lbm_geometry.flags */
+#define LBM_PERIODIC_X 1u  /* no inlet/outlet: x wraps (test configurations) */
+#define LBM_PERIODIC_Y 2u  /* no y walls: y wraps (test configurations) */
+#define LBM_BODY_FORCE 4u  /* add phi * (body_force_x, body_force_y) to the flow force */
+#define LBM_NO_REACTION 8u /* switch the CL reaction off */
+
+typedef struct lbm_geometry {
+  int32_t nx, ny;                      /* nx >= 3, ny >= 1 */
+  int32_t ny_channel, ny_gdl, ny_cl;   /* non-negative, sum to ny */
+  int32_t precision;                   /* 32 (float populations) or 64 (double) */
+  uint32_t flags;                      /* LBM_* flags above */
+} lbm_geometry;
+
+/*
+ * Model inputs.  lbm_default_params() fills the paper's constants
+ * (Nomenclature, Eqs. 7, 13-19) and the solver defaults; the operating point
+ * (V_op, T_in_K, Re) and the porous-layer properties are what a user varies
+ * (Section 5).
+ */
+typedef struct lbm_params {
+  double tau_f;            /* flow relaxation time, nu = (tau_f - 1/2)/3 (Section 2.1); > 0.5 */
+  double D_f_lat;          /* O2 diffusivity in the clear gas, lattice units; sets dt */
+  double Re;               /* inlet Reynolds number U_avg * ny_channel / nu (Table 1 definition) */
+  double T_in_K;           /* inlet / operating temperature, K */
+  double c_in;             /* inlet O2 concentration relative to C_ref */
+  double V_op;             /* operating voltage, V (Eq. 14) */
+  double phi_gdl;          /* porosity of GDL and CL when no per-cell field is given */
+  double Da_gdl;           /* Darcy number K / h^2, h = GDL thickness (Table 2) */
+  double deff_ratio_gdl;   /* D_eff / D_f in GDL and CL; 0 selects Bruggeman phi^1.5 (Eq. 18) */
+  double dp_lat;           /* Kozeny-Carman particle diameter in lattice units (Eq. 7); >0 derives K from porosity */
+  double gdl_thickness_cm; /* physical GDL thickness; dx = gdl_thickness_cm / ny_gdl */
+  double dx_cm;            /* > 0 overrides the lattice spacing (cm) */
+  double D_O2_cm2s;        /* clear-gas O2 diffusivity, cm^2/s; dt = D_f_lat dx^2 / D_O2 */
+  double aj0_ref;          /* reference exchange current density x area, A/cm^3 (Eq. 13) */
+  double C_ref;            /* reference O2 concentration, mol/cm^3 */
+  double alpha_c;          /* cathodic transfer coefficient */
+  double faraday;          /* C/mol */
+  double R_gas;            /* J/(mol K) */
+  double E_over_R;         /* Arrhenius temperature of Eq. 17, K */
+  double T_arrh;           /* reference temperature of Eq. 17, K */
+  double U0_slope;         /* open-circuit voltage slope, V/K (Eq. 16) */
+  double U0_icept;         /* open-circuit voltage intercept, V (Eq. 16) */
+  double k_f, k_s;         /* fluid / solid thermal conductivity, W/(m K) (Eq. 19) */
+  double rhocp_f, rhocp_s; /* fluid / solid volumetric heat capacity, J/(cm^3 K) (Eq. 19) */
+  double body_force_x;     /* acceleration, lattice units (LBM_BODY_FORCE only) */
+  double body_force_y;
+  int32_t independent_fields; /* nonzero: keep porosity, 1/K and D_eff as three per-cell fields */
+  int32_t reserved;
+} lbm_params;
+
+/* Observables of Section 5 on the current state (see Conventions). */
+typedef struct lbm_obs {
+  int64_t step;
+  double current_density;  /* mean over x of i(x) = sum_CL (-j) dx, A/cm^2 */
+  double power_density;    /* V_op * current_density, W/cm^2 */
+  double heat_rate;        /* mean over x of sum_CL Q dx, W/cm^2 (Eq. 15) */
+  double o2_utilisation;   /* O2 consumed per step / O2 advected in per step */
+  double T_max;            /* maximum temperature, K */
+  double sum_f;            /* sum of all flow populations */
+  double sum_theta;        /* sum of the temperature-rise lattice (K x cells) */
+  double sum_c;            /* sum of the O2 lattice */
+  double consumed_c;       /* O2 the next step removes (sum over CL) */
+  double heat_added;       /* temperature rise the next step adds (sum over CL, K x cells) */
+} lbm_obs;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fill *p with the paper's constants and the solver defaults. */
+void lbm_default_params(lbm_params* p);
+
+/* Device workspace bytes a context of this geometry needs; 0 if invalid. */
+size_t lbm_workspace_bytes(const lbm_geometry* g);
+
+/* Create a context on the current HIP device.  dev_ws: device memory of at
+ * least lbm_workspace_bytes(g) bytes, 256-byte aligned; hip_stream: a
+ * hipStream_t (NULL = default stream).  Errors: LBM_ERR_INVALID_ARG. */
+lbm_status lbm_create(const lbm_geometry* g, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                      lbm_ctx** out);
+
+/* Set the model inputs (Sections 2 and 4).  phi, inv_k (1/K, lattice units)
+ * and d_eff (O2 diffusivity, lattice units) are optional per-cell device
+ * arrays [ny][nx]; NULL takes the layered value from *p (channel: phi = 1,
+ * 1/K = 0, D = D_f_lat; GDL and CL: phi_gdl, Da_gdl or Kozeny-Carman,
+ * deff_ratio_gdl or Bruggeman).  The arrays are copied; the caller may free
+ * them afterwards.  Synchronous.  Errors: LBM_ERR_INVALID_ARG,
+ * LBM_ERR_UNSTABLE_PARAMS (tau_f <= 0.5, a diffusivity outside
+ * (0, 1/(4 sqrt 3)], porosity outside (0, 1], 1/K < 0, inlet peak velocity
+ * above 0.1). */
+lbm_status lbm_set_params(lbm_ctx* ctx, const lbm_params* p, const void* phi, const void* inv_k,
+                          const void* d_eff);
+
+/* Initial state: fluid at rest at zero pressure, temperature T_in, O2 c_in
+ * everywhere (equilibrium populations).  Resets the step counter.  Async. */
+lbm_status lbm_init_equilibrium(lbm_ctx* ctx);
+
+/* Advance nsteps time steps (Eq. 1 and the scalar equation of Eq. 10 with
+ * the CL source).  Async; never synchronizes. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Observables (Section 5) of the current state, reduced in double precision
+ * in a fixed order (deterministic).  prof_i, prof_c, prof_T: optional host
+ * arrays of nx doubles for the local current density i(x) (A/cm^2) and the
+ * O2 and temperature (K) on the CL row next to the GDL.  Synchronous.
+ * LBM_ERR_NONFINITE if any reduced value is not finite. */
+lbm_status lbm_observables(lbm_ctx* ctx, lbm_obs* out, double* prof_i, double* prof_c,
+                           double* prof_T);
+
+/* Macroscopic fields of the current state into caller device arrays
+ * [ny][nx] (context precision): u_x, u_y (lattice), p (lattice, Section 2.1
+ * pressure relation), T (K), c (relative).  NULL skips a field.  Async. */
+lbm_status lbm_get_fields(lbm_ctx* ctx, void* ux, void* uy, void* p, void* T, void* c);
+
+/* Canonical post-collision populations, 19 dense planes (see Conventions),
+ * context precision, device memory.  Async. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, void* dev_dst);
+lbm_status lbm_set_populations(lbm_ctx* ctx, const void* dev_src, int64_t step);
+
+/* Opaque state snapshot (device memory of lbm_state_bytes() bytes) for
+ * checkpoint / restart; restoring reproduces later steps bit for bit. */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+lbm_status lbm_save_state(lbm_ctx* ctx, void* dev_dst, int64_t* step_out);
+lbm_status lbm_load_state(lbm_ctx* ctx, const void* dev_src, int64_t step);
+
+/* Number of steps taken since lbm_init_equilibrium / the last load. */
+int64_t lbm_step_count(const lbm_ctx* ctx);
+
+/* Wait for the context's stream; reports pending device errors. */
+lbm_status lbm_synchronize(lbm_ctx* ctx);
+
+void lbm_destroy(lbm_ctx* ctx);
+const char* lbm_status_string(lbm_status s);
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_PEM_H */

@@ -1,0 +1,592 @@
+// Host side of the C ABI declared in include/lbm_pem.h: context, parameter
+// derivation and validation, launches.  No device memory is allocated here;
+// everything lives in the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_kernels2d.hpp"
+#include "lbm_pem.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr double kMaxDiff = 0.14433756729740643;  // 1/(4 sqrt 3): b <= 1 keeps g0_eq >= 0
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  int pitch = 0;
+  int64_t plane = 0;  // elements
+  size_t esize = 0;
+  size_t off_state[2] = {0, 0};
+  size_t off_mat = 0;
+  size_t off_partial = 0;
+  size_t off_prof = 0;
+  size_t off_out = 0;
+  size_t total = 0;
+  int nblocks_obs = 0;
+};
+
+bool geometry_ok(const lbm_geometry* g) {
+  if (!g) return false;
+  if (g->nx < 3 || g->ny < 1 || g->ny > 65535) return false;  // rows map to gridDim.y
+  if (g->ny_channel < 0 || g->ny_gdl < 0 || g->ny_cl < 0) return false;
+  if (g->ny_channel + g->ny_gdl + g->ny_cl != g->ny) return false;
+  if (g->precision != 32 && g->precision != 64) return false;
+  if (g->flags & ~(LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_BODY_FORCE | LBM_NO_REACTION)) return false;
+  const int64_t pitch = (int64_t(g->nx) + 63) / 64 * 64;
+  if (pitch * g->ny * 19 >= (int64_t(1) << 31)) return false;  // 32-bit element offsets
+  return true;
+}
+
+Layout make_layout(const lbm_geometry* g) {
+  Layout L;
+  L.esize = g->precision == 64 ? 8 : 4;
+  L.pitch = (g->nx + 63) / 64 * 64;
+  L.plane = int64_t(L.pitch) * g->ny;
+  const size_t state = align_up(size_t(19) * L.plane * L.esize);
+  L.nblocks_obs = ((g->nx + kBlock - 1) / kBlock) * g->ny;
+  size_t o = 0;
+  L.off_state[0] = o;
+  o += state;
+  L.off_state[1] = o;
+  o += state;
+  L.off_mat = o;
+  o += align_up(size_t(3) * L.plane * L.esize);
+  L.off_partial = o;
+  o += align_up(size_t(L.nblocks_obs) * kObsQ * sizeof(double));
+  L.off_prof = o;
+  o += align_up(size_t(3) * g->nx * sizeof(double));
+  L.off_out = o;
+  o += align_up(16 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_geometry g{};
+  lbm_params p{};
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int cur = 0;            // index of the state buffer holding the current state
+  int64_t step = 0;
+  bool params_set = false;
+  int mat = MAT_LAYERED;
+  Consts<float> kf{};
+  Consts<double> kd{};
+  double dx = 0, dt = 0, u_avg = 0, inflow = 0;
+  std::string err;
+
+  void* state(int i) { return ws + L.off_state[i]; }
+  void* mat_plane(int i) { return ws + L.off_mat + size_t(i) * L.plane * L.esize; }
+  double* partial() { return reinterpret_cast<double*>(ws + L.off_partial); }
+  double* prof() { return reinterpret_cast<double*>(ws + L.off_prof); }
+  double* out() { return reinterpret_cast<double*>(ws + L.off_out); }
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+lbm_status check_launch(lbm_ctx* c, const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+template <typename R>
+void fill_consts(Consts<R>& k, const lbm_ctx* c, double nu, double invk_gdl, double d_gdl,
+                 double alpha_scale, double ln_k0) {
+  const lbm_geometry& g = c->g;
+  const lbm_params& p = c->p;
+  k.nx = g.nx;
+  k.ny = g.ny;
+  k.pitch = c->L.pitch;
+  k.ny_ch = g.ny_channel;
+  k.y_cl0 = g.ny_channel + g.ny_gdl;
+  k.flags = g.flags;
+  k.plane = int32_t(c->L.plane);
+  k.pad_ = 0;
+  const double se = 1.0 / p.tau_f;
+  k.s_e = R(se);
+  k.s_q = R(8.0 * (2.0 - se) / (8.0 - se));
+  k.nu = R(nu);
+  k.u_in_coef = g.ny_channel > 0 ? R(6.0 * c->u_avg / (double(g.ny_channel) * g.ny_channel)) : R(0);
+  k.ax = R(p.body_force_x);
+  k.ay = R(p.body_force_y);
+  k.phi_gdl = R(p.phi_gdl);
+  k.invk_gdl = R(invk_gdl);
+  k.d_gdl = R(d_gdl);
+  k.D_f = R(p.D_f_lat);
+  k.kc_inv = p.dp_lat > 0 ? R(1.0 / (0.0067 * p.dp_lat * p.dp_lat)) : R(0);
+  k.deff_ratio = R(p.deff_ratio_gdl);
+  k.k_f = R(p.k_f);
+  k.k_s = R(p.k_s);
+  k.rhocp_f = R(p.rhocp_f);
+  k.rhocp_s = R(p.rhocp_s);
+  k.alpha_scale = R(alpha_scale);
+  k.T_in = R(p.T_in_K);
+  k.c_in = R(p.c_in);
+  k.V_op = R(p.V_op);
+  k.U0_slope = R(p.U0_slope);
+  k.U0_icept = R(p.U0_icept);
+  k.ln_k0 = R(ln_k0);
+  k.E_over_R = R(p.E_over_R);
+  k.inv_T_arrh = R(1.0 / p.T_arrh);
+  k.aF_over_R = R(p.alpha_c * p.faraday / p.R_gas);
+  k.four_f_cref = R(4.0 * p.faraday * p.C_ref);
+}
+
+// Lattice thermal diffusivity of Eq. 19 at porosity phi.
+double alpha_lat(const lbm_params& p, double phi, double alpha_scale) {
+  const double rc = phi * p.rhocp_f + (1.0 - phi) * p.rhocp_s;
+  return (p.k_f * phi + p.k_s * (1.0 - phi)) * alpha_scale / rc;
+}
+
+template <typename R>
+bool host_range(lbm_ctx* c, const void* dev, double& lo, double& hi) {
+  const size_t n = size_t(c->g.nx) * c->g.ny;
+  std::vector<R> h(n);
+  if (hipMemcpyAsync(h.data(), dev, n * sizeof(R), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return false;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return false;
+  lo = 1e300;
+  hi = -1e300;
+  for (size_t i = 0; i < n; ++i) {
+    const double v = double(h[i]);
+    if (!std::isfinite(v)) {
+      lo = -1e300;
+      return true;
+    }
+    lo = std::min(lo, v);
+    hi = std::max(hi, v);
+  }
+  return true;
+}
+
+template <typename R>
+hipError_t launch_pitch_copy(lbm_ctx* c, const void* src, void* dst) {
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  hipLaunchKernelGGL(k_pitch_copy<R>, grid, dim3(kBlock), 0, c->stream, static_cast<const R*>(src),
+                     static_cast<R*>(dst), c->g.nx, c->L.pitch);
+  return hipGetLastError();
+}
+
+template <typename R>
+const Consts<R>& consts(const lbm_ctx* c);
+template <>
+const Consts<float>& consts<float>(const lbm_ctx* c) { return c->kf; }
+template <>
+const Consts<double>& consts<double>(const lbm_ctx* c) { return c->kd; }
+
+template <typename R>
+struct MatPtrs {
+  const R *phi, *invk, *d;
+};
+template <typename R>
+MatPtrs<R> mat_ptrs(lbm_ctx* c) {
+  return {static_cast<const R*>(c->mat_plane(0)), static_cast<const R*>(c->mat_plane(1)),
+          static_cast<const R*>(c->mat_plane(2))};
+}
+
+template <typename R, int MAT>
+void launch_step_mat(lbm_ctx* c, int64_t n) {
+  const MatPtrs<R> m = mat_ptrs<R>(c);
+  const Consts<R> k = consts<R>(c);
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  for (int64_t i = 0; i < n; ++i) {
+    const R* src = static_cast<const R*>(c->state(c->cur));
+    R* dst = static_cast<R*>(c->state(c->cur ^ 1));
+    hipLaunchKernelGGL((k_step<R, MAT>), grid, dim3(kBlock), 0, c->stream, src, dst, m.phi, m.invk, m.d, k);
+    c->cur ^= 1;
+  }
+}
+
+template <typename R>
+void launch_step(lbm_ctx* c, int64_t n) {
+  switch (c->mat) {
+    case MAT_LAYERED: launch_step_mat<R, MAT_LAYERED>(c, n); break;
+    case MAT_PHI: launch_step_mat<R, MAT_PHI>(c, n); break;
+    default: launch_step_mat<R, MAT_FULL>(c, n); break;
+  }
+}
+
+template <typename R, int MAT>
+void launch_init_mat(lbm_ctx* c) {
+  const MatPtrs<R> m = mat_ptrs<R>(c);
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  hipLaunchKernelGGL((k_init<R, MAT>), grid, dim3(kBlock), 0, c->stream,
+                     static_cast<R*>(c->state(c->cur)), m.phi, m.invk, m.d, consts<R>(c));
+}
+
+template <typename R>
+void launch_init(lbm_ctx* c) {
+  switch (c->mat) {
+    case MAT_LAYERED: launch_init_mat<R, MAT_LAYERED>(c); break;
+    case MAT_PHI: launch_init_mat<R, MAT_PHI>(c); break;
+    default: launch_init_mat<R, MAT_FULL>(c); break;
+  }
+}
+
+template <typename R, int MAT>
+void launch_obs_mat(lbm_ctx* c, double i_scale) {
+  const MatPtrs<R> m = mat_ptrs<R>(c);
+  const R* src = static_cast<const R*>(c->state(c->cur));
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  hipLaunchKernelGGL((k_obs_cells<R, MAT>), grid, dim3(kBlock), 0, c->stream, src, m.phi, m.invk, m.d,
+                     consts<R>(c), c->partial());
+  hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, c->stream, c->partial(), c->L.nblocks_obs, c->out());
+  const dim3 pgrid((c->g.nx + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_obs_profiles<R, MAT>), pgrid, dim3(kBlock), 0, c->stream, src, m.phi, m.invk, m.d,
+                     consts<R>(c), i_scale, c->prof());
+}
+
+template <typename R>
+void launch_obs(lbm_ctx* c, double i_scale) {
+  switch (c->mat) {
+    case MAT_LAYERED: launch_obs_mat<R, MAT_LAYERED>(c, i_scale); break;
+    case MAT_PHI: launch_obs_mat<R, MAT_PHI>(c, i_scale); break;
+    default: launch_obs_mat<R, MAT_FULL>(c, i_scale); break;
+  }
+}
+
+template <typename R, int MAT>
+void launch_fields_mat(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* cc) {
+  const MatPtrs<R> m = mat_ptrs<R>(c);
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  hipLaunchKernelGGL((k_fields<R, MAT>), grid, dim3(kBlock), 0, c->stream,
+                     static_cast<const R*>(c->state(c->cur)), m.phi, m.invk, m.d, consts<R>(c),
+                     static_cast<R*>(ux), static_cast<R*>(uy), static_cast<R*>(p), static_cast<R*>(T),
+                     static_cast<R*>(cc));
+}
+
+template <typename R>
+void launch_fields(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* cc) {
+  switch (c->mat) {
+    case MAT_LAYERED: launch_fields_mat<R, MAT_LAYERED>(c, ux, uy, p, T, cc); break;
+    case MAT_PHI: launch_fields_mat<R, MAT_PHI>(c, ux, uy, p, T, cc); break;
+    default: launch_fields_mat<R, MAT_FULL>(c, ux, uy, p, T, cc); break;
+  }
+}
+
+template <typename R>
+lbm_status set_params_t(lbm_ctx* c, const lbm_params* p, const void* phi, const void* inv_k,
+                        const void* d_eff) {
+  const lbm_geometry& g = c->g;
+  c->p = *p;
+  // Lattice <-> physical scales: dx from the GDL thickness (or given), dt
+  // from the O2 diffusivity, D_lat = D dt / dx^2.
+  if (p->dx_cm > 0) {
+    c->dx = p->dx_cm;
+  } else if (g.ny_gdl > 0 && p->gdl_thickness_cm > 0) {
+    c->dx = p->gdl_thickness_cm / g.ny_gdl;
+  } else {
+    return fail(c, LBM_ERR_INVALID_ARG, "lattice spacing undefined: give dx_cm or a GDL with gdl_thickness_cm");
+  }
+  if (!(p->D_O2_cm2s > 0) || !(p->tau_f > 0.5))
+    return fail(c, LBM_ERR_UNSTABLE_PARAMS, "need tau_f > 0.5 and D_O2_cm2s > 0");
+  if (!(p->D_f_lat > 0) || p->D_f_lat > kMaxDiff)
+    return fail(c, LBM_ERR_UNSTABLE_PARAMS, "D_f_lat outside (0, 1/(4 sqrt 3)]");
+  if (!(p->phi_gdl > 0) || p->phi_gdl > 1) return fail(c, LBM_ERR_UNSTABLE_PARAMS, "phi_gdl outside (0, 1]");
+  if (p->Da_gdl < 0 || p->deff_ratio_gdl < 0 || p->dp_lat < 0)
+    return fail(c, LBM_ERR_INVALID_ARG, "negative Da_gdl, deff_ratio_gdl or dp_lat");
+  if (!(p->T_in_K > 0) || !(p->rhocp_f > 0) || !(p->rhocp_s > 0) || !(p->C_ref > 0) || !(p->faraday > 0))
+    return fail(c, LBM_ERR_INVALID_ARG, "non-positive temperature, heat capacity or reaction constant");
+  c->dt = p->D_f_lat * c->dx * c->dx / p->D_O2_cm2s;
+  const double nu = (p->tau_f - 0.5) / 3.0;
+  c->u_avg = g.ny_channel > 0 ? p->Re * nu / g.ny_channel : 0.0;
+  if (!(g.flags & LBM_PERIODIC_X) && 1.5 * std::fabs(c->u_avg) > 0.1)
+    return fail(c, LBM_ERR_UNSTABLE_PARAMS, "inlet peak velocity above 0.1");
+  const double invk_gdl = (p->Da_gdl > 0 && g.ny_gdl > 0) ? 1.0 / (p->Da_gdl * double(g.ny_gdl) * g.ny_gdl) : 0.0;
+  const double d_gdl = p->deff_ratio_gdl > 0 ? p->deff_ratio_gdl * p->D_f_lat
+                                             : std::pow(p->phi_gdl, 1.5) * p->D_f_lat;
+  const double alpha_scale = c->dt / (c->dx * c->dx) / 100.0;
+  const double ln_k0 = std::log(p->aj0_ref * c->dt / (4.0 * p->faraday * p->C_ref));
+  fill_consts(c->kf, c, nu, invk_gdl, d_gdl, alpha_scale, ln_k0);
+  fill_consts(c->kd, c, nu, invk_gdl, d_gdl, alpha_scale, ln_k0);
+  // Mean advective O2 inflow per step over the inlet rows (denominator of
+  // the utilisation).
+  c->inflow = 0;
+  if (!(g.flags & LBM_PERIODIC_X)) {
+    const double coef = g.ny_channel > 0 ? 6.0 * c->u_avg / (double(g.ny_channel) * g.ny_channel) : 0.0;
+    for (int y = 0; y < g.ny_channel; ++y) {
+      const double yc = y + 0.5;
+      c->inflow += coef * yc * (g.ny_channel - yc) * p->c_in;
+    }
+  }
+
+  // Material mode and per-cell arrays.
+  const bool any = phi || inv_k || d_eff;
+  if (!any && !p->independent_fields) {
+    c->mat = MAT_LAYERED;
+  } else if (phi && !inv_k && !d_eff && p->dp_lat > 0 && !p->independent_fields) {
+    c->mat = MAT_PHI;
+  } else {
+    c->mat = MAT_FULL;
+  }
+  if (phi && launch_pitch_copy<R>(c, phi, c->mat_plane(0)) != hipSuccess)
+    return fail(c, LBM_ERR_DEVICE, "copy of porosity failed");
+  if (c->mat == MAT_FULL) {
+    if (inv_k && launch_pitch_copy<R>(c, inv_k, c->mat_plane(1)) != hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "copy of 1/K failed");
+    if (d_eff && launch_pitch_copy<R>(c, d_eff, c->mat_plane(2)) != hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "copy of D_eff failed");
+    const dim3 grid((g.nx + kBlock - 1) / kBlock, g.ny);
+    hipLaunchKernelGGL(k_derive_fields<R>, grid, dim3(kBlock), 0, c->stream, static_cast<R*>(c->mat_plane(0)),
+                       static_cast<R*>(c->mat_plane(1)), static_cast<R*>(c->mat_plane(2)), consts<R>(c),
+                       phi ? 1 : 0, inv_k ? 1 : 0, d_eff ? 1 : 0);
+    if (hipGetLastError() != hipSuccess) return fail(c, LBM_ERR_DEVICE, "field derivation failed");
+  }
+
+  // Validation of porosity, permeability and both diffusivities.
+  double phi_lo = p->phi_gdl, phi_hi = 1.0, d_lo = std::min(d_gdl, p->D_f_lat), d_hi = std::max(d_gdl, p->D_f_lat);
+  double k_lo = invk_gdl;
+  if (phi) {
+    if (!host_range<R>(c, phi, phi_lo, phi_hi)) return fail(c, LBM_ERR_DEVICE, "reading porosity failed");
+  }
+  if (inv_k) {
+    double hi;
+    if (!host_range<R>(c, inv_k, k_lo, hi)) return fail(c, LBM_ERR_DEVICE, "reading 1/K failed");
+  }
+  if (d_eff) {
+    if (!host_range<R>(c, d_eff, d_lo, d_hi)) return fail(c, LBM_ERR_DEVICE, "reading D_eff failed");
+  } else if (phi) {
+    const double dl = p->deff_ratio_gdl > 0 ? p->deff_ratio_gdl * p->D_f_lat : std::pow(phi_lo, 1.5) * p->D_f_lat;
+    d_lo = std::min(dl, p->D_f_lat);
+  }
+  if (!(phi_lo > 0) || phi_hi > 1.0) return fail(c, LBM_ERR_UNSTABLE_PARAMS, "porosity outside (0, 1]");
+  if (!(k_lo >= 0)) return fail(c, LBM_ERR_UNSTABLE_PARAMS, "negative or non-finite 1/K");
+  if (!(d_lo > 0) || d_hi > kMaxDiff) return fail(c, LBM_ERR_UNSTABLE_PARAMS, "O2 diffusivity outside (0, 1/(4 sqrt 3)]");
+  // Eq. 19 is monotone in porosity: check the extremes of the range and the gas.
+  const double a1 = alpha_lat(*p, phi_lo, alpha_scale), a2 = alpha_lat(*p, phi_hi, alpha_scale);
+  const double a3 = alpha_lat(*p, 1.0, alpha_scale);
+  if (std::max({a1, a2, a3}) > kMaxDiff || !(std::min({a1, a2, a3}) > 0))
+    return fail(c, LBM_ERR_UNSTABLE_PARAMS, "thermal diffusivity outside (0, 1/(4 sqrt 3)]");
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "set_params sync failed");
+  c->params_set = true;
+  return LBM_OK;
+}
+
+template <typename R>
+lbm_status observables_t(lbm_ctx* c, lbm_obs* o, double* pi, double* pc, double* pT) {
+  const lbm_params& p = c->p;
+  const double four_fc = 4.0 * p.faraday * p.C_ref;
+  const double i_scale = four_fc / c->dt * c->dx;  // i(x) = sum_CL (4 F C_ref s_c / dt) dx
+  launch_obs<R>(c, i_scale);
+  if (lbm_status s = check_launch(c, "observables"); s != LBM_OK) return s;
+  double h[kObsQ];
+  if (hipMemcpyAsync(h, c->out(), sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return fail(c, LBM_ERR_DEVICE, "observable copy failed");
+  const size_t nx = size_t(c->g.nx);
+  std::vector<double> prof(3 * nx);
+  if (hipMemcpyAsync(prof.data(), c->prof(), 3 * nx * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return fail(c, LBM_ERR_DEVICE, "profile copy failed");
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "observables sync failed");
+  const double ncell = double(c->g.nx) * c->g.ny;
+  lbm_obs r{};
+  r.step = c->step;
+  const double sum_sc = h[3];
+  r.current_density = sum_sc * i_scale / c->g.nx;
+  r.power_density = p.V_op * r.current_density;
+  r.heat_rate = h[5] * i_scale / c->g.nx;
+  r.o2_utilisation = c->inflow > 0 ? sum_sc / c->inflow : 0.0;
+  r.T_max = p.T_in_K + h[6];
+  r.sum_f = h[0] + ncell;  // the rest population is stored as f0 - rho0
+  r.sum_theta = h[1];
+  r.sum_c = h[2];
+  r.consumed_c = sum_sc;
+  r.heat_added = h[4];
+  if (o) *o = r;
+  if (pi) std::memcpy(pi, prof.data(), nx * sizeof(double));
+  if (pc) std::memcpy(pc, prof.data() + nx, nx * sizeof(double));
+  if (pT) std::memcpy(pT, prof.data() + 2 * nx, nx * sizeof(double));
+  const double vals[] = {r.current_density, r.heat_rate, r.T_max, r.sum_f, r.sum_theta, r.sum_c, r.heat_added};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(c, LBM_ERR_NONFINITE, "non-finite observable");
+  if (h[7] > 0) return fail(c, LBM_ERR_NONFINITE, "non-finite populations");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_default_params(lbm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tau_f = 0.65;
+  p->D_f_lat = 0.0125;
+  p->Re = 10.0;
+  p->T_in_K = 353.0;
+  p->c_in = 1.0;
+  p->V_op = 0.6;
+  p->phi_gdl = 0.4;
+  p->Da_gdl = 1e-3;
+  p->deff_ratio_gdl = 0.0;
+  p->dp_lat = 0.0;
+  p->gdl_thickness_cm = 0.0254;
+  p->dx_cm = 0.0;
+  p->D_O2_cm2s = 5.2197e-2;
+  p->aj0_ref = 1.0e-4;
+  p->C_ref = 17.808e-6;
+  p->alpha_c = 1.0;
+  p->faraday = 96487.0;
+  p->R_gas = 8.314;
+  p->E_over_R = 16456.0;
+  p->T_arrh = 353.15;
+  p->U0_slope = 0.0025;
+  p->U0_icept = 0.2329;
+  p->k_f = 0.026;
+  p->k_s = 1.5;
+  p->rhocp_f = 1.0e-3;
+  p->rhocp_s = 1.6;
+}
+
+size_t lbm_workspace_bytes(const lbm_geometry* g) {
+  if (!geometry_ok(g)) return 0;
+  return make_layout(g).total;
+}
+
+lbm_status lbm_create(const lbm_geometry* g, void* dev_ws, size_t ws_bytes, void* hip_stream, lbm_ctx** out) {
+  if (!out) return LBM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!geometry_ok(g) || !dev_ws) return LBM_ERR_INVALID_ARG;
+  const Layout L = make_layout(g);
+  if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0) return LBM_ERR_INVALID_ARG;
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ERR_INVALID_ARG;
+  c->g = *g;
+  c->L = L;
+  c->ws = static_cast<char*>(dev_ws);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  hipGetDevice(&c->device);
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_params(lbm_ctx* c, const lbm_params* p, const void* phi, const void* inv_k, const void* d_eff) {
+  if (!c || !p) return LBM_ERR_INVALID_ARG;
+  c->params_set = false;
+  return c->g.precision == 64 ? set_params_t<double>(c, p, phi, inv_k, d_eff)
+                              : set_params_t<float>(c, p, phi, inv_k, d_eff);
+}
+
+lbm_status lbm_init_equilibrium(lbm_ctx* c) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  c->cur = 0;
+  c->step = 0;
+  if (c->g.precision == 64) launch_init<double>(c); else launch_init<float>(c);
+  return check_launch(c, "init");
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c || n < 0) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  if (c->g.precision == 64) launch_step<double>(c, n); else launch_step<float>(c, n);
+  c->step += n;
+  return check_launch(c, "step");
+}
+
+lbm_status lbm_observables(lbm_ctx* c, lbm_obs* out, double* pi, double* pc, double* pT) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  return c->g.precision == 64 ? observables_t<double>(c, out, pi, pc, pT) : observables_t<float>(c, out, pi, pc, pT);
+}
+
+lbm_status lbm_get_fields(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* cc) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  if (c->g.precision == 64) launch_fields<double>(c, ux, uy, p, T, cc); else launch_fields<float>(c, ux, uy, p, T, cc);
+  return check_launch(c, "fields");
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, void* dst) {
+  if (!c || !dst) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  if (c->g.precision == 64)
+    hipLaunchKernelGGL(k_export<double>, grid, dim3(kBlock), 0, c->stream,
+                       static_cast<const double*>(c->state(c->cur)), static_cast<double*>(dst), c->kd);
+  else
+    hipLaunchKernelGGL(k_export<float>, grid, dim3(kBlock), 0, c->stream,
+                       static_cast<const float*>(c->state(c->cur)), static_cast<float*>(dst), c->kf);
+  return check_launch(c, "get_populations");
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const void* src, int64_t step) {
+  if (!c || !src) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  if (c->g.precision == 64)
+    hipLaunchKernelGGL(k_import<double>, grid, dim3(kBlock), 0, c->stream, static_cast<const double*>(src),
+                       static_cast<double*>(c->state(c->cur)), c->kd);
+  else
+    hipLaunchKernelGGL(k_import<float>, grid, dim3(kBlock), 0, c->stream, static_cast<const float*>(src),
+                       static_cast<float*>(c->state(c->cur)), c->kf);
+  c->step = step;
+  return check_launch(c, "set_populations");
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c) {
+  if (!c) return 0;
+  return size_t(19) * c->L.plane * c->L.esize;
+}
+
+lbm_status lbm_save_state(lbm_ctx* c, void* dst, int64_t* step_out) {
+  if (!c || !dst) return LBM_ERR_INVALID_ARG;
+  if (hipMemcpyAsync(dst, c->state(c->cur), lbm_state_bytes(c), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, LBM_ERR_DEVICE, "save_state copy failed");
+  if (step_out) *step_out = c->step;
+  return LBM_OK;
+}
+
+lbm_status lbm_load_state(lbm_ctx* c, const void* src, int64_t step) {
+  if (!c || !src) return LBM_ERR_INVALID_ARG;
+  if (hipMemcpyAsync(c->state(c->cur), src, lbm_state_bytes(c), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, LBM_ERR_DEVICE, "load_state copy failed");
+  c->step = step;
+  return LBM_OK;
+}
+
+int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->step : -1; }
+
+lbm_status lbm_synchronize(lbm_ctx* c) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, std::string("synchronize: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+const char* lbm_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_INVALID_ARG: return "invalid argument";
+    case LBM_ERR_UNSTABLE_PARAMS: return "parameters outside the stable range";
+    case LBM_ERR_DEVICE: return "device error";
+    case LBM_ERR_NONFINITE: return "non-finite result";
+    case LBM_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+// Kernels of the single-lattice 2D solver.  One thread owns one lattice node.
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+constexpr int kBlock = 256;     // 4 wavefronts of 64 lanes along x
+constexpr int kObsQ = 8;        // per-block observable partials
+
+// Map a 2D launch (blocks along x, rows along y) so that the eight XCDs
+// (which receive consecutive workgroups round-robin) each get a contiguous
+// band of rows: spatial neighbours then share an L2.
+__device__ __forceinline__ void xcd_tile(int nbx, int nby, int& bx, int& by) {
+  const int flat = blockIdx.y * nbx + blockIdx.x;
+  const int total = nbx * nby;
+  // XCD j receives flats j, j+8, ...: full + (j < rem) workgroups.  Give it
+  // the contiguous logical range starting at j*full + min(j, rem).
+  const int xcd = flat & 7;
+  const int slot = flat >> 3;
+  const int full = total >> 3, rem = total & 7;
+  const int logical = xcd * full + (xcd < rem ? xcd : rem) + slot;
+  by = logical / nbx;
+  bx = logical - by * nbx;
+}
+
+// One time step: pull-stream, boundary columns, macros, flow collision,
+// reaction, scalar collisions, store.
+template <typename R, int MAT>
+__global__ __launch_bounds__(kBlock) void k_step(const R* __restrict__ src, R* __restrict__ dst,
+                                                 const R* __restrict__ phi_f,
+                                                 const R* __restrict__ invk_f,
+                                                 const R* __restrict__ d_f, Consts<R> k) {
+  int bx, by;
+  xcd_tile(gridDim.x, gridDim.y, bx, by);
+  const int x = bx * kBlock + threadIdx.x;
+  const int y = by;
+  if (x >= k.nx) return;
+  R f[19];
+  const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);
+  const bool cl = y >= k.y_cl0 && !(k.flags & F_NO_REACTION);
+  collide(f, mt, k, cl);
+  const int o = y * k.pitch + x;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
+}
+
+// Equilibrium initial state: rest fluid at zero pressure (shifted f = 0),
+// theta = 0, O2 at c_in.
+template <typename R, int MAT>
+__global__ __launch_bounds__(kBlock) void k_init(R* __restrict__ dst, const R* __restrict__ phi_f,
+                                                 const R* __restrict__ invk_f,
+                                                 const R* __restrict__ d_f, Consts<R> k) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= k.nx) return;
+  const Mat<R> mt = material<R, MAT>(k, phi_f, invk_f, d_f, x, y);
+  R g[5] = {R(0), R(0), R(0), R(0), R(0)};
+  add_geq(k.c_in, R(0), R(0), mt.bC, R(1), g);
+  const int o = y * k.pitch + x;
+#pragma unroll
+  for (int q = 0; q < 14; ++q) dst[q * k.plane + o] = R(0);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) dst[(14 + q) * k.plane + o] = g[q];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+// Observable partial sums over the pre-collision state, one row of partials
+// per workgroup: sum f (shifted), sum theta, sum c, sum s_c, sum S_T,
+// sum s_c (eta + T dU0/dT), max theta, count of non-finite values.
+template <typename R, int MAT>
+__global__ __launch_bounds__(kBlock) void k_obs_cells(const R* __restrict__ src,
+                                                      const R* __restrict__ phi_f,
+                                                      const R* __restrict__ invk_f,
+                                                      const R* __restrict__ d_f, Consts<R> k,
+                                                      double* __restrict__ partial) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  double v[kObsQ] = {0, 0, 0, 0, 0, 0, -1e300, 0};
+  if (x < k.nx) {
+    R f[19];
+    const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);
+    double sf = 0, th = 0, c = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sf += double(f[q]);
+#pragma unroll
+    for (int q = 9; q < 14; ++q) th += double(f[q]);
+#pragma unroll
+    for (int q = 14; q < 19; ++q) c += double(f[q]);
+    v[0] = sf;
+    v[1] = th;
+    v[2] = c;
+    if (y >= k.y_cl0 && !(k.flags & F_NO_REACTION)) {
+      const React<R> r = reaction(R(th), R(c), mt.rhocp, k);
+      v[3] = double(r.s_c);
+      v[4] = double(r.S_T);
+      v[5] = double(r.s_c) * double(r.ehs);
+    }
+    v[6] = th;
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) bad |= !isfinite(f[q]);
+    v[7] = bad ? 1.0 : 0.0;
+  }
+  __shared__ double red[kObsQ][kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kObsQ; ++i) {
+    const double s = i == 6 ? wave_max(v[i]) : wave_sum(v[i]);
+    if (lane == 0) red[i][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kObsQ) {
+    const int i = threadIdx.x;
+    double s = red[i][0];
+    for (int w = 1; w < kBlock / 64; ++w) s = i == 6 ? fmax(s, red[i][w]) : s + red[i][w];
+    partial[(size_t)(blockIdx.y * gridDim.x + blockIdx.x) * kObsQ + i] = s;
+  }
+}
+
+// Sum the per-workgroup partials in a fixed order.
+__global__ void k_obs_final(const double* __restrict__ partial, int nblocks, double* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i >= kObsQ) return;
+  double s = i == 6 ? -1e300 : 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const double v = partial[(size_t)b * kObsQ + i];
+    s = i == 6 ? fmax(s, v) : s + v;
+  }
+  out[i] = s;
+}
+
+// Per-column CL profiles: i(x) = sum over CL rows of 4 F C_ref s_c / dt * dx,
+// and c, T on the CL row next to the GDL.
+template <typename R, int MAT>
+__global__ __launch_bounds__(kBlock) void k_obs_profiles(const R* __restrict__ src,
+                                                         const R* __restrict__ phi_f,
+                                                         const R* __restrict__ invk_f,
+                                                         const R* __restrict__ d_f, Consts<R> k,
+                                                         double i_scale, double* __restrict__ prof) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  if (x >= k.nx) return;
+  double isum = 0, c0 = 0, t0 = 0;
+  const bool react = !(k.flags & F_NO_REACTION);
+  for (int y = k.y_cl0; y < k.ny; ++y) {
+    R f[19];
+    const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);
+    const R th = f[9] + f[10] + f[11] + f[12] + f[13];
+    const R c = f[14] + f[15] + f[16] + f[17] + f[18];
+    if (react) isum += double(reaction(th, c, mt.rhocp, k).s_c);
+    if (y == k.y_cl0) {
+      c0 = double(c);
+      t0 = double(k.T_in) + double(th);
+    }
+  }
+  prof[x] = isum * i_scale;
+  prof[k.nx + x] = c0;
+  prof[2 * k.nx + x] = t0;
+}
+
+// Macroscopic fields of the pre-collision state into dense [ny][nx] arrays.
+template <typename R, int MAT>
+__global__ __launch_bounds__(kBlock) void k_fields(const R* __restrict__ src,
+                                                   const R* __restrict__ phi_f,
+                                                   const R* __restrict__ invk_f,
+                                                   const R* __restrict__ d_f, Consts<R> k,
+                                                   R* ux, R* uy, R* p, R* T, R* c) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= k.nx) return;
+  R f[19];
+  const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);
+  const Macro<R> a = flow_macros(f, mt, k);
+  const int o = y * k.nx + x;
+  if (ux) ux[o] = a.ux;
+  if (uy) uy[o] = a.uy;
+  if (p) p[o] = a.p;
+  if (T) T[o] = k.T_in + (f[9] + f[10] + f[11] + f[12] + f[13]);
+  if (c) c[o] = f[14] + f[15] + f[16] + f[17] + f[18];
+}
+
+// Internal (pitched, shifted rest population) <-> canonical dense populations.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_export(const R* __restrict__ src, R* __restrict__ dst,
+                                                   Consts<R> k) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= k.nx) return;
+  const size_t dense = (size_t)k.nx * k.ny;
+  for (int q = 0; q < 19; ++q) {
+    R v = src[q * k.plane + y * k.pitch + x];
+    if (q == 0) v += R(1);
+    dst[q * dense + (size_t)y * k.nx + x] = v;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_import(const R* __restrict__ src, R* __restrict__ dst,
+                                                   Consts<R> k) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= k.nx) return;
+  const size_t dense = (size_t)k.nx * k.ny;
+  for (int q = 0; q < 19; ++q) {
+    R v = src[q * dense + (size_t)y * k.nx + x];
+    if (q == 0) v -= R(1);
+    dst[q * k.plane + y * k.pitch + x] = v;
+  }
+}
+
+// Full-field mode: fill the fields not given by the caller from porosity
+// (Kozeny-Carman, Bruggeman / ratio) or from the layered inputs.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_derive_fields(R* __restrict__ phi, R* __restrict__ invk,
+                                                          R* __restrict__ d, Consts<R> k, int have_phi,
+                                                          int have_invk, int have_d) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= k.nx) return;
+  const int o = y * k.pitch + x;
+  const bool porous = y >= k.ny_ch;
+  if (!have_phi) phi[o] = porous ? k.phi_gdl : R(1);
+  const R ph = phi[o];
+  if (!have_invk) {
+    if (k.kc_inv > R(0)) {
+      const R om = R(1) - ph;
+      invk[o] = om * om * k.kc_inv / (ph * ph * ph);
+    } else {
+      invk[o] = porous ? k.invk_gdl : R(0);
+    }
+  }
+  if (!have_d) d[o] = (porous && k.deff_ratio > R(0)) ? k.deff_ratio * k.D_f : ph * sqrt(ph) * k.D_f;
+}
+
+// Copy a dense [ny][nx] caller array into a pitched workspace plane.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pitch_copy(const R* __restrict__ src, R* __restrict__ dst,
+                                                       int nx, int pitch) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= nx) return;
+  dst[y * pitch + x] = src[(size_t)y * nx + x];
+}
+
+}  // namespace lbm

@@ -1,0 +1,246 @@
+"""Thin ctypes binding of ``liblbmpem.so`` (C ABI in ``include/lbm_pem.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP
+kernels of the library.  PyTorch provides device memory (the workspace and
+per-cell arrays are CUDA tensors) and the stream.  There is no CPU fallback:
+if the library is not built, or no GPU is present, constructing a solver
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbmpem.so")
+
+LBM_PERIODIC_X = 1
+LBM_PERIODIC_Y = 2
+LBM_BODY_FORCE = 4
+LBM_NO_REACTION = 8
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "parameters outside the stable range", 3: "device error",
+          4: "non-finite result", 5: "call out of order"}
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("ny_channel", ctypes.c_int32),
+                ("ny_gdl", ctypes.c_int32), ("ny_cl", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+_PARAM_NAMES = ["tau_f", "D_f_lat", "Re", "T_in_K", "c_in", "V_op", "phi_gdl", "Da_gdl", "deff_ratio_gdl",
+                "dp_lat", "gdl_thickness_cm", "dx_cm", "D_O2_cm2s", "aj0_ref", "C_ref", "alpha_c", "faraday",
+                "R_gas", "E_over_R", "T_arrh", "U0_slope", "U0_icept", "k_f", "k_s", "rhocp_f", "rhocp_s",
+                "body_force_x", "body_force_y"]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in _PARAM_NAMES] + [
+        ("independent_fields", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64)] + [(n, ctypes.c_double) for n in (
+        "current_density", "power_density", "heat_rate", "o2_utilisation", "T_max", "sum_f", "sum_theta",
+        "sum_c", "consumed_c", "heat_added")]
+
+
+_lib = None
+
+EXPORTED = ["lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_set_params", "lbm_init_equilibrium",
+            "lbm_step", "lbm_observables", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations",
+            "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count", "lbm_synchronize",
+            "lbm_destroy", "lbm_status_string", "lbm_last_error"]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2103_01444_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64
+    P = ctypes.POINTER
+    sig = {
+        "lbm_default_params": (None, [P(Params)]),
+        "lbm_workspace_bytes": (sz, [P(Geometry)]),
+        "lbm_create": (ctypes.c_int, [P(Geometry), vp, sz, vp, P(vp)]),
+        "lbm_set_params": (ctypes.c_int, [vp, P(Params), vp, vp, vp]),
+        "lbm_init_equilibrium": (ctypes.c_int, [vp]),
+        "lbm_step": (ctypes.c_int, [vp, i64]),
+        "lbm_observables": (ctypes.c_int, [vp, P(Obs), vp, vp, vp]),
+        "lbm_get_fields": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+        "lbm_get_populations": (ctypes.c_int, [vp, vp]),
+        "lbm_set_populations": (ctypes.c_int, [vp, vp, i64]),
+        "lbm_state_bytes": (sz, [vp]),
+        "lbm_save_state": (ctypes.c_int, [vp, vp, P(i64)]),
+        "lbm_load_state": (ctypes.c_int, [vp, vp, i64]),
+        "lbm_step_count": (i64, [vp]),
+        "lbm_synchronize": (ctypes.c_int, [vp]),
+        "lbm_destroy": (None, [vp]),
+        "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "lbm_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class LbmError(RuntimeError):
+    pass
+
+
+def default_params() -> Params:
+    p = Params()
+    load_library().lbm_default_params(ctypes.byref(p))
+    return p
+
+
+def params_from_workload(w: dict, **over) -> Params:
+    """lbm_params for a workload dictionary (see ``workloads``)."""
+    p = default_params()
+    keymap = {"T_in": "T_in_K"}
+    for k in ("tau_f", "D_f_lat", "Re", "T_in", "c_in", "V_op", "phi_gdl", "Da_gdl", "deff_ratio_gdl"):
+        if k in w:
+            setattr(p, keymap.get(k, k), float(w[k]))
+    if w.get("dp_over_hgdl", 0.0) > 0:
+        p.dp_lat = float(w["dp_over_hgdl"] * w["ny_gdl"])
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Cathode:
+    """One 2D cathode lattice on the current GPU.
+
+    ``phi``, ``inv_k``, ``d_eff``: optional per-cell [ny, nx] tensors (any
+    device; copied to the GPU in the context precision).
+    """
+
+    def __init__(self, nx, ny, ny_channel, ny_gdl, ny_cl, params: Params, precision=32, flags=0,
+                 phi=None, inv_k=None, d_eff=None, device=None):
+        if not torch.cuda.is_available():
+            raise LbmError("no GPU: the solver runs only on the HIP device")
+        self.lib = load_library()
+        self.device = torch.device(device or "cuda")
+        self.dtype = torch.float64 if precision == 64 else torch.float32
+        self.geom = Geometry(nx, ny, ny_channel, ny_gdl, ny_cl, precision, flags)
+        self.nx, self.ny = nx, ny
+        nbytes = self.lib.lbm_workspace_bytes(ctypes.byref(self.geom))
+        if nbytes == 0:
+            raise LbmError("invalid geometry")
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = ctypes.c_void_p()
+        self._check(self.lib.lbm_create(ctypes.byref(self.geom), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx)))
+        self.params = params
+        self.set_params(params, phi, inv_k, d_eff)
+        self.init_equilibrium()
+
+    @classmethod
+    def from_workload(cls, w: dict, phi=None, inv_k=None, d_eff=None, flags=0, **over):
+        return cls(w["nx"], w["ny"], w["ny_channel"], w["ny_gdl"], w["ny_cl"], params_from_workload(w, **over),
+                   precision=w.get("precision", 32), flags=flags, phi=phi, inv_k=inv_k, d_eff=d_eff)
+
+    # ------------------------------------------------------------------ util
+    def _check(self, st):
+        if st != 0:
+            msg = ""
+            if self.ctx:
+                msg = self.lib.lbm_last_error(self.ctx).decode()
+            raise LbmError(f"{STATUS.get(st, st)}: {msg}")
+
+    def _dev(self, a):
+        if a is None:
+            return None
+        t = torch.as_tensor(a).to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(t.shape) != (self.ny, self.nx):
+            raise ValueError(f"per-cell array must be [{self.ny}, {self.nx}]")
+        return t
+
+    # --------------------------------------------------------------- the ABI
+    def set_params(self, params: Params, phi=None, inv_k=None, d_eff=None):
+        arrs = [self._dev(a) for a in (phi, inv_k, d_eff)]
+        self._check(self.lib.lbm_set_params(self.ctx, ctypes.byref(params), *[_ptr(a) for a in arrs]))
+        self.params = params
+
+    def init_equilibrium(self):
+        self._check(self.lib.lbm_init_equilibrium(self.ctx))
+
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm_step(self.ctx, int(n)))
+
+    @property
+    def step_count(self) -> int:
+        return int(self.lib.lbm_step_count(self.ctx))
+
+    def synchronize(self):
+        self._check(self.lib.lbm_synchronize(self.ctx))
+
+    def observables(self) -> dict:
+        o = Obs()
+        pi = np.zeros(self.nx)
+        pc = np.zeros(self.nx)
+        pT = np.zeros(self.nx)
+        st = self.lib.lbm_observables(self.ctx, ctypes.byref(o), pi.ctypes.data_as(ctypes.c_void_p),
+                                      pc.ctypes.data_as(ctypes.c_void_p), pT.ctypes.data_as(ctypes.c_void_p))
+        self._check(st)
+        d = {name: getattr(o, name) for name, _ in Obs._fields_}
+        d.update(i_profile=pi, c_profile=pc, T_profile=pT)
+        return d
+
+    def fields(self) -> dict:
+        out = {k: torch.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
+               for k in ("ux", "uy", "p", "T", "c")}
+        self._check(self.lib.lbm_get_fields(self.ctx, *[_ptr(out[k]) for k in ("ux", "uy", "p", "T", "c")]))
+        return out
+
+    def populations(self) -> torch.Tensor:
+        out = torch.empty((19, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        self._check(self.lib.lbm_get_populations(self.ctx, _ptr(out)))
+        return out
+
+    def set_populations(self, pops, step: int = 0):
+        t = torch.as_tensor(pops).to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(t.shape) != (19, self.ny, self.nx):
+            raise ValueError("populations must be [19, ny, nx]")
+        self._check(self.lib.lbm_set_populations(self.ctx, _ptr(t), int(step)))
+        self.synchronize()  # t may be freed after return
+
+    def save_state(self):
+        n = self.lib.lbm_state_bytes(self.ctx)
+        buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+        step = ctypes.c_int64()
+        self._check(self.lib.lbm_save_state(self.ctx, _ptr(buf), ctypes.byref(step)))
+        return buf, step.value
+
+    def load_state(self, buf, step: int):
+        self._check(self.lib.lbm_load_state(self.ctx, _ptr(buf), int(step)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.lbm_synchronize(self.ctx)
+                self.lib.lbm_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass

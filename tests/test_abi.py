@@ -1,0 +1,84 @@
+"""The C-ABI library loads and exports every entry point its header
+declares; host-side argument checks.  CPU only (no kernel launches)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2103_01444_amd", "liblbmpem.so")
+
+
+def _declared():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("liblbmpem.so is not built (python -m paper_2103_01444_amd.build)")
+    from paper_2103_01444_amd import lbm
+    return lbm.load_library(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert len(declared) >= 18
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\b(lbm_[a-z0-9_]+)\b", out))
+    missing = declared - exported
+    assert not missing, missing
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+def test_binding_names_match_header():
+    from paper_2103_01444_amd import lbm
+    assert set(lbm.EXPORTED) <= _declared()
+
+
+def test_struct_layouts_match_header():
+    from paper_2103_01444_amd import lbm
+    # lbm_geometry: 7 x 4 bytes; lbm_params: 28 doubles + 2 int32; lbm_obs: int64 + 10 doubles.
+    assert ctypes.sizeof(lbm.Geometry) == 28
+    assert ctypes.sizeof(lbm.Params) == 28 * 8 + 8
+    assert ctypes.sizeof(lbm.Obs) == 8 + 10 * 8
+
+
+def test_defaults_are_the_paper_constants(lib):
+    from paper_2103_01444_amd import lbm
+    p = lbm.default_params()
+    assert (p.aj0_ref, p.C_ref, p.alpha_c, p.faraday, p.R_gas) == (1e-4, 17.808e-6, 1.0, 96487.0, 8.314)
+    assert (p.D_O2_cm2s, p.k_f, p.k_s, p.U0_slope, p.U0_icept) == (5.2197e-2, 0.026, 1.5, 0.0025, 0.2329)
+    assert (p.E_over_R, p.T_arrh) == (16456.0, 353.15)
+
+
+def test_workspace_size_and_geometry_checks(lib):
+    from paper_2103_01444_amd import lbm
+    g = lbm.Geometry(200, 40, 20, 18, 2, 64, 0)
+    n64 = lib.lbm_workspace_bytes(ctypes.byref(g))
+    # two states of 19 planes of 256 x 40 doubles (pitch padded to 64)
+    assert n64 >= 2 * 19 * 256 * 40 * 8
+    g32 = lbm.Geometry(200, 40, 20, 18, 2, 32, 0)
+    assert lib.lbm_workspace_bytes(ctypes.byref(g32)) < n64
+    for bad in (lbm.Geometry(2, 40, 20, 18, 2, 64, 0),      # nx < 3
+                lbm.Geometry(200, 40, 20, 18, 3, 64, 0),    # layers do not sum to ny
+                lbm.Geometry(200, 40, 20, 18, 2, 16, 0),    # precision
+                lbm.Geometry(200, 40, 20, 18, 2, 32, 64),   # unknown flag
+                lbm.Geometry(1 << 16, 1 << 12, 1 << 11, 1 << 11, 0, 32, 0)):  # 32-bit offsets
+        assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(lbm.Geometry(2, 40, 20, 18, 2, 64, 0)), ctypes.c_void_p(256), 1 << 30,
+                          None, ctypes.byref(ctx)) == 1
+    assert lib.lbm_create(ctypes.byref(g), None, 1 << 30, None, ctypes.byref(ctx)) == 1
+    assert lib.lbm_create(ctypes.byref(g), ctypes.c_void_p(256), 16, None, ctypes.byref(ctx)) == 1
+    assert lib.lbm_status_string(2) == b"parameters outside the stable range"

@@ -1,0 +1,287 @@
+"""GPU (HIP, through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances: FP64 kernels 1e-12 relative on fields and observables; FP32
+kernels 1e-4 relative on velocity, temperature rise and O2 (the accuracy
+the solver is specified to).  Inputs are seeded and synthetic (``workloads``).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import lbm2d as L
+
+pytestmark = pytest.mark.gpu
+
+DT = torch.float64
+
+
+def _gpu_mod():
+    from paper_2103_01444_amd import lbm
+    return lbm
+
+
+def rel(a, b):
+    a = torch.as_tensor(a, dtype=DT).cpu()
+    b = torch.as_tensor(b, dtype=DT).cpu()
+    scale = float(b.abs().max())
+    return float((a - b).abs().max()) / (scale if scale > 0 else 1.0)
+
+
+def oracle_for(w, phi=None, inv_k=None, d_eff=None, geom=None, **over):
+    g = geom or L.geometry_from_workload(w)
+    p = L.Params.from_workload(w)
+    for k, v in over.items():
+        setattr(p, k, v)
+    t = lambda a: None if a is None else torch.as_tensor(a, dtype=DT)
+    return L.Model(g, p, phi=t(phi), inv_k=t(inv_k), d_eff=t(d_eff))
+
+
+def _flags(px=False, py=False, body=False, noreact=False):
+    lbm = _gpu_mod()
+    return ((lbm.LBM_PERIODIC_X if px else 0) | (lbm.LBM_PERIODIC_Y if py else 0)
+            | (lbm.LBM_BODY_FORCE if body else 0) | (lbm.LBM_NO_REACTION if noreact else 0))
+
+
+def compare_fields(fg, fo, tol, label=""):
+    u_scale = max(float(fo["ux"].abs().max()), float(fo["uy"].abs().max()))
+    eu = max(float((fg["ux"].double().cpu() - fo["ux"]).abs().max()),
+             float((fg["uy"].double().cpu() - fo["uy"]).abs().max())) / u_scale
+    theta_g = fg["T"].double().cpu() - float(fo["T"].flatten()[0] - fo["theta"].flatten()[0])
+    eth = rel(theta_g, fo["theta"]) if float(fo["theta"].abs().max()) > 0 else float(theta_g.abs().max())
+    eT = rel(fg["T"], fo["T"])
+    ec = rel(fg["c"], fo["c"])
+    print(f"{label} rel err: u {eu:.2e} theta {eth:.2e} T {eT:.2e} c {ec:.2e}", flush=True)
+    assert eu < tol and eth < tol and eT < tol and ec < tol, (eu, eth, eT, ec)
+    return eu, eth, eT, ec
+
+
+# ---------------------------------------------------------------- FP64 parity
+def test_fp64_cathode_200x40_full_run():
+    """The 200x40 FP64 cathode (Re 10, 353 K, 0.6 V) over its 2000 steps."""
+    lbm = _gpu_mod()
+    w = W.cathode2d_200x40()
+    gpu = lbm.Cathode.from_workload(w)
+    m = oracle_for(w)
+    s = m.initial_state()
+    for chunk in (500, 500, 1000):
+        gpu.step(chunk)
+        s = m.run(s, chunk)
+        fg = gpu.fields()
+        fo = m.fields(s)
+        compare_fields(fg, fo, 1e-12, f"200x40 fp64 step {gpu.step_count}")
+        assert rel(fg["p"], fo["p"]) < 1e-11
+    og, oo = gpu.observables(), m.observables(s)
+    for key in ("current_density", "power_density", "heat_rate", "o2_utilisation", "T_max", "sum_f", "sum_theta",
+                "sum_c", "consumed_c", "heat_added"):
+        e = abs(og[key] - float(oo[key])) / abs(float(oo[key]))
+        print(f"obs {key}: gpu {og[key]:.12e} oracle {float(oo[key]):.12e} rel {e:.1e}", flush=True)
+        assert e < 1e-12, key
+    for key in ("i_profile", "c_profile", "T_profile"):
+        assert rel(og[key], oo[key]) < 1e-12, key
+
+
+MODES = ["layered", "phi", "full"]
+
+
+def _random_case(nx, ny, layers, mode, precision, seed, flags=0, **over):
+    lbm = _gpu_mod()
+    w = W.cathode2d_200x40()
+    w.update(nx=nx, ny=ny, ny_channel=layers[0], ny_gdl=layers[1], ny_cl=layers[2], precision=precision)
+    w.update(over)
+    rng = np.random.default_rng(seed)
+    phi = inv_k = d_eff = None
+    if mode in ("phi", "full"):
+        phi = np.ones((ny, nx))
+        phi[layers[0]:] = rng.uniform(0.4, 0.8, size=(ny - layers[0], nx))
+        w["dp_over_hgdl"] = 0.3325
+    if mode == "full":
+        inv_k = np.zeros((ny, nx))
+        inv_k[layers[0]:] = rng.uniform(0.0, 2.0, size=(ny - layers[0], nx))
+        d_eff = rng.uniform(0.001, 0.02, size=(ny, nx))
+    if precision == 32:  # both sides see the same rounded inputs
+        rnd = lambda a: None if a is None else a.astype(np.float32).astype(np.float64)
+        phi, inv_k, d_eff = rnd(phi), rnd(inv_k), rnd(d_eff)
+    pops = W.random_populations(ny, nx, seed + 1)
+    if precision == 32:
+        pops = pops.astype(np.float32).astype(np.float64)
+    gpu = lbm.Cathode.from_workload(w, phi=phi, inv_k=inv_k, d_eff=d_eff, flags=flags,
+                                    body_force_x=over.get("bfx", 0.0), body_force_y=over.get("bfy", 0.0))
+    geom = L.Geometry(nx, ny, *layers, periodic_x=bool(flags & 1), periodic_y=bool(flags & 2))
+    m = oracle_for(w, phi, inv_k, d_eff, geom=geom, body_force=(over.get("bfx", 0.0), over.get("bfy", 0.0)),
+                   reaction=not (flags & 8))
+    return gpu, m, torch.from_numpy(pops)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("shape", [(203, 37, (18, 15, 4)), (64, 16, (8, 7, 1)), (300, 9, (3, 3, 3))])
+def test_one_step_from_arbitrary_state(mode, precision, shape):
+    """One update of an arbitrary population state, every population of
+    every node, ragged tiles included."""
+    nx, ny, layers = shape
+    gpu, m, pops = _random_case(nx, ny, layers, mode, precision, seed=100 + nx)
+    gpu.set_populations(pops)
+    fg = gpu.fields()
+    fo = m.fields(pops)
+    tol = 1e-12 if precision == 64 else 1e-4
+    compare_fields(fg, fo, tol, f"fields {mode} fp{precision} {nx}x{ny}")
+    gpu.step(1)
+    out = gpu.populations().double().cpu()
+    ref = m.step(pops)
+    err = float((out - ref).abs().max())
+    print(f"one step {mode} fp{precision} {nx}x{ny}: max |df| = {err:.2e}", flush=True)
+    assert err < (1e-13 if precision == 64 else 2e-6)
+
+
+@pytest.mark.parametrize("flags", [(True, False, True, True), (True, True, True, False), (False, True, False, False)])
+def test_one_step_periodic_and_body_force_modes(flags):
+    px, py, body, noreact = flags
+    f = _flags(px, py, body, noreact)
+    gpu, m, pops = _random_case(50, 12, (6, 5, 1), "layered", 64, seed=7, flags=f,
+                                bfx=2e-5 if body else 0.0, bfy=-1e-5 if body else 0.0)
+    gpu.set_populations(pops)
+    gpu.step(1)
+    err = float((gpu.populations().double().cpu() - m.step(pops)).abs().max())
+    assert err < 1e-13, err
+
+
+def test_poiseuille_on_gpu_matches_closed_form():
+    """Independent of the oracle: the FP64 kernel reproduces the exact
+    half-way bounce-back Poiseuille profile (Section 2.1 rates)."""
+    lbm = _gpu_mod()
+    H, a = 8, 1e-7
+    p = lbm.default_params()
+    p.tau_f, p.body_force_x, p.dx_cm, p.Re = 0.8, a, 1e-3, 0.0
+    gpu = lbm.Cathode(4, H, H, 0, 0, p, precision=64, flags=_flags(px=True, body=True, noreact=True))
+    gpu.step(2500)
+    u = gpu.fields()["ux"][:, 0].double().cpu()
+    nu = (0.8 - 0.5) / 3
+    y = torch.arange(H, dtype=DT)
+    exact = a / (2 * nu) * (y + 0.5) * (H - 0.5 - y)
+    assert rel(u, exact) < 1e-11
+
+
+# ---------------------------------------------------------------- FP32 parity
+def test_fp32_porosity_field_run_256x64():
+    """The 4096x1024 recipe scaled to 256x64 (per-cell porosity,
+    Kozeny-Carman), FP32, 600 steps."""
+    lbm = _gpu_mod()
+    w = W.cathode2d_scaled(256, 64, precision=32, phi_seed=5)
+    phi = W.porosity_field(w)
+    phi32 = phi.astype(np.float32).astype(np.float64)
+    gpu = lbm.Cathode.from_workload(w, phi=phi32)
+    m = oracle_for(w, phi=phi32)
+    gpu.step(600)
+    s = m.run(m.initial_state(), 600)
+    compare_fields(gpu.fields(), m.fields(s), 1e-4, "256x64 fp32")
+    og, oo = gpu.observables(), m.observables(s)
+    assert abs(og["current_density"] / float(oo["current_density"]) - 1) < 1e-4
+
+
+# ------------------------------------------------ full size, bench launch shape
+def _full_size_case():
+    w = W.cathode2d_4096x1024()
+    phi = W.porosity_field(w).astype(np.float32).astype(np.float64)
+    return w, phi
+
+
+def test_full_size_one_step_from_arbitrary_state():
+    """4096x1024 FP32, porosity field: one update of an arbitrary state over
+    the whole lattice (the kernel and launch shape the benchmark times)."""
+    lbm = _gpu_mod()
+    w, phi = _full_size_case()
+    pops = W.random_populations(w["ny"], w["nx"], 4242).astype(np.float32).astype(np.float64)
+    gpu = lbm.Cathode.from_workload(w, phi=phi)
+    gpu.set_populations(torch.from_numpy(pops))
+    gpu.step(1)
+    out = gpu.populations().double().cpu()
+    m = oracle_for(w, phi=phi)
+    ref = m.step(torch.from_numpy(pops))
+    err = float((out - ref).abs().max())
+    print(f"full size one step: max |df| = {err:.2e}", flush=True)
+    assert err < 2e-6
+
+
+def _window_oracle(w, phi, x0, x1, n):
+    """Oracle run of n steps on the columns [x0 - h, x1 + h) of the full
+    lattice (all rows), h = 2n + 2: every node of [x0, x1) then depends only
+    on data inside the window, so its values equal those of the full run."""
+    h = 2 * n + 2
+    xa, xb = max(0, x0 - h), min(w["nx"], x1 + h)
+    ww = dict(w)
+    ww["nx"] = xb - xa
+    m0 = oracle_for(w, phi=phi)  # full-lattice scales (dx, dt) reused below
+    g = L.Geometry(xb - xa, w["ny"], w["ny_channel"], w["ny_gdl"], w["ny_cl"])
+    m = oracle_for(ww, phi=phi[:, xa:xb], geom=g, dx_cm=m0.dx)
+    s = m.run(m.initial_state(), n)
+    f = m.fields(s)
+    return {k: v[:, x0 - xa:x1 - xa] for k, v in f.items()}
+
+
+def test_full_size_multistep_windows():
+    """4096x1024 FP32 from the initial state for 40 steps; inlet, interior
+    and outlet windows of 24 columns checked against light-cone oracle runs."""
+    lbm = _gpu_mod()
+    w, phi = _full_size_case()
+    n = 40
+    gpu = lbm.Cathode.from_workload(w, phi=phi)
+    gpu.step(n)
+    fg = {k: v.double().cpu() for k, v in gpu.fields().items()}
+    for x0 in (0, 2000, w["nx"] - 24):
+        fo = _window_oracle(w, phi, x0, x0 + 24, n)
+        sub = {k: v[:, x0:x0 + 24] for k, v in fg.items()}
+        for key in ("ux", "uy", "c", "T"):
+            scale = max(float(fo[key].abs().max()), 1e-12)
+            err = float((sub[key] - fo[key]).abs().max()) / scale
+            print(f"window x0={x0} {key}: rel {err:.2e}", flush=True)
+            assert err < 1e-4, (x0, key, err)
+        th = fo["T"] - w["T_in"]
+        if float(th.abs().max()) > 0:
+            err = float(((sub["T"] - w["T_in"]) - th).abs().max()) / float(th.abs().max())
+            assert err < 1e-3, (x0, err)
+
+
+# ------------------------------------------------------------ state handling
+def test_determinism_save_load_and_population_roundtrip():
+    lbm = _gpu_mod()
+    w = W.cathode2d_scaled(300, 40, precision=32, phi_seed=9)
+    phi = W.porosity_field(w)
+    a = lbm.Cathode.from_workload(w, phi=phi)
+    b = lbm.Cathode.from_workload(w, phi=phi)
+    a.step(300)
+    b.step(150)
+    buf, st = b.save_state()
+    b.step(77)  # diverge, then restore
+    b.load_state(buf, st)
+    b.step(150)
+    assert torch.equal(a.populations(), b.populations())
+    pops = a.populations()
+    a.set_populations(pops, step=a.step_count)
+    assert torch.equal(a.populations(), pops)
+
+
+def test_nonfinite_state_is_reported():
+    lbm = _gpu_mod()
+    w = W.cathode2d_200x40()
+    w.update(nx=40, ny=20, ny_channel=10, ny_gdl=9, ny_cl=1)
+    gpu = lbm.Cathode.from_workload(w)
+    pops = gpu.populations()
+    pops[3, 5, 7] = float("nan")
+    gpu.set_populations(pops)
+    with pytest.raises(lbm.LbmError, match="non-finite"):
+        gpu.observables()
+
+
+def test_parameter_validation():
+    lbm = _gpu_mod()
+    w = W.cathode2d_200x40()
+    for over in (dict(tau_f=0.5), dict(D_f_lat=0.2), dict(Re=200.0), dict(phi_gdl=1.5)):
+        with pytest.raises(lbm.LbmError, match="stable range"):
+            lbm.Cathode.from_workload(w, **over)
+    phi = np.ones((40, 200))
+    phi[30, 30] = 0.0
+    with pytest.raises(lbm.LbmError, match="stable range"):
+        lbm.Cathode.from_workload(dict(w, dp_over_hgdl=0.3), phi=phi)
