@@ -177,8 +177,9 @@ lbm_status lbm_observables(lbm_ctx* ctx, lbm_obs* out, double* prof_i, double* p
 
 /* Macroscopic fields of the current state into caller device arrays
  * [ny][nx] (context precision): u_x, u_y (lattice), p (lattice, Section 2.1
- * pressure relation), T (K), c (relative).  NULL skips a field.  Async. */
-lbm_status lbm_get_fields(lbm_ctx* ctx, void* ux, void* uy, void* p, void* T, void* c);
+ * pressure relation), T (K), theta = T - T_in (K, the stored variable, at
+ * full relative precision), c (relative).  NULL skips a field.  Async. */
+lbm_status lbm_get_fields(lbm_ctx* ctx, void* ux, void* uy, void* p, void* T, void* theta, void* c);
 
 /* Canonical post-collision populations, 19 dense planes (see Conventions),
  * context precision, device memory.  Async. */

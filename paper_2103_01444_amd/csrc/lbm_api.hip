@@ -250,7 +250,7 @@ void launch_obs_mat(lbm_ctx* c, double i_scale) {
   const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
   hipLaunchKernelGGL((k_obs_cells<R, MAT>), grid, dim3(kBlock), 0, c->stream, src, m.phi, m.invk, m.d,
                      consts<R>(c), c->partial());
-  hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, c->stream, c->partial(), c->L.nblocks_obs, c->out());
+  hipLaunchKernelGGL(k_obs_final, dim3(kObsQ), dim3(kBlock), 0, c->stream, c->partial(), c->L.nblocks_obs, c->out());
   const dim3 pgrid((c->g.nx + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_obs_profiles<R, MAT>), pgrid, dim3(kBlock), 0, c->stream, src, m.phi, m.invk, m.d,
                      consts<R>(c), i_scale, c->prof());
@@ -266,21 +266,21 @@ void launch_obs(lbm_ctx* c, double i_scale) {
 }
 
 template <typename R, int MAT>
-void launch_fields_mat(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* cc) {
+void launch_fields_mat(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* th, void* cc) {
   const MatPtrs<R> m = mat_ptrs<R>(c);
   const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
   hipLaunchKernelGGL((k_fields<R, MAT>), grid, dim3(kBlock), 0, c->stream,
                      static_cast<const R*>(c->state(c->cur)), m.phi, m.invk, m.d, consts<R>(c),
                      static_cast<R*>(ux), static_cast<R*>(uy), static_cast<R*>(p), static_cast<R*>(T),
-                     static_cast<R*>(cc));
+                     static_cast<R*>(th), static_cast<R*>(cc));
 }
 
 template <typename R>
-void launch_fields(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* cc) {
+void launch_fields(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* th, void* cc) {
   switch (c->mat) {
-    case MAT_LAYERED: launch_fields_mat<R, MAT_LAYERED>(c, ux, uy, p, T, cc); break;
-    case MAT_PHI: launch_fields_mat<R, MAT_PHI>(c, ux, uy, p, T, cc); break;
-    default: launch_fields_mat<R, MAT_FULL>(c, ux, uy, p, T, cc); break;
+    case MAT_LAYERED: launch_fields_mat<R, MAT_LAYERED>(c, ux, uy, p, T, th, cc); break;
+    case MAT_PHI: launch_fields_mat<R, MAT_PHI>(c, ux, uy, p, T, th, cc); break;
+    default: launch_fields_mat<R, MAT_FULL>(c, ux, uy, p, T, th, cc); break;
   }
 }
 
@@ -509,10 +509,11 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* out, double* pi, double* pc, dou
   return c->g.precision == 64 ? observables_t<double>(c, out, pi, pc, pT) : observables_t<float>(c, out, pi, pc, pT);
 }
 
-lbm_status lbm_get_fields(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* cc) {
+lbm_status lbm_get_fields(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* th, void* cc) {
   if (!c) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
-  if (c->g.precision == 64) launch_fields<double>(c, ux, uy, p, T, cc); else launch_fields<float>(c, ux, uy, p, T, cc);
+  if (c->g.precision == 64) launch_fields<double>(c, ux, uy, p, T, th, cc);
+  else launch_fields<float>(c, ux, uy, p, T, th, cc);
   return check_launch(c, "fields");
 }
 

@@ -128,16 +128,32 @@ __global__ __launch_bounds__(kBlock) void k_obs_cells(const R* __restrict__ src,
   }
 }
 
-// Sum the per-workgroup partials in a fixed order.
-__global__ void k_obs_final(const double* __restrict__ partial, int nblocks, double* __restrict__ out) {
-  const int i = threadIdx.x;
-  if (i >= kObsQ) return;
-  double s = i == 6 ? -1e300 : 0.0;
-  for (int b = 0; b < nblocks; ++b) {
+// Sum the per-workgroup partials in a fixed order: workgroup i reduces
+// quantity i; thread t sums the contiguous chunk t of the partials, then a
+// fixed tree combines the chunks.
+__global__ __launch_bounds__(kBlock) void k_obs_final(const double* __restrict__ partial, int nblocks,
+                                                      double* __restrict__ out) {
+  const int i = blockIdx.x;
+  const bool is_max = i == 6;
+  const int per = (nblocks + kBlock - 1) / kBlock;
+  const int b0 = threadIdx.x * per;
+  const int b1 = b0 + per < nblocks ? b0 + per : nblocks;
+  double s = is_max ? -1e300 : 0.0;
+  for (int b = b0; b < b1; ++b) {
     const double v = partial[(size_t)b * kObsQ + i];
-    s = i == 6 ? fmax(s, v) : s + v;
+    s = is_max ? fmax(s, v) : s + v;
   }
-  out[i] = s;
+  __shared__ double red[kBlock];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double o = red[threadIdx.x + w];
+      red[threadIdx.x] = is_max ? fmax(red[threadIdx.x], o) : red[threadIdx.x] + o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
 }
 
 // Per-column CL profiles: i(x) = sum over CL rows of 4 F C_ref s_c / dt * dx,
@@ -174,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_fields(const R* __restrict__ src,
                                                    const R* __restrict__ phi_f,
                                                    const R* __restrict__ invk_f,
                                                    const R* __restrict__ d_f, Consts<R> k,
-                                                   R* ux, R* uy, R* p, R* T, R* c) {
+                                                   R* ux, R* uy, R* p, R* T, R* theta, R* c) {
   const int x = blockIdx.x * kBlock + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= k.nx) return;
@@ -185,7 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_fields(const R* __restrict__ src,
   if (ux) ux[o] = a.ux;
   if (uy) uy[o] = a.uy;
   if (p) p[o] = a.p;
-  if (T) T[o] = k.T_in + (f[9] + f[10] + f[11] + f[12] + f[13]);
+  const R th = f[9] + f[10] + f[11] + f[12] + f[13];
+  if (T) T[o] = k.T_in + th;
+  if (theta) theta[o] = th;
   if (c) c[o] = f[14] + f[15] + f[16] + f[17] + f[18];
 }
 

@@ -75,7 +75,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_init_equilibrium": (ctypes.c_int, [vp]),
         "lbm_step": (ctypes.c_int, [vp, i64]),
         "lbm_observables": (ctypes.c_int, [vp, P(Obs), vp, vp, vp]),
-        "lbm_get_fields": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+        "lbm_get_fields": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
         "lbm_set_populations": (ctypes.c_int, [vp, vp, i64]),
         "lbm_state_bytes": (sz, [vp]),
@@ -210,8 +210,8 @@ class Cathode:
 
     def fields(self) -> dict:
         out = {k: torch.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
-               for k in ("ux", "uy", "p", "T", "c")}
-        self._check(self.lib.lbm_get_fields(self.ctx, *[_ptr(out[k]) for k in ("ux", "uy", "p", "T", "c")]))
+               for k in ("ux", "uy", "p", "T", "theta", "c")}
+        self._check(self.lib.lbm_get_fields(self.ctx, *[_ptr(out[k]) for k in ("ux", "uy", "p", "T", "theta", "c")]))
         return out
 
     def populations(self) -> torch.Tensor:
