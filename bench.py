@@ -69,12 +69,67 @@ def cpu_baseline(w, phi, target_s: float = 15.0):
                       f"({dt:.1f} s)"}
 
 
+def _timed(stream, fn):
+    """Run fn() between two events on ``stream``; returns (wall s, event s)."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, e0.elapsed_time(e1) / 1e3
+
+
+def bench_batched(steps: int, seq_steps: int) -> dict:
+    """The 64-case sweep in one batch (autotuned schedule) against the plain
+    single-case solver run on the same cases one after the other."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2103_01444_amd import BatchedSweep, Cathode
+
+    cases = W.batched_cases()
+    cells = sum(w["nx"] * w["ny"] for w in cases)
+    b = BatchedSweep(cases)
+    tune = b.autotune(trial_steps=10, cache_path=os.environ.get(
+        "LBMPEM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lbmpem_tune.json")))
+    b.step(20)
+    wall, ev = _timed(b.stream, lambda: b.step(steps))
+    obs = b.observables()
+    del b
+    sims = [Cathode.from_workload(w) for w in cases]
+    for s in sims:
+        s.step(5)
+
+    def seq():
+        for s in sims:
+            s.step(seq_steps)
+
+    wall_seq, _ = _timed(sims[0].stream, seq)
+    del sims
+    mlups = cells * steps / wall / 1e6
+    mlups_seq = cells * seq_steps / wall_seq / 1e6
+    achieved = cells * BYTES_PER_LU_POPS * steps / ev / 1e9
+    return {"workload": "batched_sweep_64", "cases": len(cases), "cells": cells, "steps": steps,
+            "value": round(mlups, 1), "unit": "MLUPS", "ms_per_step": round(wall * 1e3 / steps, 4),
+            "schedule": {k: tune[k] for k in ("tile_x", "tile_y", "persistent")},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_lattice_update": BYTES_PER_LU_POPS},
+            "plain_sequential": {"value": round(mlups_seq, 1), "unit": "MLUPS", "steps_per_case": seq_steps},
+            "speedup_vs_plain_sequential": round(mlups / mlups_seq, 3),
+            "mean_current_density_A_cm2": float(np.mean([o["current_density"] for o in obs]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=500, help="0 skips the batched sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write copy kernel 5 times (counter calibration)")
     args = ap.parse_args()
@@ -152,6 +207,12 @@ def main():
         "observables": {"current_density_A_cm2": obs["current_density"], "T_max_K": obs["T_max"],
                         "o2_utilisation": obs["o2_utilisation"]},
     }
+    del sim
+    if args.batched_steps > 0:
+        print("bench: batched sweep", file=sys.stderr, flush=True)
+        line["batched"] = bench_batched(args.batched_steps, max(1, args.batched_steps // 2))
+        print(f"bench: batched {line['batched']['value']} MLUPS, "
+              f"{line['batched']['speedup_vs_plain_sequential']}x plain sequential", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, phi)
     print(json.dumps(line), flush=True)

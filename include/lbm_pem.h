@@ -202,6 +202,55 @@ void lbm_destroy(lbm_ctx* ctx);
 const char* lbm_status_string(lbm_status s);
 const char* lbm_last_error(const lbm_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Batched parameter sweep.  The paper's results are sweeps over operating
+ * voltage, temperature, flow rate, permeability, porosity and effective
+ * diffusivity (Section 5); a batch advances many such independent cases,
+ * each a layered cathode (lbm_params' layered inputs, no per-cell arrays)
+ * with its own lattice size, all in one precision, together.  Each case
+ * computes exactly what a single context with the same geometry and
+ * parameters computes (bit for bit).
+ *
+ * Work is cut into equal tiles of tile_x x tile_y nodes; the schedule runs
+ * either one launch per step (persistent = 0) or one cooperative
+ * persistent launch that steps all cases with a grid-wide barrier between
+ * steps (persistent = 1).  lbm_batch_autotune times candidate schedules on
+ * the batch's current state, keeps the fastest and restores the state.
+ * --------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+typedef struct lbm_schedule {
+  int32_t tile_x, tile_y;  /* tile_x * tile_y in [64, 65536] */
+  int32_t persistent;      /* 0: one launch per step; 1: one cooperative launch */
+  int32_t reserved;
+} lbm_schedule;
+
+/* Device workspace for ncases lattices (state pool, autotuning backup,
+ * tables, reduction scratch); 0 if a geometry is invalid or precisions differ. */
+size_t lbm_batch_workspace_bytes(const lbm_geometry* g, int32_t ncases);
+
+/* g[ncases], p[ncases]: per-case geometry and layered inputs, validated as
+ * by lbm_set_params.  On error *out may still hold a batch so that
+ * lbm_batch_last_error() can explain; destroy it.  Synchronous. */
+lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t ncases, void* dev_ws,
+                            size_t ws_bytes, void* hip_stream, lbm_batch** out);
+lbm_status lbm_batch_init_equilibrium(lbm_batch* b);
+lbm_status lbm_batch_set_schedule(lbm_batch* b, const lbm_schedule* s);
+lbm_status lbm_batch_get_schedule(const lbm_batch* b, lbm_schedule* s);
+/* Time every candidate schedule for trial_steps steps from the current
+ * state; keep the fastest, restore the state.  Synchronous. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_schedule* best, double* best_ms_per_step);
+/* Advance every case nsteps steps.  Async. */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
+/* out[ncases]: observables of every case (as lbm_observables).  Synchronous. */
+lbm_status lbm_batch_observables(lbm_batch* b, lbm_obs* out);
+/* Canonical populations of case i (layout of lbm_get_populations).  Async. */
+lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t i, void* dev_dst);
+int64_t lbm_batch_step_count(const lbm_batch* b);
+lbm_status lbm_batch_synchronize(lbm_batch* b);
+void lbm_batch_destroy(lbm_batch* b);
+const char* lbm_batch_last_error(const lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

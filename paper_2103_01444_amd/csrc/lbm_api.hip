@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "lbm_host.hpp"
 #include "lbm_kernels2d.hpp"
 #include "lbm_pem.h"
 
@@ -19,8 +20,6 @@ using namespace lbm;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr double kMaxDiff = 0.14433756729740643;  // 1/(4 sqrt 3): b <= 1 keeps g0_eq >= 0
-
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
@@ -35,18 +34,6 @@ struct Layout {
   size_t total = 0;
   int nblocks_obs = 0;
 };
-
-bool geometry_ok(const lbm_geometry* g) {
-  if (!g) return false;
-  if (g->nx < 3 || g->ny < 1 || g->ny > 65535) return false;  // rows map to gridDim.y
-  if (g->ny_channel < 0 || g->ny_gdl < 0 || g->ny_cl < 0) return false;
-  if (g->ny_channel + g->ny_gdl + g->ny_cl != g->ny) return false;
-  if (g->precision != 32 && g->precision != 64) return false;
-  if (g->flags & ~(LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_BODY_FORCE | LBM_NO_REACTION)) return false;
-  const int64_t pitch = (int64_t(g->nx) + 63) / 64 * 64;
-  if (pitch * g->ny * 19 >= (int64_t(1) << 31)) return false;  // 32-bit element offsets
-  return true;
-}
 
 Layout make_layout(const lbm_geometry* g) {
   Layout L;
@@ -87,7 +74,7 @@ struct lbm_ctx {
   int mat = MAT_LAYERED;
   Consts<float> kf{};
   Consts<double> kd{};
-  double dx = 0, dt = 0, u_avg = 0, inflow = 0;
+  Derived d;
   std::string err;
 
   void* state(int i) { return ws + L.off_state[i]; }
@@ -108,55 +95,6 @@ lbm_status check_launch(lbm_ctx* c, const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
   return LBM_OK;
-}
-
-template <typename R>
-void fill_consts(Consts<R>& k, const lbm_ctx* c, double nu, double invk_gdl, double d_gdl,
-                 double alpha_scale, double ln_k0) {
-  const lbm_geometry& g = c->g;
-  const lbm_params& p = c->p;
-  k.nx = g.nx;
-  k.ny = g.ny;
-  k.pitch = c->L.pitch;
-  k.ny_ch = g.ny_channel;
-  k.y_cl0 = g.ny_channel + g.ny_gdl;
-  k.flags = g.flags;
-  k.plane = int32_t(c->L.plane);
-  k.pad_ = 0;
-  const double se = 1.0 / p.tau_f;
-  k.s_e = R(se);
-  k.s_q = R(8.0 * (2.0 - se) / (8.0 - se));
-  k.nu = R(nu);
-  k.u_in_coef = g.ny_channel > 0 ? R(6.0 * c->u_avg / (double(g.ny_channel) * g.ny_channel)) : R(0);
-  k.ax = R(p.body_force_x);
-  k.ay = R(p.body_force_y);
-  k.phi_gdl = R(p.phi_gdl);
-  k.invk_gdl = R(invk_gdl);
-  k.d_gdl = R(d_gdl);
-  k.D_f = R(p.D_f_lat);
-  k.kc_inv = p.dp_lat > 0 ? R(1.0 / (0.0067 * p.dp_lat * p.dp_lat)) : R(0);
-  k.deff_ratio = R(p.deff_ratio_gdl);
-  k.k_f = R(p.k_f);
-  k.k_s = R(p.k_s);
-  k.rhocp_f = R(p.rhocp_f);
-  k.rhocp_s = R(p.rhocp_s);
-  k.alpha_scale = R(alpha_scale);
-  k.T_in = R(p.T_in_K);
-  k.c_in = R(p.c_in);
-  k.V_op = R(p.V_op);
-  k.U0_slope = R(p.U0_slope);
-  k.U0_icept = R(p.U0_icept);
-  k.ln_k0 = R(ln_k0);
-  k.E_over_R = R(p.E_over_R);
-  k.inv_T_arrh = R(1.0 / p.T_arrh);
-  k.aF_over_R = R(p.alpha_c * p.faraday / p.R_gas);
-  k.four_f_cref = R(4.0 * p.faraday * p.C_ref);
-}
-
-// Lattice thermal diffusivity of Eq. 19 at porosity phi.
-double alpha_lat(const lbm_params& p, double phi, double alpha_scale) {
-  const double rc = phi * p.rhocp_f + (1.0 - phi) * p.rhocp_s;
-  return (p.k_f * phi + p.k_s * (1.0 - phi)) * alpha_scale / rc;
 }
 
 template <typename R>
@@ -250,7 +188,7 @@ void launch_obs_mat(lbm_ctx* c, double i_scale) {
   const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
   hipLaunchKernelGGL((k_obs_cells<R, MAT>), grid, dim3(kBlock), 0, c->stream, src, m.phi, m.invk, m.d,
                      consts<R>(c), c->partial());
-  hipLaunchKernelGGL(k_obs_final, dim3(kObsQ), dim3(kBlock), 0, c->stream, c->partial(), c->L.nblocks_obs, c->out());
+  hipLaunchKernelGGL(k_obs_final<kObsQ>, dim3(kObsQ), dim3(kBlock), 0, c->stream, c->partial(), c->L.nblocks_obs, c->out());
   const dim3 pgrid((c->g.nx + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_obs_profiles<R, MAT>), pgrid, dim3(kBlock), 0, c->stream, src, m.phi, m.invk, m.d,
                      consts<R>(c), i_scale, c->prof());
@@ -289,46 +227,11 @@ lbm_status set_params_t(lbm_ctx* c, const lbm_params* p, const void* phi, const 
                         const void* d_eff) {
   const lbm_geometry& g = c->g;
   c->p = *p;
-  // Lattice <-> physical scales: dx from the GDL thickness (or given), dt
-  // from the O2 diffusivity, D_lat = D dt / dx^2.
-  if (p->dx_cm > 0) {
-    c->dx = p->dx_cm;
-  } else if (g.ny_gdl > 0 && p->gdl_thickness_cm > 0) {
-    c->dx = p->gdl_thickness_cm / g.ny_gdl;
-  } else {
-    return fail(c, LBM_ERR_INVALID_ARG, "lattice spacing undefined: give dx_cm or a GDL with gdl_thickness_cm");
-  }
-  if (!(p->D_O2_cm2s > 0) || !(p->tau_f > 0.5))
-    return fail(c, LBM_ERR_UNSTABLE_PARAMS, "need tau_f > 0.5 and D_O2_cm2s > 0");
-  if (!(p->D_f_lat > 0) || p->D_f_lat > kMaxDiff)
-    return fail(c, LBM_ERR_UNSTABLE_PARAMS, "D_f_lat outside (0, 1/(4 sqrt 3)]");
-  if (!(p->phi_gdl > 0) || p->phi_gdl > 1) return fail(c, LBM_ERR_UNSTABLE_PARAMS, "phi_gdl outside (0, 1]");
-  if (p->Da_gdl < 0 || p->deff_ratio_gdl < 0 || p->dp_lat < 0)
-    return fail(c, LBM_ERR_INVALID_ARG, "negative Da_gdl, deff_ratio_gdl or dp_lat");
-  if (!(p->T_in_K > 0) || !(p->rhocp_f > 0) || !(p->rhocp_s > 0) || !(p->C_ref > 0) || !(p->faraday > 0))
-    return fail(c, LBM_ERR_INVALID_ARG, "non-positive temperature, heat capacity or reaction constant");
-  c->dt = p->D_f_lat * c->dx * c->dx / p->D_O2_cm2s;
-  const double nu = (p->tau_f - 0.5) / 3.0;
-  c->u_avg = g.ny_channel > 0 ? p->Re * nu / g.ny_channel : 0.0;
-  if (!(g.flags & LBM_PERIODIC_X) && 1.5 * std::fabs(c->u_avg) > 0.1)
-    return fail(c, LBM_ERR_UNSTABLE_PARAMS, "inlet peak velocity above 0.1");
-  const double invk_gdl = (p->Da_gdl > 0 && g.ny_gdl > 0) ? 1.0 / (p->Da_gdl * double(g.ny_gdl) * g.ny_gdl) : 0.0;
-  const double d_gdl = p->deff_ratio_gdl > 0 ? p->deff_ratio_gdl * p->D_f_lat
-                                             : std::pow(p->phi_gdl, 1.5) * p->D_f_lat;
-  const double alpha_scale = c->dt / (c->dx * c->dx) / 100.0;
-  const double ln_k0 = std::log(p->aj0_ref * c->dt / (4.0 * p->faraday * p->C_ref));
-  fill_consts(c->kf, c, nu, invk_gdl, d_gdl, alpha_scale, ln_k0);
-  fill_consts(c->kd, c, nu, invk_gdl, d_gdl, alpha_scale, ln_k0);
-  // Mean advective O2 inflow per step over the inlet rows (denominator of
-  // the utilisation).
-  c->inflow = 0;
-  if (!(g.flags & LBM_PERIODIC_X)) {
-    const double coef = g.ny_channel > 0 ? 6.0 * c->u_avg / (double(g.ny_channel) * g.ny_channel) : 0.0;
-    for (int y = 0; y < g.ny_channel; ++y) {
-      const double yc = y + 0.5;
-      c->inflow += coef * yc * (g.ny_channel - yc) * p->c_in;
-    }
-  }
+  std::string msg;
+  if (lbm_status st = derive(g, *p, c->d, msg); st != LBM_OK) return fail(c, st, msg);
+  const double invk_gdl = c->d.invk_gdl, d_gdl = c->d.d_gdl, alpha_scale = c->d.alpha_scale;
+  fill_consts(c->kf, g, *p, c->d, c->L.pitch);
+  fill_consts(c->kd, g, *p, c->d, c->L.pitch);
 
   // Material mode and per-cell arrays.
   const bool any = phi || inv_k || d_eff;
@@ -386,7 +289,7 @@ template <typename R>
 lbm_status observables_t(lbm_ctx* c, lbm_obs* o, double* pi, double* pc, double* pT) {
   const lbm_params& p = c->p;
   const double four_fc = 4.0 * p.faraday * p.C_ref;
-  const double i_scale = four_fc / c->dt * c->dx;  // i(x) = sum_CL (4 F C_ref s_c / dt) dx
+  const double i_scale = four_fc / c->d.dt * c->d.dx;  // i(x) = sum_CL (4 F C_ref s_c / dt) dx
   launch_obs<R>(c, i_scale);
   if (lbm_status s = check_launch(c, "observables"); s != LBM_OK) return s;
   double h[kObsQ];
@@ -404,7 +307,7 @@ lbm_status observables_t(lbm_ctx* c, lbm_obs* o, double* pi, double* pc, double*
   r.current_density = sum_sc * i_scale / c->g.nx;
   r.power_density = p.V_op * r.current_density;
   r.heat_rate = h[5] * i_scale / c->g.nx;
-  r.o2_utilisation = c->inflow > 0 ? sum_sc / c->inflow : 0.0;
+  r.o2_utilisation = c->d.inflow > 0 ? sum_sc / c->d.inflow : 0.0;
   r.T_max = p.T_in_K + h[6];
   r.sum_f = h[0] + ncell;  // the rest population is stored as f0 - rho0
   r.sum_theta = h[1];
@@ -474,7 +377,7 @@ lbm_status lbm_create(const lbm_geometry* g, void* dev_ws, size_t ws_bytes, void
   c->L = L;
   c->ws = static_cast<char*>(dev_ws);
   c->stream = static_cast<hipStream_t>(hip_stream);
-  hipGetDevice(&c->device);
+  (void)hipGetDevice(&c->device);
   *out = c;
   return LBM_OK;
 }

@@ -1,0 +1,83 @@
+// Batched parameter sweep: many independent layered cathode lattices of
+// uneven sizes advanced together.  The lattices live in one pool; a flat
+// list of equal-shape tiles (case, x0, y0) covers all of them.  Two launch
+// forms share the per-tile body:
+//   k_batch_step        one workgroup per tile, one launch per time step;
+//   k_batch_persistent  one cooperative launch for many steps: each
+//                       workgroup owns a contiguous chunk of tiles and the
+//                       grid synchronizes between steps.
+#pragma once
+
+#include <hip/hip_cooperative_groups.h>
+
+#include "lbm_kernels2d.hpp"
+
+namespace lbm {
+
+template <typename R>
+struct BatchCase {
+  Consts<R> k;
+  int64_t off[2];  // element offsets of the two state buffers in the pool
+};
+
+struct Tile {
+  int32_t c, x0, y0, pad;
+};
+
+// Advance the cells of one tile (tx x ty cells, row-major inside the tile).
+template <typename R>
+__device__ __forceinline__ void batch_tile(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
+                                           const Tile& t, int parity, int tx, int ty) {
+  const Consts<R> k = cases[t.c].k;
+  const int64_t o_src = cases[t.c].off[parity], o_dst = cases[t.c].off[parity ^ 1];
+  const R* src = pool + o_src;
+  R* dst = pool + o_dst;
+  const int n = tx * ty;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int y = t.y0 + i / tx;
+    const int x = t.x0 + i % tx;
+    if (x >= k.nx || y >= k.ny) continue;
+    R f[19];
+    const Mat<R> mt = pre_collision<R, MAT_LAYERED>(src, k, nullptr, nullptr, nullptr, x, y, f);
+    collide(f, mt, k, y >= k.y_cl0 && !(k.flags & F_NO_REACTION));
+    const int o = y * k.pitch + x;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
+  }
+}
+
+// Logical index of this workgroup such that each XCD (workgroups are dealt
+// to the 8 XCDs round-robin) owns a contiguous range of logical indices.
+__device__ __forceinline__ int xcd_logical(int flat, int total) {
+  const int xcd = flat & 7, slot = flat >> 3;
+  const int full = total >> 3, rem = total & 7;
+  return xcd * full + (xcd < rem ? xcd : rem) + slot;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_batch_step(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
+                                                       const Tile* __restrict__ tiles, int ntiles, int parity,
+                                                       int tx, int ty) {
+  const int t = xcd_logical(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;
+  batch_tile(pool, cases, tiles[t], parity, tx, ty);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_batch_persistent(R* __restrict__ pool,
+                                                             const BatchCase<R>* __restrict__ cases,
+                                                             const Tile* __restrict__ tiles, int ntiles,
+                                                             int nsteps, int parity0, int tx, int ty) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int t0 = int((int64_t(lb) * ntiles) / gridDim.x);
+  const int t1 = int((int64_t(lb + 1) * ntiles) / gridDim.x);
+  for (int s = 0; s < nsteps; ++s) {
+    const int parity = (parity0 + s) & 1;
+    for (int t = t0; t < t1; ++t) batch_tile(pool, cases, tiles[t], parity, tx, ty);
+    grid.sync();
+  }
+}
+
+}  // namespace lbm

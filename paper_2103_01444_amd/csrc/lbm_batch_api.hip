@@ -1,0 +1,423 @@
+// Host side of the batched sweep (lbm_batch_* in include/lbm_pem.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_batch.hpp"
+#include "lbm_host.hpp"
+#include "lbm_pem.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMinTileCells = 64;  // smallest tile the schedule accepts (sizes the tile table)
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct BatchLayout {
+  std::vector<int64_t> state_off[2];  // element offsets per case
+  int64_t pool_elems = 0;
+  size_t off_pool = 0, off_backup = 0, off_cases = 0, off_tiles = 0, off_partial = 0, off_prof = 0, off_out = 0;
+  size_t total = 0;
+  int max_tiles = 0;
+  int max_obs_blocks = 0;
+  int max_nx = 0;
+  size_t esize = 4;
+};
+
+bool batch_geometry_ok(const lbm_geometry* g, int n) {
+  if (!g || n < 1) return false;
+  for (int i = 0; i < n; ++i) {
+    if (!geometry_ok(&g[i])) return false;
+    if (g[i].precision != g[0].precision) return false;
+  }
+  return true;
+}
+
+BatchLayout make_batch_layout(const lbm_geometry* g, int n) {
+  BatchLayout L;
+  L.esize = g[0].precision == 64 ? 8 : 4;
+  int64_t e = 0;
+  L.state_off[0].resize(n);
+  L.state_off[1].resize(n);
+  for (int i = 0; i < n; ++i) {
+    const int64_t plane = int64_t(pitch_of(g[i].nx)) * g[i].ny;
+    for (int s = 0; s < 2; ++s) {
+      L.state_off[s][i] = e;
+      e += (19 * plane + 63) / 64 * 64;  // 256-byte aligned per buffer
+    }
+    L.max_tiles += int((int64_t(pitch_of(g[i].nx)) * g[i].ny + kMinTileCells - 1) / kMinTileCells);
+    L.max_obs_blocks = std::max(L.max_obs_blocks, ((g[i].nx + kBlock - 1) / kBlock) * g[i].ny);
+    L.max_nx = std::max(L.max_nx, g[i].nx);
+  }
+  L.pool_elems = e;
+  size_t o = 0;
+  L.off_pool = o;
+  o += align_up(size_t(e) * L.esize);
+  L.off_backup = o;  // one state per case, for autotuning trials
+  o += align_up(size_t(e) * L.esize / 2 + size_t(n) * 256);
+  L.off_cases = o;
+  o += align_up(size_t(n) * (L.esize == 8 ? sizeof(BatchCase<double>) : sizeof(BatchCase<float>)));
+  L.off_tiles = o;
+  o += align_up(size_t(L.max_tiles) * sizeof(Tile));
+  L.off_partial = o;
+  o += align_up(size_t(L.max_obs_blocks) * kObsQ * sizeof(double));
+  L.off_prof = o;
+  o += align_up(size_t(3) * L.max_nx * sizeof(double));
+  L.off_out = o;
+  o += align_up(16 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_batch {
+  int n = 0;
+  std::vector<lbm_geometry> g;
+  std::vector<lbm_params> p;
+  std::vector<Derived> d;
+  std::vector<Consts<float>> kf;
+  std::vector<Consts<double>> kd;
+  BatchLayout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int parity = 0;  // state buffer index holding the current state
+  int64_t step = 0;
+  lbm_schedule sched{256, 1, 0, 0};
+  int ntiles = 0;
+  int persistent_grid = 0;
+  std::string err;
+
+  template <typename R>
+  R* pool() { return reinterpret_cast<R*>(ws + L.off_pool); }
+  template <typename R>
+  BatchCase<R>* cases() { return reinterpret_cast<BatchCase<R>*>(ws + L.off_cases); }
+  Tile* tiles() { return reinterpret_cast<Tile*>(ws + L.off_tiles); }
+  double* partial() { return reinterpret_cast<double*>(ws + L.off_partial); }
+  double* prof() { return reinterpret_cast<double*>(ws + L.off_prof); }
+  double* out() { return reinterpret_cast<double*>(ws + L.off_out); }
+};
+
+namespace {
+
+lbm_status bfail(lbm_batch* b, lbm_status s, const std::string& m) {
+  if (b) b->err = m;
+  return s;
+}
+
+template <typename R>
+const Consts<R>& bconsts(const lbm_batch* b, int i);
+template <>
+const Consts<float>& bconsts<float>(const lbm_batch* b, int i) { return b->kf[i]; }
+template <>
+const Consts<double>& bconsts<double>(const lbm_batch* b, int i) { return b->kd[i]; }
+
+template <typename R>
+lbm_status upload_cases(lbm_batch* b) {
+  std::vector<BatchCase<R>> h(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    h[i].k = bconsts<R>(b, i);
+    h[i].off[0] = b->L.state_off[0][i];
+    h[i].off[1] = b->L.state_off[1][i];
+  }
+  if (hipMemcpyAsync(b->cases<R>(), h.data(), h.size() * sizeof(BatchCase<R>), hipMemcpyHostToDevice, b->stream) !=
+      hipSuccess)
+    return bfail(b, LBM_ERR_DEVICE, "case table upload failed");
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, LBM_ERR_DEVICE, "case table sync failed");
+  return LBM_OK;
+}
+
+// Build the tile list for a tile shape; cases in order, rows then columns.
+lbm_status build_tiles(lbm_batch* b, int tx, int ty) {
+  std::vector<Tile> t;
+  for (int i = 0; i < b->n; ++i)
+    for (int y0 = 0; y0 < b->g[i].ny; y0 += ty)
+      for (int x0 = 0; x0 < b->g[i].nx; x0 += tx) t.push_back({i, x0, y0, 0});
+  if (int(t.size()) > b->L.max_tiles) return bfail(b, LBM_ERR_INVALID_ARG, "tile too small");
+  if (hipMemcpyAsync(b->tiles(), t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    return bfail(b, LBM_ERR_DEVICE, "tile table upload failed");
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, LBM_ERR_DEVICE, "tile table sync failed");
+  b->ntiles = int(t.size());
+  return LBM_OK;
+}
+
+template <typename R>
+int cooperative_grid(lbm_batch* b) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_batch_persistent<R>),
+                                                   kBlock, 0) != hipSuccess)
+    return 0;
+  const int co = ncu * per_cu;
+  return std::min(co, b->ntiles);
+}
+
+template <typename R>
+lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
+  R* pool = b->pool<R>();
+  const BatchCase<R>* cases = b->cases<R>();
+  const Tile* tiles = b->tiles();
+  const int tx = b->sched.tile_x, ty = b->sched.tile_y;
+  if (b->sched.persistent) {
+    int grid = b->persistent_grid;
+    int64_t left = nsteps;
+    while (left > 0) {
+      int chunk = int(std::min<int64_t>(left, 1 << 20));
+      int ntiles = b->ntiles, par = b->parity;
+      void* args[] = {&pool, &cases, &tiles, &ntiles, &chunk, &par, const_cast<int*>(&tx), const_cast<int*>(&ty)};
+      const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch_persistent<R>),
+                                                      dim3(grid), dim3(kBlock), args, 0, b->stream);
+      if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
+      b->parity = (b->parity + chunk) & 1;
+      left -= chunk;
+    }
+  } else {
+    for (int64_t s = 0; s < nsteps; ++s) {
+      hipLaunchKernelGGL(k_batch_step<R>, dim3(b->ntiles), dim3(kBlock), 0, b->stream, pool, cases, tiles, b->ntiles,
+                         b->parity, tx, ty);
+      b->parity ^= 1;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
+  }
+  b->step += nsteps;
+  return LBM_OK;
+}
+
+template <typename R>
+lbm_status set_schedule_t(lbm_batch* b, const lbm_schedule& s) {
+  if (s.tile_x < 1 || s.tile_y < 1 || s.tile_x * s.tile_y < kMinTileCells || s.tile_x * s.tile_y > 1 << 16)
+    return bfail(b, LBM_ERR_INVALID_ARG, "tile shape out of range");
+  b->sched = s;
+  if (lbm_status st = build_tiles(b, s.tile_x, s.tile_y); st != LBM_OK) return st;
+  if (s.persistent) {
+    b->persistent_grid = cooperative_grid<R>(b);
+    if (b->persistent_grid < 1) return bfail(b, LBM_ERR_DEVICE, "no co-resident grid for the persistent kernel");
+  }
+  return LBM_OK;
+}
+
+template <typename R>
+lbm_status init_t(lbm_batch* b) {
+  for (int i = 0; i < b->n; ++i) {
+    const dim3 grid((b->g[i].nx + kBlock - 1) / kBlock, b->g[i].ny);
+    hipLaunchKernelGGL((k_init<R, MAT_LAYERED>), grid, dim3(kBlock), 0, b->stream,
+                       b->pool<R>() + b->L.state_off[0][i], nullptr, nullptr, nullptr, bconsts<R>(b, i));
+  }
+  b->parity = 0;
+  b->step = 0;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LBM_OK : bfail(b, LBM_ERR_DEVICE, std::string("batch init: ") + hipGetErrorString(e));
+}
+
+template <typename R>
+lbm_status observables_t(lbm_batch* b, lbm_obs* out) {
+  for (int i = 0; i < b->n; ++i) {
+    const lbm_geometry& g = b->g[i];
+    const lbm_params& p = b->p[i];
+    const Consts<R>& k = bconsts<R>(b, i);
+    const R* src = b->pool<R>() + b->L.state_off[b->parity][i];
+    const dim3 grid((g.nx + kBlock - 1) / kBlock, g.ny);
+    hipLaunchKernelGGL((k_obs_cells<R, MAT_LAYERED>), grid, dim3(kBlock), 0, b->stream, src, nullptr, nullptr,
+                       nullptr, k, b->partial());
+    hipLaunchKernelGGL(k_obs_final<kObsQ>, dim3(kObsQ), dim3(kBlock), 0, b->stream, b->partial(),
+                       int(grid.x * grid.y), b->out());
+    double h[kObsQ];
+    if (hipMemcpyAsync(h, b->out(), sizeof(h), hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+      return bfail(b, LBM_ERR_DEVICE, "batch observables failed");
+    const double i_scale = 4.0 * p.faraday * p.C_ref / b->d[i].dt * b->d[i].dx;
+    lbm_obs r{};
+    r.step = b->step;
+    r.current_density = h[3] * i_scale / g.nx;
+    r.power_density = p.V_op * r.current_density;
+    r.heat_rate = h[5] * i_scale / g.nx;
+    r.o2_utilisation = b->d[i].inflow > 0 ? h[3] / b->d[i].inflow : 0.0;
+    r.T_max = p.T_in_K + h[6];
+    r.sum_f = h[0] + double(g.nx) * g.ny;
+    r.sum_theta = h[1];
+    r.sum_c = h[2];
+    r.consumed_c = h[3];
+    r.heat_added = h[4];
+    out[i] = r;
+    if (!std::isfinite(r.current_density) || !std::isfinite(r.sum_f) || h[7] > 0)
+      return bfail(b, LBM_ERR_NONFINITE, "non-finite observable in case " + std::to_string(i));
+  }
+  return LBM_OK;
+}
+
+template <typename R>
+lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double* best_ms) {
+  // Save the current state of every case, time each candidate from it, restore.
+  const size_t bytes = size_t(b->L.pool_elems) * sizeof(R);
+  char* pool = reinterpret_cast<char*>(b->pool<R>());
+  char* backup = b->ws + b->L.off_backup;
+  // The backup region holds one buffer per case: copy the current buffer of each case.
+  std::vector<size_t> boff(b->n);
+  size_t o = 0;
+  for (int i = 0; i < b->n; ++i) {
+    const size_t sz = size_t(19) * pitch_of(b->g[i].nx) * b->g[i].ny * sizeof(R);
+    boff[i] = o;
+    if (hipMemcpyAsync(backup + o, pool + b->L.state_off[b->parity][i] * sizeof(R), sz, hipMemcpyDeviceToDevice,
+                       b->stream) != hipSuccess)
+      return bfail(b, LBM_ERR_DEVICE, "autotune backup failed");
+    o += align_up(sz);
+  }
+  (void)bytes;
+  const int parity0 = b->parity;
+  const int64_t step0 = b->step;
+  const lbm_schedule keep = b->sched;
+  static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {1024, 1}, {64, 4},
+                                  {128, 2}, {256, 2}, {256, 4}, {512, 2}, {128, 8}, {64, 16}};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return bfail(b, LBM_ERR_DEVICE, "autotune events failed");
+  double best_t = 1e300;
+  lbm_schedule best_s = keep;
+  lbm_status st = LBM_OK;
+  for (int persistent = 0; persistent < 2 && st == LBM_OK; ++persistent) {
+    for (const auto& sh : shapes) {
+      lbm_schedule s{sh[0], sh[1], persistent, 0};
+      if (set_schedule_t<R>(b, s) != LBM_OK) continue;  // shape not usable here
+      st = launch_steps<R>(b, 2);                        // warm up
+      if (st != LBM_OK) break;
+      (void)hipEventRecord(e0, b->stream);
+      st = launch_steps<R>(b, trial_steps);
+      if (st != LBM_OK) break;
+      (void)hipEventRecord(e1, b->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st = bfail(b, LBM_ERR_DEVICE, "autotune trial failed");
+        break;
+      }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double per = double(ms) / trial_steps;
+      if (per < best_t) {
+        best_t = per;
+        best_s = s;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // Restore the saved state into the original buffers.
+  for (int i = 0; i < b->n; ++i) {
+    const size_t sz = size_t(19) * pitch_of(b->g[i].nx) * b->g[i].ny * sizeof(R);
+    if (hipMemcpyAsync(pool + b->L.state_off[parity0][i] * sizeof(R), backup + boff[i], sz, hipMemcpyDeviceToDevice,
+                       b->stream) != hipSuccess)
+      return bfail(b, LBM_ERR_DEVICE, "autotune restore failed");
+  }
+  b->parity = parity0;
+  b->step = step0;
+  if (st != LBM_OK) return st;
+  if (lbm_status s2 = set_schedule_t<R>(b, best_s); s2 != LBM_OK) return s2;
+  if (best) *best = best_s;
+  if (best_ms) *best_ms = best_t;
+  return hipStreamSynchronize(b->stream) == hipSuccess ? LBM_OK : bfail(b, LBM_ERR_DEVICE, "autotune sync failed");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(const lbm_geometry* g, int32_t ncases) {
+  if (!batch_geometry_ok(g, ncases)) return 0;
+  return make_batch_layout(g, ncases).total;
+}
+
+lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t ncases, void* dev_ws,
+                            size_t ws_bytes, void* hip_stream, lbm_batch** out) {
+  if (!out) return LBM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!batch_geometry_ok(g, ncases) || !p || !dev_ws) return LBM_ERR_INVALID_ARG;
+  const BatchLayout L = make_batch_layout(g, ncases);
+  if (ws_bytes < L.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign != 0) return LBM_ERR_INVALID_ARG;
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_ERR_INVALID_ARG;
+  b->n = ncases;
+  b->g.assign(g, g + ncases);
+  b->p.assign(p, p + ncases);
+  b->d.resize(ncases);
+  b->kf.resize(ncases);
+  b->kd.resize(ncases);
+  b->L = L;
+  b->ws = static_cast<char*>(dev_ws);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  *out = b;
+  for (int i = 0; i < ncases; ++i) {
+    std::string msg;
+    if (lbm_status st = derive(g[i], p[i], b->d[i], msg); st != LBM_OK)
+      return bfail(b, st, "case " + std::to_string(i) + ": " + msg);
+    fill_consts(b->kf[i], g[i], p[i], b->d[i], pitch_of(g[i].nx));
+    fill_consts(b->kd[i], g[i], p[i], b->d[i], pitch_of(g[i].nx));
+  }
+  const bool dbl = g[0].precision == 64;
+  if (lbm_status st = dbl ? upload_cases<double>(b) : upload_cases<float>(b); st != LBM_OK) return st;
+  lbm_schedule s{256, 1, 0, 0};
+  return dbl ? set_schedule_t<double>(b, s) : set_schedule_t<float>(b, s);
+}
+
+lbm_status lbm_batch_init_equilibrium(lbm_batch* b) {
+  if (!b) return LBM_ERR_INVALID_ARG;
+  return b->g[0].precision == 64 ? init_t<double>(b) : init_t<float>(b);
+}
+
+lbm_status lbm_batch_set_schedule(lbm_batch* b, const lbm_schedule* s) {
+  if (!b || !s) return LBM_ERR_INVALID_ARG;
+  return b->g[0].precision == 64 ? set_schedule_t<double>(b, *s) : set_schedule_t<float>(b, *s);
+}
+
+lbm_status lbm_batch_get_schedule(const lbm_batch* b, lbm_schedule* s) {
+  if (!b || !s) return LBM_ERR_INVALID_ARG;
+  *s = b->sched;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_schedule* best, double* best_ms_per_step) {
+  if (!b || trial_steps < 1) return LBM_ERR_INVALID_ARG;
+  return b->g[0].precision == 64 ? autotune_t<double>(b, trial_steps, best, best_ms_per_step)
+                                 : autotune_t<float>(b, trial_steps, best, best_ms_per_step);
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return LBM_ERR_INVALID_ARG;
+  return b->g[0].precision == 64 ? launch_steps<double>(b, nsteps) : launch_steps<float>(b, nsteps);
+}
+
+lbm_status lbm_batch_observables(lbm_batch* b, lbm_obs* out) {
+  if (!b || !out) return LBM_ERR_INVALID_ARG;
+  return b->g[0].precision == 64 ? observables_t<double>(b, out) : observables_t<float>(b, out);
+}
+
+lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t i, void* dst) {
+  if (!b || !dst || i < 0 || i >= b->n) return LBM_ERR_INVALID_ARG;
+  const dim3 grid((b->g[i].nx + kBlock - 1) / kBlock, b->g[i].ny);
+  if (b->g[0].precision == 64)
+    hipLaunchKernelGGL(k_export<double>, grid, dim3(kBlock), 0, b->stream,
+                       b->pool<double>() + b->L.state_off[b->parity][i], static_cast<double*>(dst), b->kd[i]);
+  else
+    hipLaunchKernelGGL(k_export<float>, grid, dim3(kBlock), 0, b->stream,
+                       b->pool<float>() + b->L.state_off[b->parity][i], static_cast<float*>(dst), b->kf[i]);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LBM_OK : bfail(b, LBM_ERR_DEVICE, std::string("get_populations: ") + hipGetErrorString(e));
+}
+
+int64_t lbm_batch_step_count(const lbm_batch* b) { return b ? b->step : -1; }
+
+lbm_status lbm_batch_synchronize(lbm_batch* b) {
+  if (!b) return LBM_ERR_INVALID_ARG;
+  const hipError_t e = hipStreamSynchronize(b->stream);
+  return e == hipSuccess ? LBM_OK : bfail(b, LBM_ERR_DEVICE, std::string("synchronize: ") + hipGetErrorString(e));
+}
+
+void lbm_batch_destroy(lbm_batch* b) { delete b; }
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"

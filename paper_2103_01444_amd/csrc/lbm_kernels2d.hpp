@@ -131,6 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_obs_cells(const R* __restrict__ src,
 // Sum the per-workgroup partials in a fixed order: workgroup i reduces
 // quantity i; thread t sums the contiguous chunk t of the partials, then a
 // fixed tree combines the chunks.
+template <int Q = kObsQ>  // a template so that every translation unit may instantiate it
 __global__ __launch_bounds__(kBlock) void k_obs_final(const double* __restrict__ partial, int nblocks,
                                                       double* __restrict__ out) {
   const int i = blockIdx.x;
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_obs_final(const double* __restrict__
   const int b1 = b0 + per < nblocks ? b0 + per : nblocks;
   double s = is_max ? -1e300 : 0.0;
   for (int b = b0; b < b1; ++b) {
-    const double v = partial[(size_t)b * kObsQ + i];
+    const double v = partial[(size_t)b * Q + i];
     s = is_max ? fmax(s, v) : s + v;
   }
   __shared__ double red[kBlock];

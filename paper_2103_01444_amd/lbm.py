@@ -49,12 +49,21 @@ class Obs(ctypes.Structure):
         "sum_c", "consumed_c", "heat_added")]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 _lib = None
 
 EXPORTED = ["lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_set_params", "lbm_init_equilibrium",
             "lbm_step", "lbm_observables", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations",
             "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count", "lbm_synchronize",
-            "lbm_destroy", "lbm_status_string", "lbm_last_error"]
+            "lbm_destroy", "lbm_status_string", "lbm_last_error",
+            "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_init_equilibrium", "lbm_batch_set_schedule",
+            "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_observables",
+            "lbm_batch_get_populations", "lbm_batch_step_count", "lbm_batch_synchronize", "lbm_batch_destroy",
+            "lbm_batch_last_error"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -86,6 +95,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_destroy": (None, [vp]),
         "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
+        "lbm_batch_workspace_bytes": (sz, [P(Geometry), ctypes.c_int32]),
+        "lbm_batch_create": (ctypes.c_int, [P(Geometry), P(Params), ctypes.c_int32, vp, sz, vp, P(vp)]),
+        "lbm_batch_init_equilibrium": (ctypes.c_int, [vp]),
+        "lbm_batch_set_schedule": (ctypes.c_int, [vp, P(Schedule)]),
+        "lbm_batch_get_schedule": (ctypes.c_int, [vp, P(Schedule)]),
+        "lbm_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int32, P(Schedule), P(ctypes.c_double)]),
+        "lbm_batch_step": (ctypes.c_int, [vp, i64]),
+        "lbm_batch_observables": (ctypes.c_int, [vp, P(Obs)]),
+        "lbm_batch_get_populations": (ctypes.c_int, [vp, ctypes.c_int32, vp]),
+        "lbm_batch_step_count": (i64, [vp]),
+        "lbm_batch_synchronize": (ctypes.c_int, [vp]),
+        "lbm_batch_destroy": (None, [vp]),
+        "lbm_batch_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -242,5 +264,117 @@ class Cathode:
                 self.lib.lbm_synchronize(self.ctx)
                 self.lib.lbm_destroy(self.ctx)
                 self.ctx = None
+        except Exception:
+            pass
+
+
+def _arch_name() -> str:
+    try:
+        return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+class BatchedSweep:
+    """Many independent layered cathode cases advanced together (C ABI
+    lbm_batch_*).  ``cases``: workload dictionaries (see ``workloads``), all
+    of one precision.  The schedule (tile shape, per-step or persistent
+    launch) is picked by ``autotune`` and cached in a JSON file keyed by GPU
+    architecture, precision and the case lattice sizes."""
+
+    def __init__(self, cases: list, device=None):
+        if not torch.cuda.is_available():
+            raise LbmError("no GPU: the solver runs only on the HIP device")
+        self.lib = load_library()
+        self.device = torch.device(device or "cuda")
+        n = len(cases)
+        prec = cases[0].get("precision", 32)
+        self.dtype = torch.float64 if prec == 64 else torch.float32
+        self.shapes = [(w["nx"], w["ny"]) for w in cases]
+        self.geoms = (Geometry * n)(*[Geometry(w["nx"], w["ny"], w["ny_channel"], w["ny_gdl"], w["ny_cl"],
+                                               w.get("precision", 32), 0) for w in cases])
+        self.params = (Params * n)(*[params_from_workload(w) for w in cases])
+        self.n = n
+        nbytes = self.lib.lbm_batch_workspace_bytes(self.geoms, n)
+        if nbytes == 0:
+            raise LbmError("invalid batch geometry")
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        self.h = ctypes.c_void_p()
+        st = self.lib.lbm_batch_create(self.geoms, self.params, n, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.h))
+        self._check(st)
+        self._check(self.lib.lbm_batch_init_equilibrium(self.h))
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.lbm_batch_last_error(self.h).decode() if self.h else ""
+            raise LbmError(f"{STATUS.get(st, st)}: {msg}")
+
+    def cache_key(self) -> str:
+        prec = 64 if self.dtype == torch.float64 else 32
+        return f"{_arch_name()}|fp{prec}|" + ",".join(f"{nx}x{ny}" for nx, ny in self.shapes)
+
+    @property
+    def schedule(self) -> dict:
+        s = Schedule()
+        self._check(self.lib.lbm_batch_get_schedule(self.h, ctypes.byref(s)))
+        return dict(tile_x=s.tile_x, tile_y=s.tile_y, persistent=s.persistent)
+
+    def set_schedule(self, tile_x: int, tile_y: int, persistent: int):
+        s = Schedule(tile_x, tile_y, persistent, 0)
+        self._check(self.lib.lbm_batch_set_schedule(self.h, ctypes.byref(s)))
+
+    def autotune(self, trial_steps: int = 20, cache_path: str | None = None) -> dict:
+        """Pick the fastest schedule (from the cache when present)."""
+        import json
+        key = self.cache_key()
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        if key in cache:
+            c = cache[key]
+            self.set_schedule(c["tile_x"], c["tile_y"], c["persistent"])
+            return dict(c, cached=True)
+        best = Schedule()
+        ms = ctypes.c_double()
+        self._check(self.lib.lbm_batch_autotune(self.h, int(trial_steps), ctypes.byref(best), ctypes.byref(ms)))
+        res = dict(tile_x=best.tile_x, tile_y=best.tile_y, persistent=best.persistent, ms_per_step=ms.value)
+        if cache_path:
+            cache[key] = res
+            os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1)
+        return dict(res, cached=False)
+
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm_batch_step(self.h, int(n)))
+
+    @property
+    def step_count(self) -> int:
+        return int(self.lib.lbm_batch_step_count(self.h))
+
+    def synchronize(self):
+        self._check(self.lib.lbm_batch_synchronize(self.h))
+
+    def observables(self) -> list:
+        out = (Obs * self.n)()
+        self._check(self.lib.lbm_batch_observables(self.h, out))
+        return [{name: getattr(o, name) for name, _ in Obs._fields_} for o in out]
+
+    def populations(self, i: int) -> torch.Tensor:
+        nx, ny = self.shapes[i]
+        t = torch.empty((19, ny, nx), dtype=self.dtype, device=self.device)
+        self._check(self.lib.lbm_batch_get_populations(self.h, int(i), _ptr(t)))
+        return t
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.lbm_batch_synchronize(self.h)
+                self.lib.lbm_batch_destroy(self.h)
+                self.h = None
         except Exception:
             pass
