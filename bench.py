@@ -123,6 +123,42 @@ def bench_batched(steps: int, seq_steps: int) -> dict:
             "mean_current_density_A_cm2": float(np.mean([o["current_density"] for o in obs]))}
 
 
+ADJ_BYTES_PER_LU = 19 * 4 * 4 + 3 * 4 + 3 * 4 * 2  # reverse step: S, lambda in/out pushes, 3 fields, gradient RMW
+FWD_FULL_BYTES_PER_LU = 19 * 4 * 2 + 3 * 4          # replayed forward step with three per-cell fields
+
+
+def bench_adjoint(nsteps: int = 4000, every: int = 200) -> dict:
+    """1024x256 FP32 cathode with per-cell (porosity, 1/K, D_eff): plain
+    forward, checkpointed forward and the hand-written adjoint."""
+    import workloads as W
+    from paper_2103_01444_amd import Cathode
+
+    w = W.adjoint2d()
+    phi = W.porosity_field(w)
+    sim = Cathode.from_workload(w, phi=phi, independent_fields=1)
+    cells = w["nx"] * w["ny"]
+    sim.step(50)
+    wall_f, _ = _timed(sim.stream, lambda: sim.step(nsteps))
+    res = {}
+    wall_cf, _ = _timed(sim.stream, lambda: res.update(J=sim.forward_checkpointed(nsteps, every)))
+    wall_b, _ = _timed(sim.stream, lambda: res.update(g=sim.backward(1.0)))
+    g = res["g"]
+    mlups_f = cells * nsteps / wall_f / 1e6
+    mlups_b = cells * nsteps / wall_b / 1e6
+    # backward = replay (one forward per step) + reverse step
+    achieved = cells * nsteps * (ADJ_BYTES_PER_LU + FWD_FULL_BYTES_PER_LU) / wall_b / 1e9
+    return {"workload": w["name"], "cells": cells, "steps": nsteps, "checkpoint_every": every,
+            "forward": {"value": round(mlups_f, 1), "unit": "MLUPS"},
+            "forward_checkpointed": {"value": round(cells * nsteps / wall_cf / 1e6, 1), "unit": "MLUPS"},
+            "adjoint": {"value": round(mlups_b, 1), "unit": "MLUPS", "seconds": round(wall_b, 4)},
+            "adjoint_over_forward_time": round(wall_b / wall_f, 3),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "bytes_per_lattice_update": ADJ_BYTES_PER_LU + FWD_FULL_BYTES_PER_LU},
+            "J_A_cm2": res["J"],
+            "max_abs_grad": {k: float(v.abs().max()) for k, v in g.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +166,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500, help="0 skips the batched sweep")
+    ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write copy kernel 5 times (counter calibration)")
     args = ap.parse_args()
@@ -213,6 +250,11 @@ def main():
         line["batched"] = bench_batched(args.batched_steps, max(1, args.batched_steps // 2))
         print(f"bench: batched {line['batched']['value']} MLUPS, "
               f"{line['batched']['speedup_vs_plain_sequential']}x plain sequential", file=sys.stderr, flush=True)
+    if args.adjoint_steps > 0:
+        print("bench: adjoint", file=sys.stderr, flush=True)
+        line["adjoint"] = bench_adjoint(args.adjoint_steps)
+        print(f"bench: adjoint {line['adjoint']['adjoint']['value']} MLUPS, "
+              f"{line['adjoint']['adjoint_over_forward_time']}x forward time", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, phi)
     print(json.dumps(line), flush=True)

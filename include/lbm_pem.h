@@ -181,6 +181,12 @@ lbm_status lbm_observables(lbm_ctx* ctx, lbm_obs* out, double* prof_i, double* p
  * full relative precision), c (relative).  NULL skips a field.  Async. */
 lbm_status lbm_get_fields(lbm_ctx* ctx, void* ux, void* uy, void* p, void* T, void* theta, void* c);
 
+/* The per-cell porosity, 1/K (lattice units) and O2 diffusivity (lattice
+ * units) the update uses, after the layered / Kozeny-Carman (Eq. 7) /
+ * Bruggeman (Eq. 18) derivations, into caller device arrays [ny][nx]
+ * (context precision; NULL skips one).  Async. */
+lbm_status lbm_get_material(lbm_ctx* ctx, void* phi, void* inv_k, void* d_eff);
+
 /* Canonical post-collision populations, 19 dense planes (see Conventions),
  * context precision, device memory.  Async. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, void* dev_dst);
@@ -201,6 +207,38 @@ lbm_status lbm_synchronize(lbm_ctx* ctx);
 void lbm_destroy(lbm_ctx* ctx);
 const char* lbm_status_string(lbm_status s);
 const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint.  The paper studies how the cell's current density
+ * responds to the GDL permeability, porosity and effective O2 diffusivity
+ * varied independently (Section 5); the adjoint gives the derivative of the
+ * mean current density J (lbm_obs.current_density, after nsteps steps from
+ * the equilibrium state) with respect to all three per-cell fields at once.
+ * It is the exact transpose of the discrete update (FP32 or FP64, as the
+ * context), with the derivative of |u| and of sqrt(1/K) taken as 0 where the
+ * argument is 0.  The context must hold the three fields as independent
+ * per-cell arrays (lbm_params.independent_fields = 1, or all three arrays
+ * given to lbm_set_params).
+ * --------------------------------------------------------------------------- */
+
+/* Device workspace for a checkpointed run: ceil(nsteps/every) checkpoints,
+ * a replay buffer of `every` states, two adjoint states, three gradient
+ * planes.  0 if invalid. */
+size_t lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int64_t nsteps, int32_t every);
+
+/* Initialise to equilibrium, run nsteps steps storing a checkpoint every
+ * `every` steps in dev_ws (caller-owned, kept until lbm_backward), and
+ * return J in *J_out.  Synchronous.  LBM_ERR_STATE if the context does not
+ * hold independent per-cell fields. */
+lbm_status lbm_forward_checkpointed(lbm_ctx* ctx, int64_t nsteps, int32_t every, void* dev_ws, size_t ws_bytes,
+                                    double* J_out);
+
+/* dJ times dJ/d(1/K), dJ/dphi, dJ/dD_eff of the preceding checkpointed run,
+ * written (not accumulated) into caller device arrays [ny][nx] (context
+ * precision; NULL skips one).  Replays each segment from its checkpoint and
+ * sweeps it in reverse.  Synchronous.  LBM_ERR_STATE without a matching
+ * lbm_forward_checkpointed (or after the state was changed since). */
+lbm_status lbm_backward(lbm_ctx* ctx, double dJ, void* grad_inv_k, void* grad_phi, void* grad_d_eff);
 
 /* ---------------------------------------------------------------------------
  * Batched parameter sweep.  The paper's results are sweeps over operating

@@ -255,6 +255,17 @@ class Model:
         # Eq. 10: b = 20 sqrt(3) alpha - 4 for each scalar lattice.
         self.b_T = 20.0 * _S3 * self.alpha - 4.0
         self.b_C = 20.0 * _S3 * self.d_eff - 4.0
+        # [R10] Scalar material of the outlet column: its nodes collide the
+        # copied scalar populations with the b and (rho c_p) of column nx-2,
+        # so the last two columns act as one medium for temperature and O2
+        # ("fully developed", Section 4).  With the node's own b the
+        # equilibrium fluxes (4 + b) X / 20 of the two columns differ and the
+        # outlet becomes a source or sink proportional to X (unstable for
+        # porosity fields); for layers uniform in x both choices coincide.
+        self.b_T_coll, self.b_C_coll, self.rhocp_coll = self.b_T, self.b_C, self.rhocp
+        if not geom.periodic_x:
+            last = lambda a: torch.cat([a[:, :-1], a[:, -2:-1]], dim=1)
+            self.b_T_coll, self.b_C_coll, self.rhocp_coll = last(self.b_T), last(self.b_C), last(self.rhocp)
         # Eq. 7 and Eq. 8 coefficients (dt = 1).
         self.F_phi = 0.143 * phi ** (-1.5)
         self.sqrt_inv_k = _safe_sqrt(inv_k)
@@ -375,7 +386,8 @@ class Model:
         temperature rise and c_in for O2 (Dirichlet, Section 4).
         Outlet (x = nx-1, all rows): f = f_eq(0, u_2) + (f_2 - f_eq(p_2, u_2)),
         with column 2 = nx-2; scalars copied from column nx-2 (fully
-        developed, Section 4) [R10].
+        developed, Section 4), and collided with column nx-2's scalar
+        material [R10].
         """
         if self.g.periodic_x:
             return pre
@@ -454,14 +466,14 @@ class Model:
 
         theta, c = gT.sum(0), gC.sum(0)
         if self.p.reaction:
-            s_c, S_T, _, _, _ = self.reaction(theta, c, self.rhocp)
+            s_c, S_T, _, _, _ = self.reaction(theta, c, self.rhocp_coll)
             zero = torch.zeros_like(theta)
             src_C = torch.where(self.is_cl, -s_c, zero)
             src_T = torch.where(self.is_cl, S_T, zero)
         else:
             src_C = src_T = torch.zeros_like(theta)
-        gT_post = self._collide_scalar(gT, theta, ux, uy, self.b_T, src_T)
-        gC_post = self._collide_scalar(gC, c, ux, uy, self.b_C, src_C)
+        gT_post = self._collide_scalar(gT, theta, ux, uy, self.b_T_coll, src_T)
+        gC_post = self._collide_scalar(gC, c, ux, uy, self.b_C_coll, src_C)
         return torch.cat([f_post, gT_post, gC_post])
 
     def _collide_scalar(self, g, X, ux, uy, b, src):
@@ -516,7 +528,7 @@ class Model:
         """
         pre = self.pre_collision(post)
         theta, c = pre[9:14].sum(0), pre[14:19].sum(0)
-        s_c, S_T, j_eff, Q, _ = self.reaction(theta, c, self.rhocp)
+        s_c, S_T, j_eff, Q, _ = self.reaction(theta, c, self.rhocp_coll)
         zero = torch.zeros_like(theta)
         cl = self.is_cl if self.p.reaction else torch.zeros_like(self.is_cl)
         s_c, S_T = torch.where(cl, s_c, zero), torch.where(cl, S_T, zero)

@@ -3,8 +3,9 @@
 The solver is the HIP library ``liblbmpem.so`` (C ABI: ``include/lbm_pem.h``);
 ``paper_2103_01444_amd.lbm`` is its thin Python binding.
 """
-from .lbm import (LBM_BODY_FORCE, LBM_NO_REACTION, LBM_PERIODIC_X, LBM_PERIODIC_Y, BatchedSweep, Cathode, LbmError,
+from .lbm import (LBM_BODY_FORCE, LBM_NO_REACTION, LBM_PERIODIC_X, LBM_PERIODIC_Y, BatchedSweep, Cathode,
+                  CurrentDensity, LbmError,
                   Params, default_params, load_library, params_from_workload)
 
-__all__ = ["BatchedSweep", "Cathode", "LbmError", "Params", "default_params", "load_library", "params_from_workload",
+__all__ = ["BatchedSweep", "Cathode", "CurrentDensity", "LbmError", "Params", "default_params", "load_library", "params_from_workload",
            "LBM_PERIODIC_X", "LBM_PERIODIC_Y", "LBM_BODY_FORCE", "LBM_NO_REACTION"]

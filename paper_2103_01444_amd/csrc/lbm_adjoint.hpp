@@ -1,0 +1,355 @@
+// Discrete adjoint of the coupled step (reverse mode, written by hand).
+//
+// The forward step is S' = C(P(S)): P pulls the populations (a permutation
+// with half-way bounce-back) and applies the inlet / outlet extrapolation
+// columns, C collides every node.  With lambda the adjoint of S', the
+// adjoint of S is obtained per node x by
+//   mu_x  = (dC_x / d pre_x)^T lambda_x                       (collision)
+//   mu_xp += (dB / d pre_xp)^T mu_b     for the boundary node b fed by xp
+//   lambda_new[source of pull (x, q)] = mu_x[q]                (push)
+// Every element of the state is pulled by exactly one node, so the push
+// writes every element of lambda_new once; boundary nodes, whose pulled
+// values the forward step discards, write zeros.  Each node accumulates
+// only its own gradient with respect to (porosity, 1/K, D_eff).
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+template <typename R>
+struct MatAdj {
+  R phi = R(0), invk = R(0), sqk = R(0), fphi = R(0), l0 = R(0), l1 = R(0), bT = R(0), bC = R(0), rhocp = R(0);
+};
+
+// Chain the adjoints of the derived material quantities to (phi, 1/K, D).
+template <typename R>
+__device__ __forceinline__ void material_adj(const Consts<R>& k, const Mat<R>& m, const MatAdj<R>& a, R& g_phi,
+                                             R& g_invk, R& g_d) {
+  const R phi = m.phi;
+  R lphi = a.phi, linvk = a.invk, lsqk = a.sqk, lfphi = a.fphi;
+  // l1 = phi fphi sqk / 2
+  lphi += a.l1 * m.fphi * m.sqk * R(0.5);
+  lfphi += a.l1 * phi * m.sqk * R(0.5);
+  lsqk += a.l1 * phi * m.fphi * R(0.5);
+  // l0 = 1/2 + phi nu invk / 4
+  lphi += a.l0 * k.nu * m.invk * R(0.25);
+  linvk += a.l0 * phi * k.nu * R(0.25);
+  // fphi = 0.143 phi^-1.5
+  lphi += lfphi * R(-1.5) * m.fphi / phi;
+  // sqk = sqrt(invk); derivative taken as 0 at invk = 0 (clear fluid)
+  if (m.sqk > R(0)) linvk += lsqk * R(0.5) / m.sqk;
+  // rhocp = phi rhocp_f + (1 - phi) rhocp_s; alpha (Eq. 19) -> bT = 20 sqrt3 alpha - 4
+  const R c20s3 = R(34.64101615137754587);
+  const R alpha = (m.bT + R(4)) / c20s3;
+  const R drc = k.rhocp_f - k.rhocp_s;
+  const R lalpha = a.bT * c20s3;
+  lphi += lalpha * ((k.k_f - k.k_s) * k.alpha_scale / m.rhocp - alpha * drc / m.rhocp);
+  lphi += a.rhocp * drc;
+  g_phi += lphi;
+  g_invk += linvk;
+  g_d += a.bC * c20s3;
+}
+
+// Adjoint of meq_shifted(p, ux, uy, phi) given the adjoint lm[1..8] of the moments.
+template <typename R>
+__device__ __forceinline__ void meq_adj(R p, R ux, R uy, R phi, const R (&lm)[9], R& lp, R& lux, R& luy, R& lphi) {
+  const R iphi = R(1) / phi;
+  const R u2 = ux * ux + uy * uy;
+  lp += R(6) * phi * lm[1] - R(9) * phi * lm[2];
+  lphi += R(6) * p * lm[1] - R(9) * p * lm[2] + (lm[2] - lm[1]) * R(3) * u2 * iphi * iphi -
+          (ux * ux - uy * uy) * iphi * iphi * lm[7] - ux * uy * iphi * iphi * lm[8];
+  const R a12 = R(6) * iphi * (lm[1] - lm[2]);
+  lux += a12 * ux + lm[3] - lm[4] + R(2) * ux * iphi * lm[7] + uy * iphi * lm[8];
+  luy += a12 * uy + lm[5] - lm[6] - R(2) * uy * iphi * lm[7] + ux * iphi * lm[8];
+}
+
+// Forward intermediates of flow_macros kept for its adjoint.
+template <typename R>
+struct MacroTape {
+  R vx, vy, vm, r, den, ux, uy, um, drag, s18, p, Fx, Fy;
+};
+
+template <typename R>
+__device__ __forceinline__ MacroTape<R> flow_macros_tape(const R (&f)[19], const Mat<R>& m, const Consts<R>& k) {
+  MacroTape<R> t;
+  t.vx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  t.vy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  if (k.flags & F_BODY_FORCE) {
+    t.vx += R(0.5) * m.phi * k.ax;
+    t.vy += R(0.5) * m.phi * k.ay;
+  }
+  t.vm = dsqrt(t.vx * t.vx + t.vy * t.vy);
+  t.r = dsqrt(m.l0 * m.l0 + m.l1 * t.vm);
+  t.den = m.l0 + t.r;
+  t.ux = t.vx / t.den;
+  t.uy = t.vy / t.den;
+  const R u2 = t.ux * t.ux + t.uy * t.uy;
+  t.um = dsqrt(u2);
+  t.drag = m.phi * (k.nu * m.invk + m.fphi * m.sqk * t.um);
+  t.Fx = -t.drag * t.ux;
+  t.Fy = -t.drag * t.uy;
+  if (k.flags & F_BODY_FORCE) {
+    t.Fx += m.phi * k.ax;
+    t.Fy += m.phi * k.ay;
+  }
+  t.s18 = f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const R iphi = R(1) / m.phi;
+  t.p = R(0.6) * iphi * t.s18 - R(0.4) * u2 * iphi * iphi;
+  return t;
+}
+
+// Adjoint of flow_macros: given the adjoints of (ux, uy, p, Fx, Fy), add the
+// adjoints of the flow populations to lf[0..8] and of the material to ma.
+template <typename R>
+__device__ __forceinline__ void flow_macros_adj(const MacroTape<R>& t, const Mat<R>& m, const Consts<R>& k, R lux,
+                                                R luy, R lp, R lFx, R lFy, R* lf, MatAdj<R>& ma) {
+  const R iphi = R(1) / m.phi;
+  const R u2 = t.ux * t.ux + t.uy * t.uy;
+  // p = 0.6 iphi s18 - 0.4 u2 iphi^2
+  const R ls18 = R(0.6) * iphi * lp;
+  R lu2 = R(-0.4) * iphi * iphi * lp;
+  R liphi = (R(0.6) * t.s18 - R(0.8) * u2 * iphi) * lp;
+  // F = -drag u (+ phi a)
+  if (k.flags & F_BODY_FORCE) ma.phi += k.ax * lFx + k.ay * lFy;
+  const R ldrag = -(t.ux * lFx + t.uy * lFy);
+  lux += -t.drag * lFx;
+  luy += -t.drag * lFy;
+  // drag = phi (nu invk + fphi sqk um)
+  ma.phi += (k.nu * m.invk + m.fphi * m.sqk * t.um) * ldrag;
+  ma.invk += m.phi * k.nu * ldrag;
+  ma.fphi += m.phi * m.sqk * t.um * ldrag;
+  ma.sqk += m.phi * m.fphi * t.um * ldrag;
+  const R lum = m.phi * m.fphi * m.sqk * ldrag;
+  if (t.um > R(0)) lu2 += lum * R(0.5) / t.um;
+  lux += R(2) * t.ux * lu2;
+  luy += R(2) * t.uy * lu2;
+  ma.phi += -iphi * iphi * liphi;
+  // u = v / den, den = l0 + r, r = sqrt(l0^2 + l1 vm)
+  R lvx = lux / t.den, lvy = luy / t.den;
+  const R lden = -(t.ux * lux + t.uy * luy) / t.den;
+  ma.l0 += lden + lden * m.l0 / t.r;
+  ma.l1 += lden * t.vm * R(0.5) / t.r;
+  const R lvm = lden * m.l1 * R(0.5) / t.r;
+  if (t.vm > R(0)) {
+    lvx += lvm * t.vx / t.vm;
+    lvy += lvm * t.vy / t.vm;
+  }
+  if (k.flags & F_BODY_FORCE) ma.phi += R(0.5) * (k.ax * lvx + k.ay * lvy);
+  // v = sum e f, s18 = sum_{1..8} f
+  lf[1] += lvx + ls18;
+  lf[2] += lvy + ls18;
+  lf[3] += -lvx + ls18;
+  lf[4] += -lvy + ls18;
+  lf[5] += lvx + lvy + ls18;
+  lf[6] += -lvx + lvy + ls18;
+  lf[7] += -lvx - lvy + ls18;
+  lf[8] += lvx - lvy + ls18;
+}
+
+// (M^T x)_i = sum_k M[k][i] x_k  (inv_moments9 applied to x scaled by diag(M M^T)).
+template <typename R>
+__device__ __forceinline__ void mt_times(const R (&x)[9], R* out) {
+  R s[9];
+  const R d[9] = {R(9), R(36), R(36), R(6), R(12), R(6), R(12), R(4), R(4)};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s[i] = x[i] * d[i];
+  inv_moments9(s, out);
+}
+
+// M^{-T} a = (M a) / diag(M M^T).
+template <typename R>
+__device__ __forceinline__ void minvt_times(const R* a, R (&out)[9]) {
+  R f[19];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = a[i];
+  moments9(f, out);
+  const R d[9] = {R(9), R(36), R(36), R(6), R(12), R(6), R(12), R(4), R(4)};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) out[i] /= d[i];
+}
+
+// Adjoint of add_geq(X, ux, uy, b, sgn, g): given lg (adjoint of g) add the
+// adjoints of X, ux, uy, b.
+template <typename R>
+__device__ __forceinline__ void geq_adj(R X, R ux, R uy, R b, R sgn, const R* lg, R& lX, R& lux, R& luy, R& lb) {
+  const R n0 = (lg[0] + lg[1] + lg[2] + lg[3] + lg[4]) * R(0.2);
+  const R n1 = (lg[1] - lg[3]) * R(0.5);
+  const R n2 = (lg[2] - lg[4]) * R(0.5);
+  const R n3 = (R(-4) * lg[0] + lg[1] + lg[2] + lg[3] + lg[4]) * R(0.05);
+  lX += sgn * (n0 + ux * n1 + uy * n2 + b * n3);
+  lux += sgn * X * n1;
+  luy += sgn * X * n2;
+  lb += sgn * X * n3;
+}
+
+// Reaction sensitivities: ds_c/dc, ds_c/dtheta, and S_T's.
+template <typename R>
+struct ReactAdj {
+  R s_c, S_T, ehs, dsc_dc, dsc_dth;
+};
+
+template <typename R>
+__device__ __forceinline__ ReactAdj<R> reaction_tape(R theta, R c, R rhocp, const Consts<R>& k) {
+  const R T = k.T_in + theta;
+  const R iT = R(1) / T;
+  const R eta = k.V_op - (k.U0_slope * T + k.U0_icept);
+  const R kappa = exp(k.ln_k0 - k.E_over_R * (iT - k.inv_T_arrh) - k.aF_over_R * eta * iT);
+  const R em = expm1(-kappa);
+  ReactAdj<R> r;
+  r.s_c = -c * em;
+  r.ehs = eta + T * k.U0_slope;
+  r.S_T = k.four_f_cref * r.s_c * r.ehs / rhocp;
+  // dE/dT of the exponent E = ln_k0 - E/R (1/T - 1/T0) - aF/R eta / T, with
+  // deta/dT = -U0_slope.
+  const R dE = k.E_over_R * iT * iT + k.aF_over_R * k.U0_slope * iT + k.aF_over_R * eta * iT * iT;
+  r.dsc_dc = -em;
+  r.dsc_dth = c * (em + R(1)) * kappa * dE;
+  return r;
+}
+
+// Collision adjoint of one node.  In: pre-collision f, material, adjoint of
+// the post-collision populations la.  Out: adjoint of the pre-collision
+// populations mu; material adjoints accumulated in ma.
+template <typename R>
+__device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, const Consts<R>& k, bool cl,
+                                            const R (&la)[19], R (&mu)[19], MatAdj<R>& ma) {
+  const MacroTape<R> t = flow_macros_tape(f, mt, k);
+  R lux = R(0), luy = R(0);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) mu[i] = R(0);
+
+  // ---- scalars (reverse of the D2Q5 collisions and the CL source) ----
+  const R th = f[9] + f[10] + f[11] + f[12] + f[13];
+  const R c = f[14] + f[15] + f[16] + f[17] + f[18];
+  ReactAdj<R> rx{};
+  if (cl) rx = reaction_tape(th, c, mt.rhocp, k);
+  const R srcT = cl ? rx.S_T : R(0), srcC = cl ? -rx.s_c : R(0);
+  const R q1 = R(1.2679491924311228);
+  const R q3 = R(0.9282032302755092);
+  R lsrc[2], lX[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const R* a = la + 9 + 5 * s;
+    const R* g = f + 9 + 5 * s;
+    const R X = s == 0 ? th : c;
+    const R b = s == 0 ? mt.bT : mt.bC;
+    const R src = s == 0 ? srcT : srcC;
+    // g* = N^-1 n*: adjoint of n* is (N a) / (5, 2, 2, 20, 4)
+    const R ln0 = (a[0] + a[1] + a[2] + a[3] + a[4]) * R(0.2);
+    const R ln1 = (a[1] - a[3]) * R(0.5);
+    const R ln2 = (a[2] - a[4]) * R(0.5);
+    const R ln3 = (R(-4) * a[0] + a[1] + a[2] + a[3] + a[4]) * R(0.05);
+    const R ln4 = (a[1] - a[2] + a[3] - a[4]) * R(0.25);
+    lX[s] = ln0 + q1 * t.ux * ln1 + q1 * t.uy * ln2 + q3 * b * ln3;
+    lsrc[s] = ln0 + b * ln3;
+    const R lb = q3 * X * ln3 + src * ln3;
+    if (s == 0) ma.bT += lb; else ma.bC += lb;
+    lux += q1 * X * ln1;
+    luy += q1 * X * ln2;
+    const R m1 = (R(1) - q1) * ln1, m2 = (R(1) - q1) * ln2, m3 = (R(1) - q3) * ln3, m4 = (R(1) - q3) * ln4;
+    R* o = mu + 9 + 5 * s;
+    o[0] = R(-4) * m3;
+    o[1] = m1 + m3 + m4;
+    o[2] = m2 + m3 - m4;
+    o[3] = -m1 + m3 + m4;
+    o[4] = -m2 + m3 - m4;
+    (void)g;
+  }
+  if (cl) {
+    // src_T = S_T(theta, c, rhocp), src_C = -s_c(theta, c)
+    const R lST = lsrc[0], lSC = lsrc[1];
+    const R lsc = -lSC + k.four_f_cref * rx.ehs / mt.rhocp * lST;
+    ma.rhocp += -rx.S_T / mt.rhocp * lST;
+    lX[1] += rx.dsc_dc * lsc;
+    lX[0] += rx.dsc_dth * lsc;
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    mu[9 + i] += lX[0];
+    mu[14 + i] += lX[1];
+  }
+
+  // ---- flow (reverse of the MRT collision with porous forcing) ----
+  R lms[9];
+  minvt_times(la, lms);  // adjoint of m*
+  const R se = k.s_e, sq = k.s_q;
+  const R s[9] = {se, se, se, R(0), sq, R(0), sq, se, se};
+  R lm[9], lme[9], lG[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    lm[i] = (R(1) - s[i]) * lms[i];
+    lme[i] = s[i] * lms[i];
+    lG[i] = (R(1) - R(0.5) * s[i]) * lms[i];
+  }
+  lme[0] = R(0);  // the density-moment equilibrium is a constant
+  const R iphi = R(1) / mt.phi;
+  const R uF = t.ux * t.Fx + t.uy * t.Fy;
+  // G(u, F, phi)
+  const R luF = R(6) * iphi * (lG[1] - lG[2]);
+  R lFx = lG[3] - lG[4] + R(2) * t.ux * iphi * lG[7] + t.uy * iphi * lG[8] + t.ux * luF;
+  R lFy = lG[5] - lG[6] - R(2) * t.uy * iphi * lG[7] + t.ux * iphi * lG[8] + t.uy * luF;
+  lux += R(2) * t.Fx * iphi * lG[7] + t.Fy * iphi * lG[8] + t.Fx * luF;
+  luy += R(-2) * t.Fy * iphi * lG[7] + t.Fx * iphi * lG[8] + t.Fy * luF;
+  const R liphi_G = R(6) * uF * (lG[1] - lG[2]) + R(2) * (t.ux * t.Fx - t.uy * t.Fy) * lG[7] +
+                    (t.ux * t.Fy + t.uy * t.Fx) * lG[8];
+  ma.phi += -iphi * iphi * liphi_G;
+  // meq(p, u, phi)
+  R lp = R(0);
+  meq_adj(t.p, t.ux, t.uy, mt.phi, lme, lp, lux, luy, ma.phi);
+  // m = M f
+  R lfm[9];
+  mt_times(lm, lfm);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) mu[i] += lfm[i];
+  flow_macros_adj(t, mt, k, lux, luy, lp, lFx, lFy, mu, ma);
+}
+
+// Adjoint of the boundary-column extrapolation of node b fed by node xp.
+// pre_xp: pulled populations of xp; mu_b: adjoint of the boundary node's
+// pre-collision populations.  Adds to mu_xp and to the material adjoints of
+// xp (maxp) and of b (mab).
+template <typename R>
+__device__ __forceinline__ void boundary_adj(const R (&pre_xp)[19], const Mat<R>& mxp, const Mat<R>& mb,
+                                             const Consts<R>& k, bool inlet, R ubx, R uby, const R (&mu_b)[19],
+                                             R (&mu_xp)[19], MatAdj<R>& maxp, MatAdj<R>& mab) {
+  const MacroTape<R> t = flow_macros_tape(pre_xp, mxp, k);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) mu_xp[i] += mu_b[i];  // identity part (scalars at the outlet: a copy)
+  R ldm[9];
+  minvt_times(mu_b, ldm);
+  ldm[0] = R(0);
+  R lp1 = R(0), lux1 = R(0), luy1 = R(0);
+  // + meq(pb, ub; phi_b): inlet pb = p1 (ub fixed); outlet pb = 0, ub = u1.
+  R dumx = R(0), dumy = R(0);
+  if (inlet) {
+    meq_adj(t.p, ubx, uby, mb.phi, ldm, lp1, dumx, dumy, mab.phi);
+  } else {
+    R dp = R(0);
+    meq_adj(R(0), t.ux, t.uy, mb.phi, ldm, dp, lux1, luy1, mab.phi);
+  }
+  // - meq(p1, u1; phi_xp)
+  R nldm[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) nldm[i] = -ldm[i];
+  meq_adj(t.p, t.ux, t.uy, mxp.phi, nldm, lp1, lux1, luy1, maxp.phi);
+  if (inlet) {
+    const R th1 = pre_xp[9] + pre_xp[10] + pre_xp[11] + pre_xp[12] + pre_xp[13];
+    const R c1 = pre_xp[14] + pre_xp[15] + pre_xp[16] + pre_xp[17] + pre_xp[18];
+    R lth1 = R(0), lc1 = R(0), dX = R(0);
+    // + geq(0, ub; bT_b): no dependence.  - geq(theta1, u1; bT_xp)
+    geq_adj(th1, t.ux, t.uy, mxp.bT, R(-1), mu_b + 9, lth1, lux1, luy1, maxp.bT);
+    // + geq(c_in, ub; bC_b)
+    geq_adj(k.c_in, ubx, uby, mb.bC, R(1), mu_b + 14, dX, dumx, dumy, mab.bC);
+    // - geq(c1, u1; bC_xp)
+    geq_adj(c1, t.ux, t.uy, mxp.bC, R(-1), mu_b + 14, lc1, lux1, luy1, maxp.bC);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      mu_xp[9 + i] += lth1;
+      mu_xp[14 + i] += lc1;
+    }
+  }
+  flow_macros_adj(t, mxp, k, lux1, luy1, lp1, R(0), R(0), mu_xp, maxp);
+}
+
+}  // namespace lbm

@@ -1,0 +1,184 @@
+// Kernels of the reverse sweep (three per-cell fields: porosity, 1/K, D_eff).
+#pragma once
+
+#include "lbm_adjoint.hpp"
+#include "lbm_kernels2d.hpp"
+
+namespace lbm {
+
+// Adjoint of the observable J = mean current density on the pre-collision
+// populations: for CL nodes dJ/dc and dJ/dtheta on every scalar population.
+template <typename R>
+__device__ __forceinline__ void seed_mu(const R (&pre)[19], const Mat<R>& mt, const Consts<R>& k, bool cl, R w,
+                                        R (&mu)[19]) {
+#pragma unroll
+  for (int i = 0; i < 19; ++i) mu[i] = R(0);
+  if (!cl) return;
+  const R th = pre[9] + pre[10] + pre[11] + pre[12] + pre[13];
+  const R c = pre[14] + pre[15] + pre[16] + pre[17] + pre[18];
+  const ReactAdj<R> r = reaction_tape(th, c, mt.rhocp, k);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    mu[9 + i] = w * r.dsc_dth;
+    mu[14 + i] = w * r.dsc_dc;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_node(const R* __restrict__ a, const Consts<R>& k, int x, int y, R (&v)[19]) {
+  const int o = y * k.pitch + x;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) v[q] = a[q * k.plane + o];
+}
+
+// Adjoint of node b's collision (or of J when SEED) given b's pre-collision populations.
+template <typename R, bool SEED>
+__device__ __forceinline__ void node_mu(const R (&pre)[19], const Mat<R>& mt, const Consts<R>& k, bool cl,
+                                        const R* __restrict__ lam_in, int x, int y, R w, R (&mu)[19],
+                                        MatAdj<R>& ma) {
+  if constexpr (SEED) {
+    seed_mu(pre, mt, k, cl, w, mu);
+  } else {
+    R la[19];
+    load_node(lam_in, k, x, y, la);
+    collide_adj(pre, mt, k, cl, la, mu, ma);
+  }
+}
+
+// One reverse step: lam_out = (dS'/dS)^T lam_in at the state S, gradients
+// accumulated into grad (planes phi, 1/K, D_eff).  SEED: lam_out = dJ/dS
+// (times w = dJ dx / nx * 4 F C_ref / dt), no lam_in.
+template <typename R, bool SEED>
+__global__ __launch_bounds__(kBlock) void k_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
+                                                     R* __restrict__ lam_out, R* __restrict__ grad,
+                                                     const R* __restrict__ phi_f, const R* __restrict__ invk_f,
+                                                     const R* __restrict__ d_f, Consts<R> k, R w) {
+  int bx, by;
+  xcd_tile(gridDim.x, gridDim.y, bx, by);
+  const int x = bx * kBlock + threadIdx.x;
+  const int y = by;
+  if (x >= k.nx) return;
+  const bool open = !(k.flags & F_PERIODIC_X);
+  const bool react = !(k.flags & F_NO_REACTION);
+  const bool cl = react && y >= k.y_cl0;
+  const bool inlet = open && x == 0 && y < k.ny_ch;
+  const bool outlet = open && x == k.nx - 1;
+  const int xp = inlet ? 1 : (outlet ? k.nx - 2 : x);
+
+  R p[19];
+  pull(S, k, xp, y, p);
+  const Mat<R> mxp = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xp, y);
+  MatAdj<R> ma{};
+  R mu[19];
+  const int o = y * k.pitch + x;
+
+  if (inlet || outlet) {
+    // Boundary node: own collision adjoint and the material part of its
+    // extrapolation; its pulled sources were never read, so their adjoint is 0.
+    Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y);
+    R pre[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) pre[q] = p[q];
+    boundary_column(pre, k, y, inlet, mxp, mb);
+    if (outlet) outlet_scalar_material(mb, mxp);
+    node_mu<R, SEED>(pre, mb, k, cl, lam_in, x, y, w, mu, ma);
+    R dmu[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) dmu[q] = R(0);
+    MatAdj<R> dmaxp{};
+    boundary_adj(p, mxp, mb, k, inlet, inlet ? inlet_velocity(k, y) : R(0), R(0), mu, dmu, dmaxp, ma);
+    if (outlet) {  // the outlet's scalar material is column nx-2's; that thread takes these terms
+      ma.bT = R(0);
+      ma.bC = R(0);
+      ma.rhocp = R(0);
+    }
+    R g0 = R(0), g1 = R(0), g2 = R(0);
+    material_adj(k, mb, ma, g0, g1, g2);
+    grad[o] += g0;
+    grad[k.plane + o] += g1;
+    grad[2 * k.plane + o] += g2;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) mu[q] = R(0);
+  } else {
+    node_mu<R, SEED>(p, mxp, k, cl, lam_in, x, y, w, mu, ma);
+    // Columns feeding a boundary node add that node's adjoint through the
+    // extrapolation (recomputed here so that every node writes only its own data).
+    if (open && x == 1 && y < k.ny_ch) {
+      const Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, 0, y);
+      R pre[19];
+#pragma unroll
+      for (int q = 0; q < 19; ++q) pre[q] = p[q];
+      boundary_column(pre, k, y, true, mxp, mb);
+      R mub[19];
+      MatAdj<R> dmab{};
+      node_mu<R, SEED>(pre, mb, k, cl, lam_in, 0, y, w, mub, dmab);
+      MatAdj<R> dmab2{};
+      boundary_adj(p, mxp, mb, k, true, inlet_velocity(k, y), R(0), mub, mu, ma, dmab2);
+    }
+    if (open && x == k.nx - 2) {
+      Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, k.nx - 1, y);
+      R pre[19];
+#pragma unroll
+      for (int q = 0; q < 19; ++q) pre[q] = p[q];
+      boundary_column(pre, k, y, false, mxp, mb);
+      outlet_scalar_material(mb, mxp);
+      R mub[19];
+      MatAdj<R> dmab{};
+      node_mu<R, SEED>(pre, mb, k, cl, lam_in, k.nx - 1, y, w, mub, dmab);
+      ma.bT += dmab.bT;  // the outlet node collides with this column's scalar material
+      ma.bC += dmab.bC;
+      ma.rhocp += dmab.rhocp;
+      MatAdj<R> dmab2{};
+      boundary_adj(p, mxp, mb, k, false, R(0), R(0), mub, mu, ma, dmab2);
+    }
+    R g0 = R(0), g1 = R(0), g2 = R(0);
+    material_adj(k, mxp, ma, g0, g1, g2);
+    grad[o] += g0;
+    grad[k.plane + o] += g1;
+    grad[2 * k.plane + o] += g2;
+  }
+  // Push: the adjoint of the pulled element (x - e_q, q) (or of the
+  // bounced-back (x, opp q)) is mu[q].
+  const bool px = k.flags & F_PERIODIC_X;
+  const bool py = k.flags & F_PERIODIC_Y;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    int xs = x - EX[q];
+    int ys = y - EY[q];
+    if (px) xs = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
+    if (py) ys = ys < 0 ? ys + k.ny : (ys >= k.ny ? ys - k.ny : ys);
+    const bool in = (unsigned)xs < (unsigned)k.nx && (unsigned)ys < (unsigned)k.ny;
+    const int off = in ? (q * k.plane + ys * k.pitch + xs) : (OPP[q] * k.plane + y * k.pitch + x);
+    lam_out[off] = mu[q];
+  }
+}
+
+// Gradient through the initial state: the O2 equilibrium at rest depends on
+// b_C = 20 sqrt(3) D - 4 (Eq. 10).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_adj_init(const R* __restrict__ lam0, R* __restrict__ grad, Consts<R> k) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= k.nx) return;
+  const int o = y * k.pitch + x;
+  const R l0 = lam0[14 * k.plane + o];
+  const R l14 = lam0[15 * k.plane + o] + lam0[16 * k.plane + o] + lam0[17 * k.plane + o] + lam0[18 * k.plane + o];
+  grad[2 * k.plane + o] += R(34.64101615137754587) * k.c_in * (-l0 * R(0.2) + l14 * R(0.05));
+}
+
+// Pitched plane -> dense [ny][nx] caller array.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_unpitch(const R* __restrict__ src, R* __restrict__ dst, int nx, int pitch) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= nx) return;
+  dst[(size_t)y * nx + x] = src[y * pitch + x];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fill(R* __restrict__ dst, int64_t n, R v) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+
+}  // namespace lbm

@@ -76,6 +76,12 @@ struct lbm_ctx {
   Consts<double> kd{};
   Derived d;
   std::string err;
+  // checkpointed forward run held for lbm_backward
+  char* adj_ws = nullptr;
+  int64_t adj_nsteps = 0;
+  int32_t adj_every = 0;
+  int64_t adj_step = -1;
+  bool adj_ready = false;
 
   void* state(int i) { return ws + L.off_state[i]; }
   void* mat_plane(int i) { return ws + L.off_mat + size_t(i) * L.plane * L.esize; }
@@ -385,6 +391,7 @@ lbm_status lbm_create(const lbm_geometry* g, void* dev_ws, size_t ws_bytes, void
 lbm_status lbm_set_params(lbm_ctx* c, const lbm_params* p, const void* phi, const void* inv_k, const void* d_eff) {
   if (!c || !p) return LBM_ERR_INVALID_ARG;
   c->params_set = false;
+  c->adj_ready = false;
   return c->g.precision == 64 ? set_params_t<double>(c, p, phi, inv_k, d_eff)
                               : set_params_t<float>(c, p, phi, inv_k, d_eff);
 }
@@ -420,6 +427,34 @@ lbm_status lbm_get_fields(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void
   return check_launch(c, "fields");
 }
 
+lbm_status lbm_get_material(lbm_ctx* c, void* phi, void* inv_k, void* d_eff) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  if (c->g.precision == 64) {
+    const MatPtrs<double> m = mat_ptrs<double>(c);
+    auto* a = static_cast<double*>(phi);
+    auto* b = static_cast<double*>(inv_k);
+    auto* d = static_cast<double*>(d_eff);
+    switch (c->mat) {
+      case MAT_LAYERED: hipLaunchKernelGGL((k_material<double, MAT_LAYERED>), grid, dim3(kBlock), 0, c->stream, m.phi, m.invk, m.d, c->kd, a, b, d); break;
+      case MAT_PHI: hipLaunchKernelGGL((k_material<double, MAT_PHI>), grid, dim3(kBlock), 0, c->stream, m.phi, m.invk, m.d, c->kd, a, b, d); break;
+      default: hipLaunchKernelGGL((k_material<double, MAT_FULL>), grid, dim3(kBlock), 0, c->stream, m.phi, m.invk, m.d, c->kd, a, b, d); break;
+    }
+  } else {
+    const MatPtrs<float> m = mat_ptrs<float>(c);
+    auto* a = static_cast<float*>(phi);
+    auto* b = static_cast<float*>(inv_k);
+    auto* d = static_cast<float*>(d_eff);
+    switch (c->mat) {
+      case MAT_LAYERED: hipLaunchKernelGGL((k_material<float, MAT_LAYERED>), grid, dim3(kBlock), 0, c->stream, m.phi, m.invk, m.d, c->kf, a, b, d); break;
+      case MAT_PHI: hipLaunchKernelGGL((k_material<float, MAT_PHI>), grid, dim3(kBlock), 0, c->stream, m.phi, m.invk, m.d, c->kf, a, b, d); break;
+      default: hipLaunchKernelGGL((k_material<float, MAT_FULL>), grid, dim3(kBlock), 0, c->stream, m.phi, m.invk, m.d, c->kf, a, b, d); break;
+    }
+  }
+  return check_launch(c, "get_material");
+}
+
 lbm_status lbm_get_populations(lbm_ctx* c, void* dst) {
   if (!c || !dst) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
@@ -444,6 +479,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const void* src, int64_t step) {
     hipLaunchKernelGGL(k_import<float>, grid, dim3(kBlock), 0, c->stream, static_cast<const float*>(src),
                        static_cast<float*>(c->state(c->cur)), c->kf);
   c->step = step;
+  c->adj_ready = false;
   return check_launch(c, "set_populations");
 }
 
@@ -465,6 +501,7 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* src, int64_t step) {
   if (hipMemcpyAsync(c->state(c->cur), src, lbm_state_bytes(c), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return fail(c, LBM_ERR_DEVICE, "load_state copy failed");
   c->step = step;
+  c->adj_ready = false;
   return LBM_OK;
 }
 
@@ -492,5 +529,139 @@ const char* lbm_status_string(lbm_status s) {
 }
 
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Checkpointed forward run and discrete adjoint (lbm_forward_checkpointed,
+// lbm_backward).
+// ---------------------------------------------------------------------------
+#include "lbm_adjoint_kernels.hpp"
+
+namespace {
+
+struct AdjLayout {
+  size_t state = 0;  // aligned bytes of one state
+  int nck = 0;
+  size_t off_ck = 0, off_replay = 0, off_lam = 0, off_grad = 0, total = 0;
+};
+
+AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int32_t every) {
+  AdjLayout A;
+  A.state = align_up(size_t(19) * c->L.plane * c->L.esize);
+  A.nck = int((nsteps + every - 1) / every);
+  size_t o = 0;
+  A.off_ck = o;
+  o += size_t(A.nck) * A.state;
+  A.off_replay = o;
+  o += size_t(every) * A.state;
+  A.off_lam = o;
+  o += 2 * A.state;
+  A.off_grad = o;
+  o += align_up(size_t(3) * c->L.plane * c->L.esize);
+  A.total = o;
+  return A;
+}
+
+template <typename R>
+void launch_one_step(lbm_ctx* c, const void* src, void* dst) {
+  const MatPtrs<R> m = mat_ptrs<R>(c);
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  hipLaunchKernelGGL((k_step<R, MAT_FULL>), grid, dim3(kBlock), 0, c->stream, static_cast<const R*>(src),
+                     static_cast<R*>(dst), m.phi, m.invk, m.d, consts<R>(c));
+}
+
+template <typename R>
+lbm_status backward_t(lbm_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_d) {
+  const AdjLayout A = adj_layout(c, c->adj_nsteps, c->adj_every);
+  char* ws = c->adj_ws;
+  const MatPtrs<R> m = mat_ptrs<R>(c);
+  const Consts<R> k = consts<R>(c);
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  R* grad = reinterpret_cast<R*>(ws + A.off_grad);
+  R* lam[2] = {reinterpret_cast<R*>(ws + A.off_lam), reinterpret_cast<R*>(ws + A.off_lam + A.state)};
+  const int64_t ngrad = int64_t(3) * c->L.plane;
+  hipLaunchKernelGGL(k_fill<R>, dim3(unsigned((ngrad + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, grad,
+                     ngrad, R(0));
+  // Seed: adjoint of J = current density on the final state.
+  const lbm_params& p = c->p;
+  const double w = dJ * c->d.dx / c->g.nx * 4.0 * p.faraday * p.C_ref / c->d.dt;
+  hipLaunchKernelGGL((k_adj_step<R, true>), grid, dim3(kBlock), 0, c->stream,
+                     static_cast<const R*>(c->state(c->cur)), static_cast<const R*>(nullptr), lam[0], grad, m.phi,
+                     m.invk, m.d, k, R(w));
+  int cur = 0;
+  for (int seg = A.nck - 1; seg >= 0; --seg) {
+    const int64_t start = int64_t(seg) * c->adj_every;
+    const int len = int(std::min<int64_t>(c->adj_every, c->adj_nsteps - start));
+    char* replay = ws + A.off_replay;
+    if (hipMemcpyAsync(replay, ws + A.off_ck + size_t(seg) * A.state, A.state, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "replay restore failed");
+    for (int j = 1; j < len; ++j)
+      launch_one_step<R>(c, replay + size_t(j - 1) * A.state, replay + size_t(j) * A.state);
+    for (int j = len - 1; j >= 0; --j) {
+      hipLaunchKernelGGL((k_adj_step<R, false>), grid, dim3(kBlock), 0, c->stream,
+                         reinterpret_cast<const R*>(replay + size_t(j) * A.state), lam[cur], lam[cur ^ 1], grad,
+                         m.phi, m.invk, m.d, k, R(0));
+      cur ^= 1;
+    }
+  }
+  hipLaunchKernelGGL(k_adj_init<R>, grid, dim3(kBlock), 0, c->stream, lam[cur], grad, k);
+  void* outs[3] = {g_phi, g_invk, g_d};
+  for (int i = 0; i < 3; ++i)
+    if (outs[i])
+      hipLaunchKernelGGL(k_unpitch<R>, grid, dim3(kBlock), 0, c->stream, grad + size_t(i) * c->L.plane,
+                         static_cast<R*>(outs[i]), c->g.nx, c->L.pitch);
+  if (lbm_status s = check_launch(c, "backward"); s != LBM_OK) return s;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "backward sync failed");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_adjoint_workspace_bytes(const lbm_ctx* c, int64_t nsteps, int32_t every) {
+  if (!c || nsteps < 1 || every < 1) return 0;
+  return adj_layout(c, nsteps, every).total;
+}
+
+lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, void* dev_ws, size_t ws_bytes,
+                                    double* J_out) {
+  if (!c || nsteps < 1 || every < 1 || !dev_ws) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  if (c->mat != MAT_FULL)
+    return fail(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
+  const AdjLayout A = adj_layout(c, nsteps, every);
+  if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign != 0)
+    return fail(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");
+  c->adj_ready = false;
+  if (lbm_status s = lbm_init_equilibrium(c); s != LBM_OK) return s;
+  c->adj_ws = static_cast<char*>(dev_ws);
+  c->adj_nsteps = nsteps;
+  c->adj_every = every;
+  const size_t sb = size_t(19) * c->L.plane * c->L.esize;
+  for (int seg = 0; seg < A.nck; ++seg) {
+    if (hipMemcpyAsync(c->adj_ws + A.off_ck + size_t(seg) * A.state, c->state(c->cur), sb, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "checkpoint copy failed");
+    const int64_t n = std::min<int64_t>(every, nsteps - int64_t(seg) * every);
+    if (lbm_status s = lbm_step(c, n); s != LBM_OK) return s;
+  }
+  lbm_obs o{};
+  if (lbm_status s = lbm_observables(c, &o, nullptr, nullptr, nullptr); s != LBM_OK) return s;
+  if (J_out) *J_out = o.current_density;
+  c->adj_step = c->step;
+  c->adj_ready = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_backward(lbm_ctx* c, double dJ, void* grad_inv_k, void* grad_phi, void* grad_d_eff) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->adj_ready || c->adj_step != c->step)
+    return fail(c, LBM_ERR_STATE, "lbm_backward needs a preceding lbm_forward_checkpointed on the same state");
+  return c->g.precision == 64 ? backward_t<double>(c, dJ, grad_inv_k, grad_phi, grad_d_eff)
+                              : backward_t<float>(c, dJ, grad_inv_k, grad_phi, grad_d_eff);
+}
 
 }  // extern "C"

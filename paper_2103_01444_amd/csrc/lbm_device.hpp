@@ -61,10 +61,9 @@ __device__ __forceinline__ R dsqrt(R a) { return sqrt(a); }
 // permeability (Eq. 7) and Bruggeman or ratio diffusivity (Eq. 18).  Full:
 // three given fields.  Thermal diffusivity from Eq. 19 in every mode.
 template <typename R, int MAT>
-__device__ __forceinline__ Mat<R> material(const Consts<R>& k, const R* __restrict__ phi_f,
-                                           const R* __restrict__ invk_f,
-                                           const R* __restrict__ d_f, int x, int y) {
-  R phi, invk, d;
+__device__ __forceinline__ void base_fields(const Consts<R>& k, const R* __restrict__ phi_f,
+                                            const R* __restrict__ invk_f, const R* __restrict__ d_f, int x, int y,
+                                            R& phi, R& invk, R& d) {
   const bool porous = y >= k.ny_ch;
   if constexpr (MAT == MAT_LAYERED) {
     phi = porous ? k.phi_gdl : R(1);
@@ -82,6 +81,14 @@ __device__ __forceinline__ Mat<R> material(const Consts<R>& k, const R* __restri
       d = d_f[cell];
     }
   }
+}
+
+template <typename R, int MAT>
+__device__ __forceinline__ Mat<R> material(const Consts<R>& k, const R* __restrict__ phi_f,
+                                           const R* __restrict__ invk_f,
+                                           const R* __restrict__ d_f, int x, int y) {
+  R phi, invk, d;
+  base_fields<R, MAT>(k, phi_f, invk_f, d_f, x, y, phi, invk, d);
   Mat<R> m;
   m.phi = phi;
   m.invk = invk;
@@ -225,6 +232,12 @@ __device__ __forceinline__ void add_geq(R X, R ux, R uy, R b, R sgn, R* g) {
 // inlet (x = 0, channel rows) and outlet (x = nx-1) by non-equilibrium
 // extrapolation from columns 1 and nx-2 (Section 4 boundary conditions).
 // Returns the node's own material.
+template <typename R>
+__device__ __forceinline__ void boundary_column(R (&f)[19], const Consts<R>& k, int y, bool inlet, const Mat<R>& mp,
+                                                const Mat<R>& mb);
+template <typename R>
+__device__ __forceinline__ void outlet_scalar_material(Mat<R>& mb, const Mat<R>& mp);
+
 template <typename R, int MAT>
 __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const Consts<R>& k,
                                                 const R* __restrict__ phi_f,
@@ -238,13 +251,43 @@ __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const
   pull(src, k, xp, y, f);
   Mat<R> mp = material<R, MAT>(k, phi_f, invk_f, d_f, xp, y);
   if (!(inlet || outlet)) return mp;
+  Mat<R> mb = material<R, MAT>(k, phi_f, invk_f, d_f, x, y);
+  boundary_column(f, k, y, inlet, mp, mb);
+  if (outlet) outlet_scalar_material(mb, mp);
+  return mb;
+}
 
+// The outlet node collides its copied scalar populations with the scalar
+// material (b_T, b_C, rho c_p) of column nx-2, so that the last two columns
+// are one medium for temperature and O2: with its own b the equilibrium
+// fluxes (4 + b) X / 20 across the last link differ and the outlet turns
+// into a source or sink proportional to X (unbounded growth for porosity
+// fields).  For layers uniform in x nothing changes.
+template <typename R>
+__device__ __forceinline__ void outlet_scalar_material(Mat<R>& mb, const Mat<R>& mp) {
+  mb.bT = mp.bT;
+  mb.bC = mp.bC;
+  mb.rhocp = mp.rhocp;
+}
+
+// Inlet velocity of row y (parabolic over the channel rows).
+template <typename R>
+__device__ __forceinline__ R inlet_velocity(const Consts<R>& k, int y) {
+  const R yc = R(y) + R(0.5);
+  return k.u_in_coef * yc * (R(k.ny_ch) - yc);
+}
+
+// Turn the pulled populations f of the column next to a boundary node into
+// the boundary node's pre-collision populations (inlet: velocity u_in(y)
+// with the pressure of the neighbour, Dirichlet theta = 0 and c = c_in;
+// outlet: zero pressure with the neighbour's velocity, scalars copied).
+template <typename R>
+__device__ __forceinline__ void boundary_column(R (&f)[19], const Consts<R>& k, int y, bool inlet, const Mat<R>& mp,
+                                                const Mat<R>& mb) {
   const Macro<R> a = flow_macros(f, mp, k);
-  const Mat<R> mb = material<R, MAT>(k, phi_f, invk_f, d_f, x, y);
   R ubx, uby, pb;
   if (inlet) {
-    const R yc = R(y) + R(0.5);
-    ubx = k.u_in_coef * yc * (R(k.ny_ch) - yc);
+    ubx = inlet_velocity(k, y);
     uby = R(0);
     pb = a.p;
   } else {
@@ -268,7 +311,6 @@ __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const
     add_geq(k.c_in, ubx, uby, mb.bC, R(1), f + 14);
     add_geq(c1, a.ux, a.uy, mp.bC, R(-1), f + 14);
   }
-  return mb;
 }
 
 template <typename R>

@@ -272,3 +272,22 @@ __global__ __launch_bounds__(kBlock) void k_pitch_copy(const R* __restrict__ src
 }
 
 }  // namespace lbm
+
+namespace lbm {
+
+// Per-cell porosity, 1/K and O2 diffusivity as the kernels use them.
+template <typename R, int MAT>
+__global__ __launch_bounds__(kBlock) void k_material(const R* __restrict__ phi_f, const R* __restrict__ invk_f,
+                                                     const R* __restrict__ d_f, Consts<R> k, R* phi, R* invk, R* d) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= k.nx) return;
+  R a, b, c;
+  base_fields<R, MAT>(k, phi_f, invk_f, d_f, x, y, a, b, c);
+  const size_t o = (size_t)y * k.nx + x;
+  if (phi) phi[o] = a;
+  if (invk) invk[o] = b;
+  if (d) d[o] = c;
+}
+
+}  // namespace lbm

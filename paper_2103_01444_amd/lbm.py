@@ -57,13 +57,14 @@ class Schedule(ctypes.Structure):
 _lib = None
 
 EXPORTED = ["lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_set_params", "lbm_init_equilibrium",
-            "lbm_step", "lbm_observables", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations",
+            "lbm_step", "lbm_observables", "lbm_get_fields", "lbm_get_material", "lbm_get_populations",
+            "lbm_set_populations",
             "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count", "lbm_synchronize",
             "lbm_destroy", "lbm_status_string", "lbm_last_error",
             "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_init_equilibrium", "lbm_batch_set_schedule",
             "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_observables",
             "lbm_batch_get_populations", "lbm_batch_step_count", "lbm_batch_synchronize", "lbm_batch_destroy",
-            "lbm_batch_last_error"]
+            "lbm_batch_last_error", "lbm_adjoint_workspace_bytes", "lbm_forward_checkpointed", "lbm_backward"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -86,6 +87,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_observables": (ctypes.c_int, [vp, P(Obs), vp, vp, vp]),
         "lbm_get_fields": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
+        "lbm_get_material": (ctypes.c_int, [vp, vp, vp, vp]),
         "lbm_set_populations": (ctypes.c_int, [vp, vp, i64]),
         "lbm_state_bytes": (sz, [vp]),
         "lbm_save_state": (ctypes.c_int, [vp, vp, P(i64)]),
@@ -108,6 +110,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_batch_synchronize": (ctypes.c_int, [vp]),
         "lbm_batch_destroy": (None, [vp]),
         "lbm_batch_last_error": (ctypes.c_char_p, [vp]),
+        "lbm_adjoint_workspace_bytes": (sz, [vp, i64, ctypes.c_int32]),
+        "lbm_forward_checkpointed": (ctypes.c_int, [vp, i64, ctypes.c_int32, vp, sz, P(ctypes.c_double)]),
+        "lbm_backward": (ctypes.c_int, [vp, ctypes.c_double, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +241,12 @@ class Cathode:
         self._check(self.lib.lbm_get_fields(self.ctx, *[_ptr(out[k]) for k in ("ux", "uy", "p", "T", "theta", "c")]))
         return out
 
+    def material(self) -> dict:
+        out = {k: torch.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
+               for k in ("phi", "inv_k", "d_eff")}
+        self._check(self.lib.lbm_get_material(self.ctx, _ptr(out["phi"]), _ptr(out["inv_k"]), _ptr(out["d_eff"])))
+        return out
+
     def populations(self) -> torch.Tensor:
         out = torch.empty((19, self.ny, self.nx), dtype=self.dtype, device=self.device)
         self._check(self.lib.lbm_get_populations(self.ctx, _ptr(out)))
@@ -257,6 +268,28 @@ class Cathode:
 
     def load_state(self, buf, step: int):
         self._check(self.lib.lbm_load_state(self.ctx, _ptr(buf), int(step)))
+
+    # ------------------------------------------------------------ adjoint
+    def forward_checkpointed(self, nsteps: int, every: int = 200) -> float:
+        """Run nsteps steps from the equilibrium state keeping a checkpoint
+        every ``every`` steps; returns the mean current density J (A/cm^2)."""
+        n = self.lib.lbm_adjoint_workspace_bytes(self.ctx, int(nsteps), int(every))
+        if n == 0:
+            raise LbmError("invalid adjoint run length")
+        self.adj_ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        J = ctypes.c_double()
+        self._check(self.lib.lbm_forward_checkpointed(self.ctx, int(nsteps), int(every), _ptr(self.adj_ws), n,
+                                                      ctypes.byref(J)))
+        return J.value
+
+    def backward(self, dJ: float = 1.0) -> dict:
+        """dJ times the gradient of J with respect to the per-cell 1/K,
+        porosity and D_eff (and K: -(1/K)^2 dJ/d(1/K)), as [ny, nx] tensors."""
+        out = {k: torch.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
+               for k in ("inv_k", "phi", "d_eff")}
+        self._check(self.lib.lbm_backward(self.ctx, float(dJ), _ptr(out["inv_k"]), _ptr(out["phi"]),
+                                          _ptr(out["d_eff"])))
+        return out
 
     def __del__(self):
         try:
@@ -378,3 +411,30 @@ class BatchedSweep:
                 self.h = None
         except Exception:
             pass
+
+
+class CurrentDensity(torch.autograd.Function):
+    """J = mean current density after ``nsteps`` steps of a cathode whose
+    porous layers are given cell by cell: 1/K (``inv_k``), porosity
+    (``phi``) and O2 diffusivity (``d_eff``), all [ny, nx] CUDA tensors in
+    lattice units.  ``backward`` runs the library's hand-written discrete
+    adjoint (checkpointed recomputation every ``every`` steps).
+
+        J = CurrentDensity.apply(inv_k, phi, d_eff, workload, nsteps, every)
+    """
+
+    @staticmethod
+    def forward(ctx, inv_k, phi, d_eff, workload: dict, nsteps: int, every: int = 200):
+        params = params_from_workload(workload, independent_fields=1)
+        sim = Cathode(workload["nx"], workload["ny"], workload["ny_channel"], workload["ny_gdl"],
+                      workload["ny_cl"], params, precision=workload.get("precision", 32),
+                      phi=phi.detach(), inv_k=inv_k.detach(), d_eff=d_eff.detach())
+        J = sim.forward_checkpointed(nsteps, every)
+        ctx.sim = sim
+        return torch.tensor(J, dtype=torch.float64, device=phi.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        g = ctx.sim.backward(float(gJ))
+        ctx.sim = None
+        return g["inv_k"], g["phi"], g["d_eff"], None, None, None

@@ -286,3 +286,24 @@ def test_parameter_validation():
     phi[30, 30] = 0.0
     with pytest.raises(lbm.LbmError, match="stable range"):
         lbm.Cathode.from_workload(dict(w, dp_over_hgdl=0.3), phi=phi)
+
+
+def test_full_size_outlet_stays_bounded():
+    """4096x1024 FP32 porosity field over 6000 steps: the temperature rise
+    grows no faster than linearly (the outlet reading; an outlet colliding
+    with its own b doubled it every ~500 steps), and O2 at the outlet
+    column stays at or below the inlet value times the largest diffusivity
+    ratio the scheme's equilibrium can produce."""
+    lbm = _gpu_mod()
+    w, phi = _full_size_case()
+    gpu = lbm.Cathode.from_workload(w, phi=phi)
+    gpu.step(3000)
+    th3 = float(gpu.fields()["theta"].max())
+    gpu.step(3000)
+    f = gpu.fields()
+    th6 = float(f["theta"].max())
+    print(f"theta max: {th3:.4e} at 3000 steps, {th6:.4e} at 6000 steps", flush=True)
+    assert 0 < th6 < 2.5 * th3
+    cout = float(f["c"][:, -2:].max())
+    ratio = 1.0 / 0.4 ** 1.5  # D_f / D_eff at the smallest porosity of the field
+    assert cout <= ratio * 1.0 + 1e-3

@@ -1,0 +1,56 @@
+"""Pin of the oracle's discrete gradient (reverse-mode differentiation of the
+oracle) against central finite differences of the oracle's forward map,
+which share no differentiation machinery.  CPU only."""
+import numpy as np
+import torch
+
+import workloads as W
+from oracle import adjoint2d as A
+from oracle import lbm2d as L
+
+DT = torch.float64
+
+
+def _case(nx=14, ny=10, layers=(5, 4, 1), seed=3):
+    w = W.adjoint2d(nx, ny)
+    w.update(ny_channel=layers[0], ny_gdl=layers[1], ny_cl=layers[2], Re=2.0, V_op=0.45)
+    rng = np.random.default_rng(seed)
+    phi = np.ones((ny, nx))
+    phi[layers[0]:] = rng.uniform(0.4, 0.8, size=(ny - layers[0], nx))
+    dp = 0.3325 * layers[1]
+    inv_k = np.where(phi < 1, (1 - phi) ** 2 / (0.0067 * phi ** 3 * dp * dp), 0.0)
+    d_eff = phi ** 1.5 * w["D_f_lat"]
+    g = L.geometry_from_workload(w)
+    p = L.Params.from_workload(w)
+    return g, p, [torch.tensor(a, dtype=DT) for a in (phi, inv_k, d_eff)]
+
+
+def test_gradient_matches_central_differences():
+    g, p, fields = _case()
+    nsteps = 40
+    J, gphi, gk, gd = A.gradient(g, p, *fields, nsteps=nsteps, every=15)
+    assert float(J) > 0
+    grads = [gphi, gk, gd]
+    cells = [(9, 3), (8, 7), (6, 11), (9, 12), (5, 0), (7, 13)]  # CL, GDL, and the inlet / outlet columns
+    for f_idx in range(3):
+        for (y, x) in cells:
+            base = fields[f_idx][y, x].item()
+            h = 1e-6 * max(abs(base), 1e-3)
+            vals = []
+            for sgn in (1, -1):
+                pert = [a.clone() for a in fields]
+                pert[f_idx][y, x] = base + sgn * h
+                vals.append(float(A.mean_current_density(g, p, *pert, nsteps=nsteps)))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            ad = float(grads[f_idx][y, x])
+            scale = float(grads[f_idx].abs().max())
+            assert abs(ad - fd) <= 1e-6 * scale + 1e-9 * abs(fd), (f_idx, y, x, ad, fd, scale)
+
+
+def test_checkpoint_segments_do_not_change_the_gradient():
+    g, p, fields = _case(seed=4)
+    a = A.gradient(g, p, *fields, nsteps=30, every=30)
+    b = A.gradient(g, p, *fields, nsteps=30, every=7)
+    assert torch.equal(a[0], b[0])  # same forward arithmetic
+    for u, v in zip(a[1:], b[1:]):  # gradient terms summed in another order
+        assert float((u - v).abs().max()) <= 1e-12 * float(v.abs().max())

@@ -123,3 +123,26 @@ def test_cathode_trends_smoke():
     assert float(current(V_op=0.5, T_in=353.0)["current_density"]) > float(base["current_density"])
     assert float(current(V_op=0.6, T_in=363.0)["current_density"]) > float(base["current_density"])
     assert float(base["heat_rate"]) > 0 and 0 < float(base["o2_utilisation"]) < 1
+
+
+def test_outlet_link_carries_no_flux_at_rest_in_a_porosity_field():
+    # Reading of the "fully developed" scalar outlet: the outlet node collides
+    # the copied populations with column nx-2's scalar material, so a resting
+    # state of uniform O2 and temperature rise exchanges nothing across the
+    # last link even where the porosity (hence b) jumps between the two
+    # columns; colliding with the node's own b would leak (4 + b) X / 20
+    # differences through the outlet every step.
+    w = W.cathode2d_scaled(12, 10, precision=64, phi_seed=5, Re=0.0)
+    phi = torch.as_tensor(W.porosity_field(w))
+    g = L.Geometry(12, 10, w["ny_channel"], w["ny_gdl"], w["ny_cl"])
+    p = L.Params.from_workload(w)
+    p.reaction = False
+    m = L.Model(g, p, phi=phi)
+    z = torch.zeros(10, 12, dtype=DT)
+    pre = m.equilibrium_state(z, z, z, z + 0.3, z + 0.8)
+    post = m.collide(m.open_boundaries(pre))
+    nx = 12
+    for base in (9, 14):
+        flux = post[base + 1, :, nx - 2] - post[base + 3, :, nx - 1]
+        assert float(flux.abs().max()) < 1e-16
+    assert float((m.b_C[:, nx - 1] - m.b_C[:, nx - 2]).abs().max()) > 1e-2  # the jump is real

@@ -143,12 +143,15 @@ def batched_cases(n: int = 64, seed: int = SEED_BATCH) -> list[dict]:
     return cases
 
 
-def fd_cells(w: dict, n: int = 32, seed: int = SEED_ADJOINT_FD) -> list[tuple[int, int]]:
-    """``n`` distinct GDL cells (y, x), seeded, for finite-difference checks."""
+def fd_cells(w: dict, n: int = 32, seed: int = SEED_ADJOINT_FD, depth: int = 12) -> list[tuple[int, int]]:
+    """``n`` distinct porous cells (y, x), seeded, for finite-difference
+    checks, drawn from the ``depth`` GDL rows next to the CL and the CL rows
+    (the cells a few thousand steps of diffusion from the CL can reach)."""
     rng = np.random.default_rng(seed)
-    ch, gdl = w["ny_channel"], w["ny_gdl"]
-    flat = rng.choice(gdl * w["nx"], size=n, replace=False)
-    return [(int(ch + i // w["nx"]), int(i % w["nx"])) for i in flat]
+    y0 = max(w["ny_channel"], w["ny"] - w["ny_cl"] - depth)
+    rows = w["ny"] - y0
+    flat = rng.choice(rows * w["nx"], size=n, replace=False)
+    return [(int(y0 + i // w["nx"]), int(i % w["nx"])) for i in flat]
 
 
 def random_populations(ny: int, nx: int, seed: int) -> np.ndarray:
