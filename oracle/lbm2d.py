@@ -186,6 +186,23 @@ def _safe_sqrt(a: torch.Tensor) -> torch.Tensor:
     return torch.where(pos, torch.sqrt(torch.where(pos, a, torch.ones_like(a))), torch.zeros_like(a))
 
 
+def catalyst_reaction(pr: "Params", dt: float, theta, c, rhocp):
+    """Catalyst-layer oxygen reduction over one step of length dt (s); see
+    Model.reaction for the definitions (Eqs. 12-17, [R11], [R12])."""
+    T = pr.T_in + theta
+    U0 = pr.U0_slope * T + pr.U0_icept
+    eta = pr.V_op - U0
+    aj0 = pr.aj0_ref * torch.exp(-pr.E_over_R * (1.0 / T - 1.0 / pr.T_arrh))
+    k = aj0 * torch.exp(-pr.alpha_c * pr.faraday * eta / (pr.R_gas * T))
+    four_f_cref = 4.0 * pr.faraday * pr.C_ref
+    kappa = k * dt / four_f_cref
+    s_c = -c * torch.expm1(-kappa)
+    j_eff = -four_f_cref * s_c / dt
+    Q = -j_eff * (eta + T * pr.U0_slope)
+    S_T = Q * dt / rhocp
+    return s_c, S_T, j_eff, Q, k
+
+
 def _mv(mat: torch.Tensor, planes: torch.Tensor) -> torch.Tensor:
     """Matrix times a stack of planes: out[i] = sum_j mat[i, j] planes[j]."""
     return torch.einsum("ij,j...->i...", mat, planes)
@@ -435,19 +452,7 @@ class Model:
           Q     = -j_eff (eta + T dU0/dT)                      [W/cm^3] (Eq. 15);
           S_T   = Q dt / (rho c_p)_eff                         [K] per step [R12].
         """
-        pr = self.p
-        T = pr.T_in + theta
-        U0 = pr.U0_slope * T + pr.U0_icept
-        eta = pr.V_op - U0
-        aj0 = pr.aj0_ref * torch.exp(-pr.E_over_R * (1.0 / T - 1.0 / pr.T_arrh))
-        k = aj0 * torch.exp(-pr.alpha_c * pr.faraday * eta / (pr.R_gas * T))
-        four_f_cref = 4.0 * pr.faraday * pr.C_ref
-        kappa = k * self.dt / four_f_cref
-        s_c = -c * torch.expm1(-kappa)
-        j_eff = -four_f_cref * s_c / self.dt
-        Q = -j_eff * (eta + T * pr.U0_slope)
-        S_T = Q * self.dt / rhocp
-        return s_c, S_T, j_eff, Q, k
+        return catalyst_reaction(self.p, self.dt, theta, c, rhocp)
 
     # ------------------------------------------------------------- one step
     def collide(self, pre: torch.Tensor) -> torch.Tensor:
