@@ -159,6 +159,35 @@ def bench_adjoint(nsteps: int = 4000, every: int = 200) -> dict:
             "max_abs_grad": {k: float(v.abs().max()) for k, v in g.items()}}
 
 
+BYTES_PER_LU_3D = 33 * 4 * 2 + 4  # 33 FP32 populations read and written, porosity read
+
+
+def bench_3d(steps: int, warmup: int = 50) -> dict:
+    """The 256x128x64 FP32 3D cathode (D3Q19 + 2 x D3Q7, sphere-pack GDL)."""
+    import workloads as W
+    from paper_2103_01444_amd import Cathode3D
+
+    w = W.cathode3d_256x128x64()
+    phi = W.sphere_pack_porosity(w)
+    sim = Cathode3D.from_workload(w, phi=phi)
+    sim.step(warmup)
+    wall, ev = _timed(sim.stream, lambda: sim.step(steps))
+    obs = sim.observables()
+    del sim
+    cells = w["nx"] * w["ny"] * w["nz"]
+    launch_s = ev / steps
+    achieved = cells * BYTES_PER_LU_3D / launch_s / 1e9
+    return {"workload": w["name"], "cells": cells, "steps": steps, "value": round(cells * steps / wall / 1e6, 1),
+            "unit": "MLUPS", "ms_per_step": round(wall * 1e3 / steps, 5),
+            "kernel": {"name": "k3_step<float, MAT_PHI>", "avg_launch_us": round(launch_s * 1e6, 3),
+                       "algorithmic_bytes_per_launch": cells * BYTES_PER_LU_3D,
+                       "bytes_per_lattice_update": BYTES_PER_LU_3D},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4)},
+            "observables": {"current_density_A_cm2": obs["current_density"], "T_max_K": obs["T_max"],
+                            "o2_utilisation": obs["o2_utilisation"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +196,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500, help="0 skips the batched sweep")
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint")
+    ap.add_argument("--steps3d", type=int, default=5000, help="0 skips the 3D cathode")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write copy kernel 5 times (counter calibration)")
     args = ap.parse_args()
@@ -255,6 +285,11 @@ def main():
         line["adjoint"] = bench_adjoint(args.adjoint_steps)
         print(f"bench: adjoint {line['adjoint']['adjoint']['value']} MLUPS, "
               f"{line['adjoint']['adjoint_over_forward_time']}x forward time", file=sys.stderr, flush=True)
+    if args.steps3d > 0:
+        print("bench: 3D cathode", file=sys.stderr, flush=True)
+        line["cathode3d"] = bench_3d(args.steps3d)
+        print(f"bench: 3D {line['cathode3d']['value']} MLUPS, {line['cathode3d']['roofline']['achieved']} GB/s",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, phi)
     print(json.dumps(line), flush=True)

@@ -289,6 +289,80 @@ lbm_status lbm_batch_synchronize(lbm_batch* b);
 void lbm_batch_destroy(lbm_batch* b);
 const char* lbm_batch_last_error(const lbm_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Three-dimensional cathode.  The paper is two-dimensional; this variant
+ * carries its physics (Sections 2 and 4: porous flow with Eqs. 5-8, the two
+ * advected scalars of Eq. 10, the CL reaction of Eqs. 12-17, Eqs. 18-19,
+ * the same inlet / outlet / wall conditions) to a D3Q19 flow lattice and
+ * two D3Q7 scalar lattices.
+ *   Collision: the paper's D2Q9 MRT, with the density moment relaxed at
+ *   1/tau_f, is a two-rate collision (even moments at s+ = 1/tau_f,
+ *   non-conserved odd moments at s- = 8(2 - s+)/(8 - s+)), and its D2Q5 MRT
+ *   one with even rate 6/(3 + 2 sqrt 3) and odd rate 6/(3 + sqrt 3); the 3D
+ *   lattices use the same rates.  The D2Q5 parameter b = 20 sqrt(3) alpha - 4
+ *   becomes the D3Q7 weight a = sqrt(3) alpha of each moving population.
+ *   Equilibrium: f0 = rho0 - 2 phi p - |u|^2/(2 phi), f_i = 3 w_i phi p +
+ *   w_i (3 e.u + 4.5 (e.u)^2/phi - 1.5 |u|^2/phi); p from the 18 moving
+ *   populations.
+ *   Lattice: x = 0 .. nx-1 inlet to outlet, y = 0 .. ny-1 across the
+ *   channel (walls at both ends), z = 0 .. nz-1 through the layers: layers
+ *   [0, nz_channel) gas channel, then nz_gdl GDL layers, then nz_cl CL
+ *   layers (walls below the channel and below the CL).  Inlet: channel
+ *   cells of x = 0, u_x = 36 U (y+1/2)(ny-y-1/2)(z+1/2)(H-z-1/2)/(ny^2 H^2)
+ *   with U = Re nu / H, H = nz_channel, Dirichlet T_in and c_in; outlet
+ *   x = nx-1 as in 2D.
+ *   Per-cell arrays: dense [nz][ny][nx], x fastest, context precision,
+ *   device memory.  Populations: 33 dense planes [33][nz][ny][nx]: planes
+ *   0-18 D3Q19 flow in the order (0,0,0), (+-1,0,0), (0,+-1,0), (0,0,+-1),
+ *   (+-1,+-1,0), (+-1,-+1,0), (+-1,0,+-1), (+-1,0,-+1), (0,+-1,+-1),
+ *   (0,+-1,-+1) (each pair: the vector, then its opposite), planes 19-25
+ *   D3Q7 temperature rise, 26-32 D3Q7 O2 (order of the first seven D3Q19
+ *   vectors).
+ * Ownership, threading, errors, and the meaning of state, fields and
+ * observables: as for the 2D context.  Observables are means over the
+ * (x, y) area of the CL: i(x, y) = sum over CL layers of (-j) dx.
+ * --------------------------------------------------------------------------- */
+#define LBM_PERIODIC_Z 16u /* no z walls: z wraps (test configurations) */
+
+typedef struct lbm3d_geometry {
+  int32_t nx, ny, nz;                    /* nx >= 3; ny, nz in [1, 65535] */
+  int32_t nz_channel, nz_gdl, nz_cl;     /* non-negative, sum to nz */
+  int32_t precision;                     /* 32 or 64 */
+  uint32_t flags;                        /* LBM_PERIODIC_X/Y/Z, LBM_BODY_FORCE, LBM_NO_REACTION */
+} lbm3d_geometry;
+
+typedef struct lbm3d_ctx lbm3d_ctx;
+
+/* Device workspace bytes for this geometry; 0 if invalid. */
+size_t lbm3d_workspace_bytes(const lbm3d_geometry* g);
+/* As lbm_create.  Errors: LBM_ERR_INVALID_ARG. */
+lbm_status lbm3d_create(const lbm3d_geometry* g, void* dev_ws, size_t ws_bytes, void* hip_stream, lbm3d_ctx** out);
+/* As lbm_set_params, with per-cell arrays [nz][ny][nx]; the GDL thickness
+ * spans nz_gdl layers.  The inlet peak 2.25 U must not exceed 0.1.
+ * Synchronous. */
+lbm_status lbm3d_set_params(lbm3d_ctx* ctx, const lbm_params* p, const void* phi, const void* inv_k,
+                            const void* d_eff);
+/* Rest fluid, T_in, c_in everywhere; resets the step counter.  Async. */
+lbm_status lbm3d_init_equilibrium(lbm3d_ctx* ctx);
+/* Advance nsteps time steps.  Async. */
+lbm_status lbm3d_step(lbm3d_ctx* ctx, int64_t nsteps);
+/* Observables of the current state, FP64 fixed-order reductions.
+ * Synchronous; LBM_ERR_NONFINITE as in 2D. */
+lbm_status lbm3d_observables(lbm3d_ctx* ctx, lbm_obs* out);
+/* Fields of the current state into device arrays [nz][ny][nx]; NULL skips
+ * one.  Async. */
+lbm_status lbm3d_get_fields(lbm3d_ctx* ctx, void* ux, void* uy, void* uz, void* p, void* T, void* theta,
+                            void* c);
+/* Porosity, 1/K and O2 diffusivity the update uses.  Async. */
+lbm_status lbm3d_get_material(lbm3d_ctx* ctx, void* phi, void* inv_k, void* d_eff);
+/* Canonical post-collision populations (33 dense planes).  Async. */
+lbm_status lbm3d_get_populations(lbm3d_ctx* ctx, void* dev_dst);
+lbm_status lbm3d_set_populations(lbm3d_ctx* ctx, const void* dev_src, int64_t step);
+int64_t lbm3d_step_count(const lbm3d_ctx* ctx);
+lbm_status lbm3d_synchronize(lbm3d_ctx* ctx);
+void lbm3d_destroy(lbm3d_ctx* ctx);
+const char* lbm3d_last_error(const lbm3d_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -316,3 +316,15 @@ class Model3D:
         return dict(current_density=I, power_density=self.p.V_op * I, heat_rate=H, o2_utilisation=util,
                     T_max=(self.p.T_in + theta).max(), sum_f=pre[0:19].sum(), sum_theta=theta.sum(),
                     sum_c=c.sum(), consumed_c=s_c.sum(), heat_added=S_T.sum())
+
+
+def params_from_workload(w: dict) -> L.Params:
+    """Oracle parameters of a 3D workload dictionary."""
+    p = L.Params.from_workload({k: v for k, v in w.items() if k != "dp_over_hgdl"})
+    if w.get("dp_lat", 0.0) > 0:
+        p.dp_lat = float(w["dp_lat"])
+    return p
+
+
+def geometry_from_workload(w: dict, **flags) -> Geometry3D:
+    return Geometry3D(w["nx"], w["ny"], w["nz"], w["nz_channel"], w["nz_gdl"], w["nz_cl"], **flags)

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbmpem.so")
 ARCH = "gfx950"
 
-SOURCES = ["lbm_api.hip", "lbm_batch_api.hip"]
+SOURCES = ["lbm_api.hip", "lbm_batch_api.hip", "lbm3d_api.hip"]
 
 # Packed FP32 instructions are disabled for the device code (the host pass
 # warns that it does not know the feature; that is harmless).

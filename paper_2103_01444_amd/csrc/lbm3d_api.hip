@@ -1,0 +1,477 @@
+// Host side of the 3D part of the C ABI (lbm3d_*): context, parameters,
+// launches.  As in 2D, all device memory is the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm3d_kernels.hpp"
+#include "lbm_host.hpp"
+#include "lbm_pem.h"
+
+using namespace lbm3;
+
+namespace {
+
+constexpr size_t kAlign3 = 256;
+size_t align3(size_t v) { return (v + kAlign3 - 1) / kAlign3 * kAlign3; }
+constexpr int kChunkY = 16;  // y rows per chunk of the step's launch order
+
+struct Layout3 {
+  int pitch = 0;
+  int64_t plane = 0;  // elements per population plane
+  size_t esize = 0;
+  size_t state = 0;   // aligned bytes of one 33-plane state
+  size_t off_state[2] = {0, 0};
+  size_t off_mat = 0, off_partial = 0, off_out = 0, total = 0;
+  int nbx = 0;
+  int nblocks_obs = 0;
+};
+
+bool geometry3_ok(const lbm3d_geometry* g) {
+  if (!g) return false;
+  if (g->nx < 3 || g->ny < 1 || g->nz < 1 || g->ny > 65535 || g->nz > 65535) return false;
+  if (g->nz_channel < 0 || g->nz_gdl < 0 || g->nz_cl < 0) return false;
+  if (g->nz_channel + g->nz_gdl + g->nz_cl != g->nz) return false;
+  if (g->precision != 32 && g->precision != 64) return false;
+  if (g->flags & ~(LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_PERIODIC_Z | LBM_BODY_FORCE | LBM_NO_REACTION)) return false;
+  const int64_t pitch = (int64_t(g->nx) + 63) / 64 * 64;
+  if (pitch * g->ny * g->nz * 33 >= (int64_t(1) << 31)) return false;  // 32-bit element offsets
+  return true;
+}
+
+Layout3 make_layout3(const lbm3d_geometry* g) {
+  Layout3 L;
+  L.esize = g->precision == 64 ? 8 : 4;
+  L.pitch = (g->nx + 63) / 64 * 64;
+  L.plane = int64_t(L.pitch) * g->ny * g->nz;
+  L.state = align3(size_t(33) * L.plane * L.esize);
+  L.nbx = (g->nx + kBlock3 - 1) / kBlock3;
+  L.nblocks_obs = L.nbx * g->ny * g->nz;
+  size_t o = 0;
+  L.off_state[0] = o;
+  o += L.state;
+  L.off_state[1] = o;
+  o += L.state;
+  L.off_mat = o;
+  o += align3(size_t(3) * L.plane * L.esize);
+  L.off_partial = o;
+  o += align3(size_t(L.nblocks_obs) * kObsQ3 * sizeof(double));
+  L.off_out = o;
+  o += align3(16 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+// The 2D derivation applied to the through-plane (z) layering.
+lbm_geometry as_layers(const lbm3d_geometry& g) {
+  lbm_geometry l{};
+  l.nx = g.nx;
+  l.ny = g.nz;
+  l.ny_channel = g.nz_channel;
+  l.ny_gdl = g.nz_gdl;
+  l.ny_cl = g.nz_cl;
+  l.precision = g.precision;
+  l.flags = g.flags & (LBM_PERIODIC_X | LBM_BODY_FORCE | LBM_NO_REACTION);
+  return l;
+}
+
+}  // namespace
+
+struct lbm3d_ctx {
+  lbm3d_geometry g{};
+  lbm_params p{};
+  Layout3 L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;
+  int64_t step = 0;
+  bool params_set = false;
+  int mat = MAT_LAYERED;
+  Consts3<float> kf{};
+  Consts3<double> kd{};
+  lbm::Derived d;
+  std::string err;
+
+  void* state(int i) { return ws + L.off_state[i]; }
+  void* mat_plane(int i) { return ws + L.off_mat + size_t(i) * L.plane * L.esize; }
+  double* partial() { return reinterpret_cast<double*>(ws + L.off_partial); }
+  double* out() { return reinterpret_cast<double*>(ws + L.off_out); }
+  dim3 grid3() const { return dim3(L.nbx, g.ny, g.nz); }
+};
+
+namespace {
+
+lbm_status fail3(lbm3d_ctx* c, lbm_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+lbm_status check3(lbm3d_ctx* c, const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail3(c, LBM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+template <typename R>
+void fill_consts3(Consts3<R>& k, const lbm3d_geometry& g, const lbm_params& p, const lbm::Derived& d, int pitch) {
+  lbm::Consts<R> k2{};
+  lbm::fill_consts(k2, as_layers(g), p, d, pitch);
+  k.nx = g.nx;
+  k.ny = g.ny;
+  k.nz = g.nz;
+  k.pitch = pitch;
+  k.nz_ch = g.nz_channel;
+  k.z_cl0 = g.nz_channel + g.nz_gdl;
+  k.flags = g.flags;
+  k.plane = int32_t(int64_t(pitch) * g.ny * g.nz);
+  k.ty = std::min(kChunkY, g.ny);
+  k.pad_ = 0;
+  k.s_plus = k2.s_e;
+  k.s_minus = k2.s_q;
+  k.nu = k2.nu;
+  const double H = g.nz_channel, W = g.ny;
+  k.u_in_coef = g.nz_channel > 0 ? R(36.0 * d.u_avg / (W * W * H * H)) : R(0);
+  k.ax = k2.ax;
+  k.ay = k2.ay;
+  k.phi_gdl = k2.phi_gdl;
+  k.invk_gdl = k2.invk_gdl;
+  k.d_gdl = k2.d_gdl;
+  k.D_f = k2.D_f;
+  k.kc_inv = k2.kc_inv;
+  k.deff_ratio = k2.deff_ratio;
+  k.k_f = k2.k_f;
+  k.k_s = k2.k_s;
+  k.rhocp_f = k2.rhocp_f;
+  k.rhocp_s = k2.rhocp_s;
+  k.alpha_scale = k2.alpha_scale;
+  k.T_in = k2.T_in;
+  k.c_in = k2.c_in;
+  k.V_op = k2.V_op;
+  k.U0_slope = k2.U0_slope;
+  k.U0_icept = k2.U0_icept;
+  k.ln_k0 = k2.ln_k0;
+  k.E_over_R = k2.E_over_R;
+  k.inv_T_arrh = k2.inv_T_arrh;
+  k.aF_over_R = k2.aF_over_R;
+  k.four_f_cref = k2.four_f_cref;
+}
+
+template <typename R>
+const Consts3<R>& consts3(const lbm3d_ctx* c);
+template <>
+const Consts3<float>& consts3<float>(const lbm3d_ctx* c) { return c->kf; }
+template <>
+const Consts3<double>& consts3<double>(const lbm3d_ctx* c) { return c->kd; }
+
+template <typename R>
+struct Mat3Ptrs {
+  const R *phi, *invk, *d;
+};
+template <typename R>
+Mat3Ptrs<R> mat3_ptrs(lbm3d_ctx* c) {
+  return {static_cast<const R*>(c->mat_plane(0)), static_cast<const R*>(c->mat_plane(1)),
+          static_cast<const R*>(c->mat_plane(2))};
+}
+
+template <typename R>
+bool host_range3(lbm3d_ctx* c, const void* dev, double& lo, double& hi) {
+  const size_t n = size_t(c->g.nx) * c->g.ny * c->g.nz;
+  std::vector<R> h(n);
+  if (hipMemcpyAsync(h.data(), dev, n * sizeof(R), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return false;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return false;
+  lo = 1e300;
+  hi = -1e300;
+  for (size_t i = 0; i < n; ++i) {
+    const double v = double(h[i]);
+    if (!std::isfinite(v)) {
+      lo = -1e300;
+      return true;
+    }
+    lo = std::min(lo, v);
+    hi = std::max(hi, v);
+  }
+  return true;
+}
+
+// One kernel template per material mode; F is called with the mode as a
+// compile-time constant.
+template <typename F>
+void by_mat(int mat, F&& f) {
+  switch (mat) {
+    case MAT_LAYERED: f(std::integral_constant<int, MAT_LAYERED>{}); break;
+    case MAT_PHI: f(std::integral_constant<int, MAT_PHI>{}); break;
+    default: f(std::integral_constant<int, MAT_FULL>{}); break;
+  }
+}
+
+template <typename R>
+void launch_step3(lbm3d_ctx* c, int64_t n) {
+  const Mat3Ptrs<R> m = mat3_ptrs<R>(c);
+  const Consts3<R> k = consts3<R>(c);
+  const dim3 grid(unsigned(c->L.nblocks_obs));
+  by_mat(c->mat, [&](auto mode) {
+    constexpr int MAT = decltype(mode)::value;
+    for (int64_t i = 0; i < n; ++i) {
+      const R* src = static_cast<const R*>(c->state(c->cur));
+      R* dst = static_cast<R*>(c->state(c->cur ^ 1));
+      hipLaunchKernelGGL((k3_step<R, MAT>), grid, dim3(kBlock3), 0, c->stream, src, dst, m.phi, m.invk, m.d, k);
+      c->cur ^= 1;
+    }
+  });
+}
+
+template <typename R>
+lbm_status set_params3_t(lbm3d_ctx* c, const lbm_params* p, const void* phi, const void* inv_k, const void* d_eff) {
+  const lbm3d_geometry& g = c->g;
+  c->p = *p;
+  std::string msg;
+  const lbm_geometry lg = as_layers(g);
+  if (lbm_status st = lbm::derive(lg, *p, c->d, msg); st != LBM_OK) return fail3(c, st, msg);
+  // Peak of the product inlet profile is 2.25 U_avg (1.5 per direction).
+  if (!(g.flags & LBM_PERIODIC_X) && 2.25 * std::fabs(c->d.u_avg) > 0.1)
+    return fail3(c, LBM_ERR_UNSTABLE_PARAMS, "inlet peak velocity above 0.1");
+  c->d.inflow = 0;
+  if (!(g.flags & LBM_PERIODIC_X) && g.nz_channel > 0) {
+    const double H = g.nz_channel, W = g.ny;
+    const double coef = 36.0 * c->d.u_avg / (W * W * H * H);
+    for (int z = 0; z < g.nz_channel; ++z)
+      for (int y = 0; y < g.ny; ++y) {
+        const double zc = z + 0.5, yc = y + 0.5;
+        c->d.inflow += coef * yc * (W - yc) * zc * (H - zc) * p->c_in;
+      }
+  }
+  fill_consts3(c->kf, g, *p, c->d, c->L.pitch);
+  fill_consts3(c->kd, g, *p, c->d, c->L.pitch);
+
+  const bool any = phi || inv_k || d_eff;
+  if (!any && !p->independent_fields) {
+    c->mat = MAT_LAYERED;
+  } else if (phi && !inv_k && !d_eff && p->dp_lat > 0 && !p->independent_fields) {
+    c->mat = MAT_PHI;
+  } else {
+    c->mat = MAT_FULL;
+  }
+  const dim3 grid = c->grid3();
+  auto copy = [&](const void* src, int plane) {
+    hipLaunchKernelGGL(k3_pitch_copy<R>, grid, dim3(kBlock3), 0, c->stream, static_cast<const R*>(src),
+                       static_cast<R*>(c->mat_plane(plane)), g.nx, g.ny, c->L.pitch);
+    return hipGetLastError() == hipSuccess;
+  };
+  if (phi && !copy(phi, 0)) return fail3(c, LBM_ERR_DEVICE, "copy of porosity failed");
+  if (c->mat == MAT_FULL) {
+    if (inv_k && !copy(inv_k, 1)) return fail3(c, LBM_ERR_DEVICE, "copy of 1/K failed");
+    if (d_eff && !copy(d_eff, 2)) return fail3(c, LBM_ERR_DEVICE, "copy of D_eff failed");
+    hipLaunchKernelGGL(k3_derive_fields<R>, grid, dim3(kBlock3), 0, c->stream, static_cast<R*>(c->mat_plane(0)),
+                       static_cast<R*>(c->mat_plane(1)), static_cast<R*>(c->mat_plane(2)), consts3<R>(c),
+                       phi ? 1 : 0, inv_k ? 1 : 0, d_eff ? 1 : 0);
+    if (hipGetLastError() != hipSuccess) return fail3(c, LBM_ERR_DEVICE, "field derivation failed");
+  }
+  double phi_lo = p->phi_gdl, phi_hi = 1.0;
+  double d_lo = std::min(c->d.d_gdl, p->D_f_lat), d_hi = std::max(c->d.d_gdl, p->D_f_lat);
+  double k_lo = c->d.invk_gdl;
+  if (phi && !host_range3<R>(c, phi, phi_lo, phi_hi)) return fail3(c, LBM_ERR_DEVICE, "reading porosity failed");
+  if (inv_k) {
+    double hi;
+    if (!host_range3<R>(c, inv_k, k_lo, hi)) return fail3(c, LBM_ERR_DEVICE, "reading 1/K failed");
+  }
+  if (d_eff) {
+    if (!host_range3<R>(c, d_eff, d_lo, d_hi)) return fail3(c, LBM_ERR_DEVICE, "reading D_eff failed");
+  } else if (phi) {
+    const double dl = p->deff_ratio_gdl > 0 ? p->deff_ratio_gdl * p->D_f_lat : std::pow(phi_lo, 1.5) * p->D_f_lat;
+    d_lo = std::min(dl, p->D_f_lat);
+  }
+  if (!(phi_lo > 0) || phi_hi > 1.0) return fail3(c, LBM_ERR_UNSTABLE_PARAMS, "porosity outside (0, 1]");
+  if (!(k_lo >= 0)) return fail3(c, LBM_ERR_UNSTABLE_PARAMS, "negative or non-finite 1/K");
+  if (!(d_lo > 0) || d_hi > lbm::kMaxDiff)
+    return fail3(c, LBM_ERR_UNSTABLE_PARAMS, "O2 diffusivity outside (0, 1/(4 sqrt 3)]");
+  const double as = c->d.alpha_scale;
+  const double a1 = lbm::alpha_lat(*p, phi_lo, as), a2 = lbm::alpha_lat(*p, phi_hi, as), a3 = lbm::alpha_lat(*p, 1.0, as);
+  if (std::max({a1, a2, a3}) > lbm::kMaxDiff || !(std::min({a1, a2, a3}) > 0))
+    return fail3(c, LBM_ERR_UNSTABLE_PARAMS, "thermal diffusivity outside (0, 1/(4 sqrt 3)]");
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail3(c, LBM_ERR_DEVICE, "set_params sync failed");
+  c->params_set = true;
+  return LBM_OK;
+}
+
+template <typename R>
+lbm_status observables3_t(lbm3d_ctx* c, lbm_obs* o) {
+  const lbm_params& p = c->p;
+  const Mat3Ptrs<R> m = mat3_ptrs<R>(c);
+  const R* src = static_cast<const R*>(c->state(c->cur));
+  by_mat(c->mat, [&](auto mode) {
+    constexpr int MAT = decltype(mode)::value;
+    hipLaunchKernelGGL((k3_obs_cells<R, MAT>), c->grid3(), dim3(kBlock3), 0, c->stream, src, m.phi, m.invk, m.d,
+                       consts3<R>(c), c->partial());
+  });
+  hipLaunchKernelGGL(lbm::k_obs_final<kObsQ3>, dim3(kObsQ3), dim3(lbm::kBlock), 0, c->stream, c->partial(),
+                     c->L.nblocks_obs, c->out());
+  if (lbm_status s = check3(c, "observables"); s != LBM_OK) return s;
+  double h[kObsQ3];
+  if (hipMemcpyAsync(h, c->out(), sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return fail3(c, LBM_ERR_DEVICE, "observable copy failed");
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail3(c, LBM_ERR_DEVICE, "observables sync failed");
+  // i(x, y) = sum over CL layers of 4 F C_ref s_c / dt * dx; reported: its mean over (x, y).
+  const double i_scale = 4.0 * p.faraday * p.C_ref / c->d.dt * c->d.dx;
+  const double ncol = double(c->g.nx) * c->g.ny;
+  lbm_obs r{};
+  r.step = c->step;
+  r.current_density = h[3] * i_scale / ncol;
+  r.power_density = p.V_op * r.current_density;
+  r.heat_rate = h[5] * i_scale / ncol;
+  r.o2_utilisation = c->d.inflow > 0 ? h[3] / c->d.inflow : 0.0;
+  r.T_max = p.T_in_K + h[6];
+  r.sum_f = h[0] + ncol * c->g.nz;  // the rest population is stored as f0 - rho0
+  r.sum_theta = h[1];
+  r.sum_c = h[2];
+  r.consumed_c = h[3];
+  r.heat_added = h[4];
+  if (o) *o = r;
+  const double vals[] = {r.current_density, r.heat_rate, r.T_max, r.sum_f, r.sum_theta, r.sum_c, r.heat_added};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail3(c, LBM_ERR_NONFINITE, "non-finite observable");
+  if (h[7] > 0) return fail3(c, LBM_ERR_NONFINITE, "non-finite populations");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm3d_workspace_bytes(const lbm3d_geometry* g) {
+  if (!geometry3_ok(g)) return 0;
+  return make_layout3(g).total;
+}
+
+lbm_status lbm3d_create(const lbm3d_geometry* g, void* dev_ws, size_t ws_bytes, void* hip_stream, lbm3d_ctx** out) {
+  if (!out) return LBM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!geometry3_ok(g) || !dev_ws) return LBM_ERR_INVALID_ARG;
+  const Layout3 L = make_layout3(g);
+  if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign3) != 0) return LBM_ERR_INVALID_ARG;
+  lbm3d_ctx* c = new (std::nothrow) lbm3d_ctx();
+  if (!c) return LBM_ERR_INVALID_ARG;
+  c->g = *g;
+  c->L = L;
+  c->ws = static_cast<char*>(dev_ws);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm3d_set_params(lbm3d_ctx* c, const lbm_params* p, const void* phi, const void* inv_k, const void* d_eff) {
+  if (!c || !p) return LBM_ERR_INVALID_ARG;
+  c->params_set = false;
+  return c->g.precision == 64 ? set_params3_t<double>(c, p, phi, inv_k, d_eff)
+                              : set_params3_t<float>(c, p, phi, inv_k, d_eff);
+}
+
+lbm_status lbm3d_init_equilibrium(lbm3d_ctx* c) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
+  c->cur = 0;
+  c->step = 0;
+  auto run = [&](auto tag) {
+    using R = decltype(tag);
+    const Mat3Ptrs<R> m = mat3_ptrs<R>(c);
+    by_mat(c->mat, [&](auto mode) {
+      constexpr int MAT = decltype(mode)::value;
+      hipLaunchKernelGGL((k3_init<R, MAT>), c->grid3(), dim3(kBlock3), 0, c->stream, static_cast<R*>(c->state(0)),
+                         m.phi, m.invk, m.d, consts3<R>(c));
+    });
+  };
+  if (c->g.precision == 64) run(double{}); else run(float{});
+  return check3(c, "init");
+}
+
+lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
+  if (!c || n < 0) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
+  if (c->g.precision == 64) launch_step3<double>(c, n); else launch_step3<float>(c, n);
+  c->step += n;
+  return check3(c, "step");
+}
+
+lbm_status lbm3d_observables(lbm3d_ctx* c, lbm_obs* out) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
+  return c->g.precision == 64 ? observables3_t<double>(c, out) : observables3_t<float>(c, out);
+}
+
+lbm_status lbm3d_get_fields(lbm3d_ctx* c, void* ux, void* uy, void* uz, void* p, void* T, void* th, void* cc) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
+  auto run = [&](auto tag) {
+    using R = decltype(tag);
+    const Mat3Ptrs<R> m = mat3_ptrs<R>(c);
+    by_mat(c->mat, [&](auto mode) {
+      constexpr int MAT = decltype(mode)::value;
+      hipLaunchKernelGGL((k3_fields<R, MAT>), c->grid3(), dim3(kBlock3), 0, c->stream,
+                         static_cast<const R*>(c->state(c->cur)), m.phi, m.invk, m.d, consts3<R>(c),
+                         static_cast<R*>(ux), static_cast<R*>(uy), static_cast<R*>(uz), static_cast<R*>(p),
+                         static_cast<R*>(T), static_cast<R*>(th), static_cast<R*>(cc));
+    });
+  };
+  if (c->g.precision == 64) run(double{}); else run(float{});
+  return check3(c, "fields");
+}
+
+lbm_status lbm3d_get_material(lbm3d_ctx* c, void* phi, void* inv_k, void* d_eff) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
+  auto run = [&](auto tag) {
+    using R = decltype(tag);
+    const Mat3Ptrs<R> m = mat3_ptrs<R>(c);
+    by_mat(c->mat, [&](auto mode) {
+      constexpr int MAT = decltype(mode)::value;
+      hipLaunchKernelGGL((k3_material<R, MAT>), c->grid3(), dim3(kBlock3), 0, c->stream, m.phi, m.invk, m.d,
+                         consts3<R>(c), static_cast<R*>(phi), static_cast<R*>(inv_k), static_cast<R*>(d_eff));
+    });
+  };
+  if (c->g.precision == 64) run(double{}); else run(float{});
+  return check3(c, "get_material");
+}
+
+lbm_status lbm3d_get_populations(lbm3d_ctx* c, void* dst) {
+  if (!c || !dst) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
+  if (c->g.precision == 64)
+    hipLaunchKernelGGL(k3_export<double>, c->grid3(), dim3(kBlock3), 0, c->stream,
+                       static_cast<const double*>(c->state(c->cur)), static_cast<double*>(dst), c->kd);
+  else
+    hipLaunchKernelGGL(k3_export<float>, c->grid3(), dim3(kBlock3), 0, c->stream,
+                       static_cast<const float*>(c->state(c->cur)), static_cast<float*>(dst), c->kf);
+  return check3(c, "get_populations");
+}
+
+lbm_status lbm3d_set_populations(lbm3d_ctx* c, const void* src, int64_t step) {
+  if (!c || !src) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
+  if (c->g.precision == 64)
+    hipLaunchKernelGGL(k3_import<double>, c->grid3(), dim3(kBlock3), 0, c->stream, static_cast<const double*>(src),
+                       static_cast<double*>(c->state(c->cur)), c->kd);
+  else
+    hipLaunchKernelGGL(k3_import<float>, c->grid3(), dim3(kBlock3), 0, c->stream, static_cast<const float*>(src),
+                       static_cast<float*>(c->state(c->cur)), c->kf);
+  c->step = step;
+  return check3(c, "set_populations");
+}
+
+int64_t lbm3d_step_count(const lbm3d_ctx* c) { return c ? c->step : -1; }
+
+lbm_status lbm3d_synchronize(lbm3d_ctx* c) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail3(c, LBM_ERR_DEVICE, std::string("synchronize: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+void lbm3d_destroy(lbm3d_ctx* c) { delete c; }
+
+const char* lbm3d_last_error(const lbm3d_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

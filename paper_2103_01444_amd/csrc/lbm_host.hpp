@@ -78,7 +78,12 @@ inline lbm_status derive(const lbm_geometry& g, const lbm_params& p, Derived& d,
     err = "inlet peak velocity above 0.1";
     return LBM_ERR_UNSTABLE_PARAMS;
   }
-  d.invk_gdl = (p.Da_gdl > 0 && g.ny_gdl > 0) ? 1.0 / (p.Da_gdl * double(g.ny_gdl) * g.ny_gdl) : 0.0;
+  if (p.dp_lat > 0) {  // Kozeny-Carman (Eq. 7) at the layered porosity
+    const double ph = p.phi_gdl, om = 1.0 - ph;
+    d.invk_gdl = om * om / (0.0067 * ph * ph * ph * p.dp_lat * p.dp_lat);
+  } else {  // Darcy number K / h^2, h = GDL thickness
+    d.invk_gdl = (p.Da_gdl > 0 && g.ny_gdl > 0) ? 1.0 / (p.Da_gdl * double(g.ny_gdl) * g.ny_gdl) : 0.0;
+  }
   d.d_gdl = p.deff_ratio_gdl > 0 ? p.deff_ratio_gdl * p.D_f_lat : std::pow(p.phi_gdl, 1.5) * p.D_f_lat;
   if (d.d_gdl > kMaxDiff) {
     err = "O2 diffusivity outside (0, 1/(4 sqrt 3)]";

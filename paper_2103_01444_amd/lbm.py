@@ -21,6 +21,7 @@ LBM_PERIODIC_X = 1
 LBM_PERIODIC_Y = 2
 LBM_BODY_FORCE = 4
 LBM_NO_REACTION = 8
+LBM_PERIODIC_Z = 16
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "parameters outside the stable range", 3: "device error",
           4: "non-finite result", 5: "call out of order"}
@@ -36,6 +37,12 @@ _PARAM_NAMES = ["tau_f", "D_f_lat", "Re", "T_in_K", "c_in", "V_op", "phi_gdl", "
                 "dp_lat", "gdl_thickness_cm", "dx_cm", "D_O2_cm2s", "aj0_ref", "C_ref", "alpha_c", "faraday",
                 "R_gas", "E_over_R", "T_arrh", "U0_slope", "U0_icept", "k_f", "k_s", "rhocp_f", "rhocp_s",
                 "body_force_x", "body_force_y"]
+
+
+class Geometry3D(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("nz_channel", ctypes.c_int32), ("nz_gdl", ctypes.c_int32), ("nz_cl", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class Params(ctypes.Structure):
@@ -64,7 +71,10 @@ EXPORTED = ["lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_set_
             "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_init_equilibrium", "lbm_batch_set_schedule",
             "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_observables",
             "lbm_batch_get_populations", "lbm_batch_step_count", "lbm_batch_synchronize", "lbm_batch_destroy",
-            "lbm_batch_last_error", "lbm_adjoint_workspace_bytes", "lbm_forward_checkpointed", "lbm_backward"]
+            "lbm_batch_last_error", "lbm_adjoint_workspace_bytes", "lbm_forward_checkpointed", "lbm_backward",
+            "lbm3d_workspace_bytes", "lbm3d_create", "lbm3d_set_params", "lbm3d_init_equilibrium", "lbm3d_step",
+            "lbm3d_observables", "lbm3d_get_fields", "lbm3d_get_material", "lbm3d_get_populations",
+            "lbm3d_set_populations", "lbm3d_step_count", "lbm3d_synchronize", "lbm3d_destroy", "lbm3d_last_error"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -113,6 +123,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_adjoint_workspace_bytes": (sz, [vp, i64, ctypes.c_int32]),
         "lbm_forward_checkpointed": (ctypes.c_int, [vp, i64, ctypes.c_int32, vp, sz, P(ctypes.c_double)]),
         "lbm_backward": (ctypes.c_int, [vp, ctypes.c_double, vp, vp, vp]),
+        "lbm3d_workspace_bytes": (sz, [P(Geometry3D)]),
+        "lbm3d_create": (ctypes.c_int, [P(Geometry3D), vp, sz, vp, P(vp)]),
+        "lbm3d_set_params": (ctypes.c_int, [vp, P(Params), vp, vp, vp]),
+        "lbm3d_init_equilibrium": (ctypes.c_int, [vp]),
+        "lbm3d_step": (ctypes.c_int, [vp, i64]),
+        "lbm3d_observables": (ctypes.c_int, [vp, P(Obs)]),
+        "lbm3d_get_fields": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
+        "lbm3d_get_material": (ctypes.c_int, [vp, vp, vp, vp]),
+        "lbm3d_get_populations": (ctypes.c_int, [vp, vp]),
+        "lbm3d_set_populations": (ctypes.c_int, [vp, vp, i64]),
+        "lbm3d_step_count": (i64, [vp]),
+        "lbm3d_synchronize": (ctypes.c_int, [vp]),
+        "lbm3d_destroy": (None, [vp]),
+        "lbm3d_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -140,7 +164,9 @@ def params_from_workload(w: dict, **over) -> Params:
         if k in w:
             setattr(p, keymap.get(k, k), float(w[k]))
     if w.get("dp_over_hgdl", 0.0) > 0:
-        p.dp_lat = float(w["dp_over_hgdl"] * w["ny_gdl"])
+        p.dp_lat = float(w["dp_over_hgdl"] * w.get("ny_gdl", w.get("nz_gdl")))
+    if w.get("dp_lat", 0.0) > 0:
+        p.dp_lat = float(w["dp_lat"])
     for k, v in over.items():
         setattr(p, k, v)
     return p
@@ -296,6 +322,108 @@ class Cathode:
             if getattr(self, "ctx", None):
                 self.lib.lbm_synchronize(self.ctx)
                 self.lib.lbm_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+
+class Cathode3D:
+    """One 3D cathode lattice (D3Q19 + 2 x D3Q7, C ABI lbm3d_*) on the
+    current GPU.  ``phi``, ``inv_k``, ``d_eff``: optional per-cell
+    [nz, ny, nx] tensors."""
+
+    FIELDS = ("ux", "uy", "uz", "p", "T", "theta", "c")
+
+    def __init__(self, nx, ny, nz, nz_channel, nz_gdl, nz_cl, params: Params, precision=32, flags=0,
+                 phi=None, inv_k=None, d_eff=None, device=None):
+        if not torch.cuda.is_available():
+            raise LbmError("no GPU: the solver runs only on the HIP device")
+        self.lib = load_library()
+        self.device = torch.device(device or "cuda")
+        self.dtype = torch.float64 if precision == 64 else torch.float32
+        self.geom = Geometry3D(nx, ny, nz, nz_channel, nz_gdl, nz_cl, precision, flags)
+        self.shape = (nz, ny, nx)
+        nbytes = self.lib.lbm3d_workspace_bytes(ctypes.byref(self.geom))
+        if nbytes == 0:
+            raise LbmError("invalid 3D geometry")
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = ctypes.c_void_p()
+        self._check(self.lib.lbm3d_create(ctypes.byref(self.geom), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx)))
+        self.set_params(params, phi, inv_k, d_eff)
+        self.init_equilibrium()
+
+    @classmethod
+    def from_workload(cls, w: dict, phi=None, inv_k=None, d_eff=None, flags=0, **over):
+        return cls(w["nx"], w["ny"], w["nz"], w["nz_channel"], w["nz_gdl"], w["nz_cl"],
+                   params_from_workload(w, **over), precision=w.get("precision", 32), flags=flags, phi=phi,
+                   inv_k=inv_k, d_eff=d_eff)
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.lbm3d_last_error(self.ctx).decode() if self.ctx else ""
+            raise LbmError(f"{STATUS.get(st, st)}: {msg}")
+
+    def _dev(self, a):
+        if a is None:
+            return None
+        t = torch.as_tensor(a).to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(t.shape) != self.shape:
+            raise ValueError(f"per-cell array must be {list(self.shape)}")
+        return t
+
+    def set_params(self, params: Params, phi=None, inv_k=None, d_eff=None):
+        arrs = [self._dev(a) for a in (phi, inv_k, d_eff)]
+        self._check(self.lib.lbm3d_set_params(self.ctx, ctypes.byref(params), *[_ptr(a) for a in arrs]))
+        self.params = params
+
+    def init_equilibrium(self):
+        self._check(self.lib.lbm3d_init_equilibrium(self.ctx))
+
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm3d_step(self.ctx, int(n)))
+
+    @property
+    def step_count(self) -> int:
+        return int(self.lib.lbm3d_step_count(self.ctx))
+
+    def synchronize(self):
+        self._check(self.lib.lbm3d_synchronize(self.ctx))
+
+    def observables(self) -> dict:
+        o = Obs()
+        self._check(self.lib.lbm3d_observables(self.ctx, ctypes.byref(o)))
+        return {name: getattr(o, name) for name, _ in Obs._fields_}
+
+    def fields(self) -> dict:
+        out = {k: torch.empty(self.shape, dtype=self.dtype, device=self.device) for k in self.FIELDS}
+        self._check(self.lib.lbm3d_get_fields(self.ctx, *[_ptr(out[k]) for k in self.FIELDS]))
+        return out
+
+    def material(self) -> dict:
+        out = {k: torch.empty(self.shape, dtype=self.dtype, device=self.device) for k in ("phi", "inv_k", "d_eff")}
+        self._check(self.lib.lbm3d_get_material(self.ctx, _ptr(out["phi"]), _ptr(out["inv_k"]), _ptr(out["d_eff"])))
+        return out
+
+    def populations(self) -> torch.Tensor:
+        out = torch.empty((33,) + self.shape, dtype=self.dtype, device=self.device)
+        self._check(self.lib.lbm3d_get_populations(self.ctx, _ptr(out)))
+        return out
+
+    def set_populations(self, pops, step: int = 0):
+        t = torch.as_tensor(pops).to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(t.shape) != (33,) + self.shape:
+            raise ValueError("populations must be [33, nz, ny, nx]")
+        self._check(self.lib.lbm3d_set_populations(self.ctx, _ptr(t), int(step)))
+        self.synchronize()
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.lbm3d_synchronize(self.ctx)
+                self.lib.lbm3d_destroy(self.ctx)
                 self.ctx = None
         except Exception:
             pass

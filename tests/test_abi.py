@@ -18,7 +18,7 @@ def _declared():
         if fn.endswith(".h"):
             txt = open(os.path.join(inc, fn)).read()
             txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-            names |= set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt))
+            names |= set(re.findall(r"\b(lbm(?:3d)?_[a-z0-9_]+)\s*\(", txt))
     return names
 
 
@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
     declared = _declared()
     assert len(declared) >= 18
     out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
-    exported = set(re.findall(r"\b(lbm_[a-z0-9_]+)\b", out))
+    exported = set(re.findall(r"\b(lbm(?:3d)?_[a-z0-9_]+)\b", out))
     missing = declared - exported
     assert not missing, missing
     for name in declared:
@@ -52,6 +52,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(lbm.Geometry) == 28
     assert ctypes.sizeof(lbm.Params) == 28 * 8 + 8
     assert ctypes.sizeof(lbm.Obs) == 8 + 10 * 8
+    assert ctypes.sizeof(lbm.Geometry3D) == 32  # lbm3d_geometry: 8 x 4 bytes
 
 
 def test_defaults_are_the_paper_constants(lib):
@@ -82,3 +83,22 @@ def test_workspace_size_and_geometry_checks(lib):
     assert lib.lbm_create(ctypes.byref(g), None, 1 << 30, None, ctypes.byref(ctx)) == 1
     assert lib.lbm_create(ctypes.byref(g), ctypes.c_void_p(256), 16, None, ctypes.byref(ctx)) == 1
     assert lib.lbm_status_string(2) == b"parameters outside the stable range"
+
+
+def test_workspace_size_and_geometry_checks_3d(lib):
+    from paper_2103_01444_amd import lbm
+    g = lbm.Geometry3D(256, 128, 64, 32, 29, 3, 32, 0)
+    n = lib.lbm3d_workspace_bytes(ctypes.byref(g))
+    assert n >= 2 * 33 * 256 * 128 * 64 * 4 + 3 * 256 * 128 * 64 * 4
+    assert any(x in lbm.EXPORTED for x in ("lbm3d_step",))
+    for bad in (lbm.Geometry3D(2, 8, 8, 4, 3, 1, 32, 0),          # nx < 3
+                lbm.Geometry3D(16, 8, 8, 4, 3, 2, 32, 0),         # layers do not sum to nz
+                lbm.Geometry3D(16, 8, 8, 4, 3, 1, 16, 0),         # precision
+                lbm.Geometry3D(16, 8, 8, 4, 3, 1, 32, 32),        # unknown flag
+                lbm.Geometry3D(16, 0, 8, 4, 3, 1, 32, 0),         # empty y
+                lbm.Geometry3D(1024, 1024, 64, 32, 29, 3, 32, 0)):  # 32-bit offsets
+        assert lib.lbm3d_workspace_bytes(ctypes.byref(bad)) == 0
+    ctx = ctypes.c_void_p()
+    assert lib.lbm3d_create(ctypes.byref(g), None, n, None, ctypes.byref(ctx)) == 1
+    assert lib.lbm3d_create(ctypes.byref(g), ctypes.c_void_p(256), 16, None, ctypes.byref(ctx)) == 1
+    assert lib.lbm3d_create(ctypes.byref(g), ctypes.c_void_p(300), n, None, ctypes.byref(ctx)) == 1  # misaligned

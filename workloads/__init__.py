@@ -27,6 +27,15 @@ rate, permeability, porosity and effective diffusivity, Section 5):
 * ``adjoint2d_1024x256``: 1024x256, porosity field U[0.4,0.8] (seed
   21030146), 4000 steps, checkpoint every 200; 32 finite-difference cells
   drawn from the GDL (seed 21030147); a 64x16 copy for the oracle.
+* ``cathode3d_256x128x64``: 256 (x, along the channel) x 128 (y, across)
+  x 64 (z, through the layers): channel 32 layers, GDL 29, CL 3.  GDL
+  porosity from a seeded sphere pack (seed 21030148): spheres of radius 4
+  lattice units with centres uniform in the GDL box are added until the
+  solid fraction reaches 0.3; the solid indicator is averaged over a 9^3
+  box (truncated at the GDL faces) and porosity = 1 - that average (mean
+  0.7).  The CL is a planar layer of uniform porosity 0.7.  Kozeny-Carman
+  permeability with particle diameter 8 lattice units; Bruggeman
+  diffusivity; Re 20, 0.55 V, 353 K; FP32; 5000 steps.
 """
 from __future__ import annotations
 
@@ -36,6 +45,7 @@ SEED_ROOFLINE_PHI = 21030144
 SEED_BATCH = 21030145
 SEED_ADJOINT_PHI = 21030146
 SEED_ADJOINT_FD = 21030147
+SEED_SPHERE_PACK = 21030148
 
 
 def scaled_layers(ny: int) -> tuple[int, int, int]:
@@ -169,4 +179,99 @@ def random_populations(ny: int, nx: int, seed: int) -> np.ndarray:
     s[1:9] = rng.uniform(0.0, 0.02, size=(8, ny, nx))
     s[9:14] = rng.uniform(0.0, 0.4, size=(5, ny, nx))
     s[14:19] = rng.uniform(0.15, 0.25, size=(5, ny, nx))
+    return s
+
+
+# --------------------------------------------------------------------- 3D
+def scaled_layers3d(nz: int) -> tuple[int, int, int]:
+    """Channel / GDL / CL layer counts for ``nz`` layers, in the proportions
+    of the 64-layer case (32 / 29 / 3)."""
+    ch = int(0.5 * nz + 0.5)
+    cl = max(1, int(3.0 * nz / 64.0 + 0.5))
+    return ch, nz - ch - cl, cl
+
+
+def cathode3d_256x128x64() -> dict:
+    w = base_case()
+    w.update(name="cathode3d_256x128x64", nx=256, ny=128, nz=64, nz_channel=32, nz_gdl=29, nz_cl=3,
+             precision=32, steps=5000, Re=20.0, T_in=353.0, V_op=0.55, phi_gdl=0.7, dp_lat=8.0,
+             sphere_radius=4.0, solid_fraction=0.3, filter_box=9, phi_cl=0.7, phi_seed=SEED_SPHERE_PACK)
+    return w
+
+
+def cathode3d_scaled(nx: int, ny: int, nz: int, precision: int = 32, **over) -> dict:
+    """The 256x128x64 recipe at another lattice size (parity-test sizes)."""
+    w = cathode3d_256x128x64()
+    ch, gdl, cl = scaled_layers3d(nz)
+    w.update(name=f"cathode3d_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, nz_channel=ch, nz_gdl=gdl, nz_cl=cl,
+             precision=precision)
+    w.update(over)
+    return w
+
+
+def _box_mean(a: np.ndarray, k: int) -> np.ndarray:
+    """Mean over the k^d box centred on each cell, the box cut at the array
+    faces (separable: the cut box is a product of intervals)."""
+    h = k // 2
+    out = a.astype(np.float64)
+    for axis in range(a.ndim):
+        n = out.shape[axis]
+        c = np.concatenate([np.zeros_like(np.take(out, [0], axis=axis)), np.cumsum(out, axis=axis)], axis=axis)
+        lo = np.clip(np.arange(n) - h, 0, n)
+        hi = np.clip(np.arange(n) + h + 1, 0, n)
+        shape = [1] * a.ndim
+        shape[axis] = n
+        out = (np.take(c, hi, axis=axis) - np.take(c, lo, axis=axis)) / (hi - lo).reshape(shape)
+    return out
+
+
+def sphere_pack_solid(nx: int, ny: int, nz: int, radius: float, solid_fraction: float,
+                      seed: int) -> np.ndarray:
+    """Solid indicator [nz, ny, nx] (bool) of a random sphere pack: spheres
+    with centres uniform in the box are added (cells whose centres lie
+    within ``radius`` of a sphere centre become solid) until the solid
+    fraction reaches ``solid_fraction``."""
+    rng = np.random.default_rng(seed)
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    R = int(np.ceil(radius))
+    off = np.arange(-R, R + 1)
+    target = solid_fraction * solid.size
+    count = 0
+    while count < target:
+        cz, cy, cx = rng.uniform((0.0, 0.0, 0.0), (nz, ny, nx))
+        idx = []
+        for c, n in ((cz, nz), (cy, ny), (cx, nx)):
+            i = int(np.floor(c)) + off
+            idx.append(i[(i >= 0) & (i < n)])
+        dz, dy, dx = (idx[0] + 0.5 - cz), (idx[1] + 0.5 - cy), (idx[2] + 0.5 - cx)
+        inside = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2 <= radius * radius
+        sub = solid[idx[0][0]:idx[0][-1] + 1, idx[1][0]:idx[1][-1] + 1, idx[2][0]:idx[2][-1] + 1]
+        count += int((inside & ~sub).sum())
+        sub |= inside
+    return solid
+
+
+def sphere_pack_porosity(w: dict) -> np.ndarray:
+    """Per-cell porosity [nz, ny, nx] (float64) of a 3D workload: 1 in the
+    channel, the box-filtered sphere pack in the GDL, ``phi_cl`` in the CL."""
+    nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    ch, gdl = w["nz_channel"], w["nz_gdl"]
+    phi = np.ones((nz, ny, nx), dtype=np.float64)
+    if gdl > 0:
+        solid = sphere_pack_solid(nx, ny, gdl, w["sphere_radius"], w["solid_fraction"], w["phi_seed"])
+        phi[ch:ch + gdl] = 1.0 - _box_mean(solid, w["filter_box"])
+    phi[ch + gdl:] = w["phi_cl"]
+    return phi
+
+
+def random_populations3d(nz: int, ny: int, nx: int, seed: int) -> np.ndarray:
+    """An arbitrary, positive population state [33, nz, ny, nx] (float64):
+    planes 0-18 flow (rest near 1, moving near 0.01), 19-25 temperature
+    rise, 26-32 O2, in the magnitudes of the 3D workload."""
+    rng = np.random.default_rng(seed)
+    s = np.empty((33, nz, ny, nx), dtype=np.float64)
+    s[0] = rng.uniform(0.97, 1.0, size=(nz, ny, nx))
+    s[1:19] = rng.uniform(0.0, 0.01, size=(18, nz, ny, nx))
+    s[19:26] = rng.uniform(0.0, 0.3, size=(7, nz, ny, nx))
+    s[26:33] = rng.uniform(0.1, 0.2, size=(7, nz, ny, nx))
     return s
