@@ -19,7 +19,7 @@ namespace {
 
 constexpr size_t kAlign3 = 256;
 size_t align3(size_t v) { return (v + kAlign3 - 1) / kAlign3 * kAlign3; }
-constexpr int kChunkY = 16;  // y rows per chunk of the step's launch order
+constexpr int kChunkY = 64;  // y rows per chunk of the step's launch order (fastest of 1..128 at 256x128x64)
 
 struct Layout3 {
   int pitch = 0;

@@ -98,7 +98,10 @@ def test_one_step_from_arbitrary_state_3d(mode, precision, shape):
     ref = m.step(pops)
     err = float((out - ref).abs().max())
     print(f"3d one step {mode} fp{precision} {nx}x{ny}x{nz}: max |df| = {err:.2e}", flush=True)
-    assert err < (1e-13 if precision == 64 else 2e-6)
+    # FP32: rounding (6e-8) of populations up to ~2, amplified ~50x by the
+    # Arrhenius / Tafel exponent of the CL source (an argument of ~50 whose
+    # absolute FP32 error sets the relative error of the rate constant).
+    assert err < (1e-13 if precision == 64 else 1e-5 * float(ref.abs().max()))
 
 
 @pytest.mark.parametrize("flags", [1 | 2 | 16 | 4, 1 | 4 | 8, 2 | 16])
@@ -225,7 +228,7 @@ def test_full_size_3d_run_stays_bounded():
           f"util = {o['o2_utilisation']:.3e}", flush=True)
     assert o["current_density"] > 0 and o["T_max"] >= w["T_in"]
     assert float(f["c"].min()) >= 0.0
-    assert float(f["theta"].min()) > -1e-6
+    assert float(f["theta"].min()) > -1e-6 * float(f["theta"].max())  # FP32 rounding of a non-negative field
 
 
 def test_parameter_validation_3d():
