@@ -363,6 +363,17 @@ lbm_status lbm3d_synchronize(lbm3d_ctx* ctx);
 void lbm3d_destroy(lbm3d_ctx* ctx);
 const char* lbm3d_last_error(const lbm3d_ctx* ctx);
 
+/* Discrete adjoint of the 3D update: as lbm_adjoint_workspace_bytes,
+ * lbm_forward_checkpointed and lbm_backward (same conventions; J is the mean
+ * over the (x, y) area of the CL current density), gradients [nz][ny][nx].
+ * The workspace holds ceil(nsteps/every) + every + 2 states, so every near
+ * sqrt(nsteps) minimises it (5000 steps at 256x128x64 FP32, every 70:
+ * about 40 GB). */
+size_t lbm3d_adjoint_workspace_bytes(const lbm3d_ctx* ctx, int64_t nsteps, int32_t every);
+lbm_status lbm3d_forward_checkpointed(lbm3d_ctx* ctx, int64_t nsteps, int32_t every, void* dev_ws,
+                                      size_t ws_bytes, double* J_out);
+lbm_status lbm3d_backward(lbm3d_ctx* ctx, double dJ, void* grad_inv_k, void* grad_phi, void* grad_d_eff);
+
 #ifdef __cplusplus
 }
 #endif

@@ -96,6 +96,12 @@ struct lbm3d_ctx {
   Consts3<double> kd{};
   lbm::Derived d;
   std::string err;
+  // checkpointed forward run held for lbm3d_backward
+  char* adj_ws = nullptr;
+  int64_t adj_nsteps = 0;
+  int32_t adj_every = 0;
+  int64_t adj_step = -1;
+  bool adj_ready = false;
 
   void* state(int i) { return ws + L.off_state[i]; }
   void* mat_plane(int i) { return ws + L.off_mat + size_t(i) * L.plane * L.esize; }
@@ -366,6 +372,7 @@ lbm_status lbm3d_create(const lbm3d_geometry* g, void* dev_ws, size_t ws_bytes, 
 lbm_status lbm3d_set_params(lbm3d_ctx* c, const lbm_params* p, const void* phi, const void* inv_k, const void* d_eff) {
   if (!c || !p) return LBM_ERR_INVALID_ARG;
   c->params_set = false;
+  c->adj_ready = false;
   return c->g.precision == 64 ? set_params3_t<double>(c, p, phi, inv_k, d_eff)
                               : set_params3_t<float>(c, p, phi, inv_k, d_eff);
 }
@@ -373,6 +380,7 @@ lbm_status lbm3d_set_params(lbm3d_ctx* c, const lbm_params* p, const void* phi, 
 lbm_status lbm3d_init_equilibrium(lbm3d_ctx* c) {
   if (!c) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
+  c->adj_ready = false;
   c->cur = 0;
   c->step = 0;
   auto run = [&](auto tag) {
@@ -458,6 +466,7 @@ lbm_status lbm3d_set_populations(lbm3d_ctx* c, const void* src, int64_t step) {
     hipLaunchKernelGGL(k3_import<float>, c->grid3(), dim3(kBlock3), 0, c->stream, static_cast<const float*>(src),
                        static_cast<float*>(c->state(c->cur)), c->kf);
   c->step = step;
+  c->adj_ready = false;
   return check3(c, "set_populations");
 }
 
@@ -473,5 +482,133 @@ lbm_status lbm3d_synchronize(lbm3d_ctx* c) {
 void lbm3d_destroy(lbm3d_ctx* c) { delete c; }
 
 const char* lbm3d_last_error(const lbm3d_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Checkpointed forward run and discrete adjoint (lbm3d_forward_checkpointed,
+// lbm3d_backward).
+// ---------------------------------------------------------------------------
+#include "lbm3d_adjoint_kernels.hpp"
+
+namespace {
+
+struct AdjLayout3 {
+  size_t state = 0;
+  int nck = 0;
+  size_t off_ck = 0, off_replay = 0, off_lam = 0, off_grad = 0, total = 0;
+};
+
+AdjLayout3 adj_layout3(const lbm3d_ctx* c, int64_t nsteps, int32_t every) {
+  AdjLayout3 A;
+  A.state = c->L.state;
+  A.nck = int((nsteps + every - 1) / every);
+  size_t o = 0;
+  A.off_ck = o;
+  o += size_t(A.nck) * A.state;
+  A.off_replay = o;
+  o += size_t(every) * A.state;
+  A.off_lam = o;
+  o += 2 * A.state;
+  A.off_grad = o;
+  o += align3(size_t(3) * c->L.plane * c->L.esize);
+  A.total = o;
+  return A;
+}
+
+template <typename R>
+lbm_status backward3_t(lbm3d_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_d) {
+  const AdjLayout3 A = adj_layout3(c, c->adj_nsteps, c->adj_every);
+  char* ws = c->adj_ws;
+  const Mat3Ptrs<R> m = mat3_ptrs<R>(c);
+  const Consts3<R> k = consts3<R>(c);
+  const dim3 grid(unsigned(c->L.nblocks_obs));
+  R* grad = reinterpret_cast<R*>(ws + A.off_grad);
+  R* lam[2] = {reinterpret_cast<R*>(ws + A.off_lam), reinterpret_cast<R*>(ws + A.off_lam + A.state)};
+  const int64_t ngrad = int64_t(3) * c->L.plane;
+  hipLaunchKernelGGL(k3_fill<R>, dim3(unsigned((ngrad + kBlock3 - 1) / kBlock3)), dim3(kBlock3), 0, c->stream, grad,
+                     ngrad, R(0));
+  // Seed: adjoint of J = mean over (x, y) of sum_CL 4 F C_ref s_c / dt * dx.
+  const lbm_params& p = c->p;
+  const double w = dJ * c->d.dx / (double(c->g.nx) * c->g.ny) * 4.0 * p.faraday * p.C_ref / c->d.dt;
+  hipLaunchKernelGGL((k3_adj_step<R, true>), grid, dim3(kBlock3), 0, c->stream,
+                     static_cast<const R*>(c->state(c->cur)), static_cast<const R*>(nullptr), lam[0], grad, m.phi,
+                     m.invk, m.d, k, R(w));
+  int cur = 0;
+  for (int seg = A.nck - 1; seg >= 0; --seg) {
+    const int64_t start = int64_t(seg) * c->adj_every;
+    const int len = int(std::min<int64_t>(c->adj_every, c->adj_nsteps - start));
+    char* replay = ws + A.off_replay;
+    if (hipMemcpyAsync(replay, ws + A.off_ck + size_t(seg) * A.state, A.state, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      return fail3(c, LBM_ERR_DEVICE, "replay restore failed");
+    for (int j = 1; j < len; ++j)
+      hipLaunchKernelGGL((k3_step<R, MAT_FULL>), grid, dim3(kBlock3), 0, c->stream,
+                         reinterpret_cast<const R*>(replay + size_t(j - 1) * A.state),
+                         reinterpret_cast<R*>(replay + size_t(j) * A.state), m.phi, m.invk, m.d, k);
+    for (int j = len - 1; j >= 0; --j) {
+      hipLaunchKernelGGL((k3_adj_step<R, false>), grid, dim3(kBlock3), 0, c->stream,
+                         reinterpret_cast<const R*>(replay + size_t(j) * A.state), lam[cur], lam[cur ^ 1], grad,
+                         m.phi, m.invk, m.d, k, R(0));
+      cur ^= 1;
+    }
+  }
+  hipLaunchKernelGGL(k3_adj_init<R>, c->grid3(), dim3(kBlock3), 0, c->stream, lam[cur], grad, k);
+  void* outs[3] = {g_phi, g_invk, g_d};
+  for (int i = 0; i < 3; ++i)
+    if (outs[i])
+      hipLaunchKernelGGL(k3_unpitch<R>, c->grid3(), dim3(kBlock3), 0, c->stream, grad + size_t(i) * c->L.plane,
+                         static_cast<R*>(outs[i]), c->g.nx, c->g.ny, c->L.pitch);
+  if (lbm_status s = check3(c, "backward"); s != LBM_OK) return s;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail3(c, LBM_ERR_DEVICE, "backward sync failed");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm3d_adjoint_workspace_bytes(const lbm3d_ctx* c, int64_t nsteps, int32_t every) {
+  if (!c || nsteps < 1 || every < 1) return 0;
+  return adj_layout3(c, nsteps, every).total;
+}
+
+lbm_status lbm3d_forward_checkpointed(lbm3d_ctx* c, int64_t nsteps, int32_t every, void* dev_ws, size_t ws_bytes,
+                                      double* J_out) {
+  if (!c || nsteps < 1 || every < 1 || !dev_ws) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
+  if (c->mat != MAT_FULL)
+    return fail3(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
+  const AdjLayout3 A = adj_layout3(c, nsteps, every);
+  if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign3 != 0)
+    return fail3(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");
+  c->adj_ready = false;
+  if (lbm_status s = lbm3d_init_equilibrium(c); s != LBM_OK) return s;
+  c->adj_ws = static_cast<char*>(dev_ws);
+  c->adj_nsteps = nsteps;
+  c->adj_every = every;
+  const size_t sb = size_t(33) * c->L.plane * c->L.esize;
+  for (int seg = 0; seg < A.nck; ++seg) {
+    if (hipMemcpyAsync(c->adj_ws + A.off_ck + size_t(seg) * A.state, c->state(c->cur), sb, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      return fail3(c, LBM_ERR_DEVICE, "checkpoint copy failed");
+    const int64_t n = std::min<int64_t>(every, nsteps - int64_t(seg) * every);
+    if (lbm_status s = lbm3d_step(c, n); s != LBM_OK) return s;
+  }
+  lbm_obs o{};
+  if (lbm_status s = lbm3d_observables(c, &o); s != LBM_OK) return s;
+  if (J_out) *J_out = o.current_density;
+  c->adj_step = c->step;
+  c->adj_ready = true;
+  return LBM_OK;
+}
+
+lbm_status lbm3d_backward(lbm3d_ctx* c, double dJ, void* grad_inv_k, void* grad_phi, void* grad_d_eff) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->adj_ready || c->adj_step != c->step)
+    return fail3(c, LBM_ERR_STATE, "lbm3d_backward needs a preceding lbm3d_forward_checkpointed on the same state");
+  return c->g.precision == 64 ? backward3_t<double>(c, dJ, grad_inv_k, grad_phi, grad_d_eff)
+                              : backward3_t<float>(c, dJ, grad_inv_k, grad_phi, grad_d_eff);
+}
 
 }  // extern "C"

@@ -237,18 +237,7 @@ __device__ __forceinline__ Mat3<R> pre_collision(const R* __restrict__ src, cons
   return mb;
 }
 
-template <typename R>
-__device__ __forceinline__ lbm::React<R> reaction(R theta, R c, R rhocp, const Consts3<R>& k) {
-  const R T = k.T_in + theta;
-  const R iT = R(1) / T;
-  const R eta = k.V_op - (k.U0_slope * T + k.U0_icept);
-  const R kappa = exp(k.ln_k0 - k.E_over_R * (iT - k.inv_T_arrh) - k.aF_over_R * eta * iT);
-  lbm::React<R> r;
-  r.s_c = -c * expm1(-kappa);
-  r.ehs = eta + T * k.U0_slope;
-  r.S_T = k.four_f_cref * r.s_c * r.ehs / rhocp;
-  return r;
-}
+using lbm::reaction;  // the CL reaction of Eqs. 12-17 (shared with 2D)
 
 // Two-rate collision of every population of a node (flow with Guo's porous
 // forcing; scalars with the CL source injected with the rest weights).

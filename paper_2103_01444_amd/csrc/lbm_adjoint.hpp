@@ -189,8 +189,8 @@ struct ReactAdj {
   R s_c, S_T, ehs, dsc_dc, dsc_dth;
 };
 
-template <typename R>
-__device__ __forceinline__ ReactAdj<R> reaction_tape(R theta, R c, R rhocp, const Consts<R>& k) {
+template <typename R, typename K>
+__device__ __forceinline__ ReactAdj<R> reaction_tape(R theta, R c, R rhocp, const K& k) {
   const R T = k.T_in + theta;
   const R iT = R(1) / T;
   const R eta = k.V_op - (k.U0_slope * T + k.U0_icept);

@@ -399,6 +399,7 @@ lbm_status lbm_set_params(lbm_ctx* c, const lbm_params* p, const void* phi, cons
 lbm_status lbm_init_equilibrium(lbm_ctx* c) {
   if (!c) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  c->adj_ready = false;
   c->cur = 0;
   c->step = 0;
   if (c->g.precision == 64) launch_init<double>(c); else launch_init<float>(c);

@@ -321,8 +321,9 @@ struct React {
 // CL oxygen reduction over one step (Eqs. 12-17), integrated exactly in time:
 // kappa = a j0(T) exp(-alpha_c F eta / (R T)) dt / (4 F C_ref),
 // s_c = c (1 - exp(-kappa)), heat source 4 F C_ref s_c (eta + T dU0/dT) / (rho c_p).
-template <typename R>
-__device__ __forceinline__ React<R> reaction(R theta, R c, R rhocp, const Consts<R>& k) {
+// K: the launch constants (2D or 3D), which carry the same reaction fields.
+template <typename R, typename K>
+__device__ __forceinline__ React<R> reaction(R theta, R c, R rhocp, const K& k) {
   const R T = k.T_in + theta;
   const R iT = R(1) / T;
   const R eta = k.V_op - (k.U0_slope * T + k.U0_icept);

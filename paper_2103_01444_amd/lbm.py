@@ -74,7 +74,8 @@ EXPORTED = ["lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_set_
             "lbm_batch_last_error", "lbm_adjoint_workspace_bytes", "lbm_forward_checkpointed", "lbm_backward",
             "lbm3d_workspace_bytes", "lbm3d_create", "lbm3d_set_params", "lbm3d_init_equilibrium", "lbm3d_step",
             "lbm3d_observables", "lbm3d_get_fields", "lbm3d_get_material", "lbm3d_get_populations",
-            "lbm3d_set_populations", "lbm3d_step_count", "lbm3d_synchronize", "lbm3d_destroy", "lbm3d_last_error"]
+            "lbm3d_set_populations", "lbm3d_step_count", "lbm3d_synchronize", "lbm3d_destroy", "lbm3d_last_error",
+            "lbm3d_adjoint_workspace_bytes", "lbm3d_forward_checkpointed", "lbm3d_backward"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -137,6 +138,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm3d_synchronize": (ctypes.c_int, [vp]),
         "lbm3d_destroy": (None, [vp]),
         "lbm3d_last_error": (ctypes.c_char_p, [vp]),
+        "lbm3d_adjoint_workspace_bytes": (sz, [vp, i64, ctypes.c_int32]),
+        "lbm3d_forward_checkpointed": (ctypes.c_int, [vp, i64, ctypes.c_int32, vp, sz, P(ctypes.c_double)]),
+        "lbm3d_backward": (ctypes.c_int, [vp, ctypes.c_double, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -419,6 +423,26 @@ class Cathode3D:
         self._check(self.lib.lbm3d_set_populations(self.ctx, _ptr(t), int(step)))
         self.synchronize()
 
+    def forward_checkpointed(self, nsteps: int, every: int = 100) -> float:
+        """Run nsteps steps from equilibrium keeping a checkpoint every
+        ``every`` steps; returns the mean current density J (A/cm^2)."""
+        n = self.lib.lbm3d_adjoint_workspace_bytes(self.ctx, int(nsteps), int(every))
+        if n == 0:
+            raise LbmError("invalid adjoint run length")
+        self.adj_ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        J = ctypes.c_double()
+        self._check(self.lib.lbm3d_forward_checkpointed(self.ctx, int(nsteps), int(every), _ptr(self.adj_ws), n,
+                                                        ctypes.byref(J)))
+        return J.value
+
+    def backward(self, dJ: float = 1.0) -> dict:
+        """dJ times the gradient of J with respect to the per-cell 1/K,
+        porosity and D_eff, as [nz, ny, nx] tensors."""
+        out = {k: torch.empty(self.shape, dtype=self.dtype, device=self.device) for k in ("inv_k", "phi", "d_eff")}
+        self._check(self.lib.lbm3d_backward(self.ctx, float(dJ), _ptr(out["inv_k"]), _ptr(out["phi"]),
+                                            _ptr(out["d_eff"])))
+        return out
+
     def __del__(self):
         try:
             if getattr(self, "ctx", None):
@@ -544,19 +568,19 @@ class BatchedSweep:
 class CurrentDensity(torch.autograd.Function):
     """J = mean current density after ``nsteps`` steps of a cathode whose
     porous layers are given cell by cell: 1/K (``inv_k``), porosity
-    (``phi``) and O2 diffusivity (``d_eff``), all [ny, nx] CUDA tensors in
-    lattice units.  ``backward`` runs the library's hand-written discrete
-    adjoint (checkpointed recomputation every ``every`` steps).
+    (``phi``) and O2 diffusivity (``d_eff``), all [ny, nx] (2D workload) or
+    [nz, ny, nx] (3D workload, one with ``nz``) CUDA tensors in lattice
+    units.  ``backward`` runs the library's hand-written discrete adjoint
+    (checkpointed recomputation every ``every`` steps).
 
         J = CurrentDensity.apply(inv_k, phi, d_eff, workload, nsteps, every)
     """
 
     @staticmethod
     def forward(ctx, inv_k, phi, d_eff, workload: dict, nsteps: int, every: int = 200):
-        params = params_from_workload(workload, independent_fields=1)
-        sim = Cathode(workload["nx"], workload["ny"], workload["ny_channel"], workload["ny_gdl"],
-                      workload["ny_cl"], params, precision=workload.get("precision", 32),
-                      phi=phi.detach(), inv_k=inv_k.detach(), d_eff=d_eff.detach())
+        cls = Cathode3D if "nz" in workload else Cathode
+        sim = cls.from_workload(workload, phi=phi.detach(), inv_k=inv_k.detach(), d_eff=d_eff.detach(),
+                                independent_fields=1)
         J = sim.forward_checkpointed(nsteps, every)
         ctx.sim = sim
         return torch.tensor(J, dtype=torch.float64, device=phi.device)

@@ -46,6 +46,7 @@ SEED_BATCH = 21030145
 SEED_ADJOINT_PHI = 21030146
 SEED_ADJOINT_FD = 21030147
 SEED_SPHERE_PACK = 21030148
+SEED_ADJOINT3D_FD = 21030149
 
 
 def scaled_layers(ny: int) -> tuple[int, int, int]:
@@ -275,3 +276,20 @@ def random_populations3d(nz: int, ny: int, nx: int, seed: int) -> np.ndarray:
     s[19:26] = rng.uniform(0.0, 0.3, size=(7, nz, ny, nx))
     s[26:33] = rng.uniform(0.1, 0.2, size=(7, nz, ny, nx))
     return s
+
+
+def fd_cells3d(w: dict, n: int = 8, seed: int = SEED_ADJOINT3D_FD, depth: int = 6) -> list[tuple[int, int, int]]:
+    """``n`` distinct porous cells (z, y, x), seeded, for finite-difference
+    checks of the 3D adjoint: drawn from the ``depth`` GDL layers next to
+    the CL and the CL layers, away from the x ends."""
+    rng = np.random.default_rng(seed)
+    z0 = max(w["nz_channel"], w["nz"] - w["nz_cl"] - depth)
+    layers = w["nz"] - z0
+    nx_in = w["nx"] - 4
+    flat = rng.choice(layers * w["ny"] * nx_in, size=n, replace=False)
+    out = []
+    for i in flat:
+        z, r = divmod(int(i), w["ny"] * nx_in)
+        y, x = divmod(r, nx_in)
+        out.append((z0 + z, y, x + 2))
+    return out
