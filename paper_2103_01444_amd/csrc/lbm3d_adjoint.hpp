@@ -214,15 +214,18 @@ __device__ __forceinline__ void collide_adj(const R (&f)[33], const Mat3<R>& mt,
     const R X = s == 0 ? th : c;
     const R aw = s == 0 ? mt.aT : mt.aC;
     const R src = s == 0 ? srcT : srcC;
-    o[0] = (R(1) - qp) * a[0];
-    R lx = qp * (R(1) - R(6) * aw) * a[0];
-    R law = (R(-6) * qp * X - R(6) * src) * a[0];
-    R ls = (R(1) - R(6) * aw) * a[0];
+    // The forward sets the rest population to X + src minus the six moving
+    // ones: its adjoint a[0] goes to X and src, and is taken off the moving.
+    o[0] = R(0);
+    R lx = a[0];
+    R law = R(0);
+    R ls = a[0];
 #pragma unroll
     for (int pr = 0; pr < 3; ++pr) {
       const int i = 2 * pr + 1, j = i + 1;
       const R eu = R(EX[19 + i]) * t.ux + R(EY[19 + i]) * t.uy + R(EZ[19 + i]) * t.uz;
-      const R lnp = a[i] + a[j], lnm = a[i] - a[j];
+      const R ai = a[i] - a[0], aj = a[j] - a[0];
+      const R lnp = ai + aj, lnm = ai - aj;
       o[i] = R(0.5) * (R(1) - qp) * lnp + R(0.5) * (R(1) - qm) * lnm;
       o[j] = R(0.5) * (R(1) - qp) * lnp - R(0.5) * (R(1) - qm) * lnm;
       lx += qp * aw * lnp + qm * R(0.5) * eu * lnm;
