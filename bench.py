@@ -23,25 +23,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_LU_POPS = 19 * 4 * 2  # 19 FP32 populations read and written per lattice update
 BYTES_PER_LU_PHI = 4            # per-cell porosity read
-COUNTERS = os.path.join(ROOT, "profiles", "step2d_4096x1024_fp32_counters.json")
+# Committed rocprofv3 counter summaries (HBM bytes per launch) and the
+# sources of the kernel each one measured.
+COUNTERS = {
+    "step2d": (os.path.join(ROOT, "profiles", "step2d_4096x1024_fp32_counters.json"),
+               ("lbm_device.hpp", "lbm_kernels2d.hpp")),
+    "step3d": (os.path.join(ROOT, "profiles", "step3d_256x128x64_fp32_counters.json"),
+               ("lbm_device.hpp", "lbm_kernels2d.hpp", "lbm3d_device.hpp", "lbm3d_kernels.hpp")),
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(which: str = "step2d") -> str:
     h = hashlib.sha256()
-    for fn in ("lbm_device.hpp", "lbm_kernels2d.hpp"):
+    for fn in COUNTERS[which][1]:
         with open(os.path.join(ROOT, "paper_2103_01444_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(per_launch_cells: int):
+def measured_traffic(per_launch_cells: int, which: str = "step2d"):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None
     if the kernel source changed since they were taken."""
-    if not os.path.exists(COUNTERS):
+    path = COUNTERS[which][0]
+    if not os.path.exists(path):
         return None
-    with open(COUNTERS) as f:
+    with open(path) as f:
         c = json.load(f)
-    if c.get("kernel_source_hash") != kernel_source_hash() or c.get("cells") != per_launch_cells:
+    if c.get("kernel_source_hash") != kernel_source_hash(which) or c.get("cells") != per_launch_cells:
         return None
     return c.get("hbm_bytes_per_launch")
 
@@ -123,7 +131,7 @@ def bench_batched(steps: int, seq_steps: int) -> dict:
             "mean_current_density_A_cm2": float(np.mean([o["current_density"] for o in obs]))}
 
 
-ADJ_BYTES_PER_LU = 19 * 4 * 4 + 3 * 4 + 3 * 4 * 2  # reverse step: S, lambda in/out pushes, 3 fields, gradient RMW
+ADJ_BYTES_PER_LU = 19 * 4 * 3 + 3 * 4 + 3 * 4 * 2  # reverse step: pull S, read lambda, push lambda', 3 fields, gradient RMW
 FWD_FULL_BYTES_PER_LU = 19 * 4 * 2 + 3 * 4          # replayed forward step with three per-cell fields
 
 
@@ -183,9 +191,44 @@ def bench_3d(steps: int, warmup: int = 50) -> dict:
                        "algorithmic_bytes_per_launch": cells * BYTES_PER_LU_3D,
                        "bytes_per_lattice_update": BYTES_PER_LU_3D},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4)},
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(cells, "step3d")},
             "observables": {"current_density_A_cm2": obs["current_density"], "T_max_K": obs["T_max"],
                             "o2_utilisation": obs["o2_utilisation"]}}
+
+
+ADJ3_BYTES_PER_LU = 33 * 4 * 3 + 3 * 4 + 3 * 4 * 2  # 3D reverse step, same streams as in 2D
+FWD3_FULL_BYTES_PER_LU = 33 * 4 * 2 + 3 * 4         # replayed 3D forward step with three per-cell fields
+
+
+def bench_adjoint3d(nsteps: int = 5000, every: int = 70) -> dict:
+    """256x128x64 FP32 sphere pack with per-cell (porosity, 1/K, D_eff):
+    plain forward, checkpointed forward and the hand-written 3D adjoint."""
+    import workloads as W
+    from paper_2103_01444_amd import Cathode3D
+
+    w = W.cathode3d_256x128x64()
+    sim = Cathode3D.from_workload(w, phi=W.sphere_pack_porosity(w), independent_fields=1)
+    cells = w["nx"] * w["ny"] * w["nz"]
+    sim.step(20)
+    wall_f, _ = _timed(sim.stream, lambda: sim.step(nsteps))
+    res = {}
+    wall_cf, _ = _timed(sim.stream, lambda: res.update(J=sim.forward_checkpointed(nsteps, every)))
+    wall_b, _ = _timed(sim.stream, lambda: res.update(g=sim.backward(1.0)))
+    g = res["g"]
+    achieved = cells * nsteps * (ADJ3_BYTES_PER_LU + FWD3_FULL_BYTES_PER_LU) / wall_b / 1e9
+    out = {"workload": w["name"], "cells": cells, "steps": nsteps, "checkpoint_every": every,
+           "workspace_GB": round(sim.adj_ws.numel() / 1e9, 2),
+           "forward": {"value": round(cells * nsteps / wall_f / 1e6, 1), "unit": "MLUPS"},
+           "forward_checkpointed": {"value": round(cells * nsteps / wall_cf / 1e6, 1), "unit": "MLUPS"},
+           "adjoint": {"value": round(cells * nsteps / wall_b / 1e6, 1), "unit": "MLUPS", "seconds": round(wall_b, 4)},
+           "adjoint_over_forward_time": round(wall_b / wall_f, 3),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "bytes_per_lattice_update": ADJ3_BYTES_PER_LU + FWD3_FULL_BYTES_PER_LU},
+           "J_A_cm2": res["J"],
+           "max_abs_grad_inv_k": float(g["inv_k"].abs().max())}
+    del sim, g, res
+    return out
 
 
 def main():
@@ -197,6 +240,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=500, help="0 skips the batched sweep")
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint")
     ap.add_argument("--steps3d", type=int, default=5000, help="0 skips the 3D cathode")
+    ap.add_argument("--adjoint3d-steps", type=int, default=5000, help="0 skips the 3D adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write copy kernel 5 times (counter calibration)")
     args = ap.parse_args()
@@ -290,6 +334,11 @@ def main():
         line["cathode3d"] = bench_3d(args.steps3d)
         print(f"bench: 3D {line['cathode3d']['value']} MLUPS, {line['cathode3d']['roofline']['achieved']} GB/s",
               file=sys.stderr, flush=True)
+    if args.adjoint3d_steps > 0:
+        print("bench: 3D adjoint", file=sys.stderr, flush=True)
+        line["adjoint3d"] = bench_adjoint3d(args.adjoint3d_steps)
+        print(f"bench: 3D adjoint {line['adjoint3d']['adjoint']['value']} MLUPS, "
+              f"{line['adjoint3d']['adjoint_over_forward_time']}x forward time", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, phi)
     print(json.dumps(line), flush=True)

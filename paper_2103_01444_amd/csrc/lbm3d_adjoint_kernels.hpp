@@ -41,8 +41,31 @@ __device__ __forceinline__ void node_mu(const R (&pre)[33], const Mat3<R>& mt, c
   }
 }
 
-// One reverse step: lam_out = (dS'/dS)^T lam_in at the state S, gradients
-// accumulated into grad (planes phi, 1/K, D_eff).  SEED: lam_out = w dJ/dS.
+// Push: the adjoint of the pulled element (x - e_q, q), or of the
+// bounced-back (x, opp q), is mu[q].  ADD: add to what is there.
+template <typename R, bool ADD>
+__device__ __forceinline__ void push(R* __restrict__ lam_out, const Consts3<R>& k, int x, int y, int z,
+                                     const R (&mu)[33]) {
+  const bool px = k.flags & F_PERIODIC_X, py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
+  const int rowp = k.pitch * k.ny;
+  const int o = z * rowp + y * k.pitch + x;
+#pragma unroll
+  for (int q = 0; q < 33; ++q) {
+    int xs = x - EX[q], ys = y - EY[q], zs = z - EZ[q];
+    if (px) xs = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
+    if (py) ys = ys < 0 ? ys + k.ny : (ys >= k.ny ? ys - k.ny : ys);
+    if (pz) zs = zs < 0 ? zs + k.nz : (zs >= k.nz ? zs - k.nz : zs);
+    const bool in = (unsigned)xs < (unsigned)k.nx && (unsigned)ys < (unsigned)k.ny && (unsigned)zs < (unsigned)k.nz;
+    const int off = in ? (q * k.plane + zs * rowp + ys * k.pitch + xs) : (OPP[q] * k.plane + o);
+    if constexpr (ADD) lam_out[off] += mu[q]; else lam_out[off] = mu[q];
+  }
+}
+
+// One reverse step, interior pass: lam_out = (dS'/dS)^T lam_in at the state
+// S without the boundary-column terms, gradients accumulated into grad
+// (planes phi, 1/K, D_eff).  Boundary nodes push zeros (the values of their
+// own pull are never read by the forward step) and leave their gradient to
+// the boundary pass.  SEED: lam_out = w dJ/dS.
 template <typename R, bool SEED>
 __global__ __launch_bounds__(kBlock3) void k3_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
                                                        R* __restrict__ lam_out, R* __restrict__ grad,
@@ -53,96 +76,127 @@ __global__ __launch_bounds__(kBlock3) void k3_adj_step(const R* __restrict__ S, 
   if (x >= k.nx) return;
   const bool open = !(k.flags & F_PERIODIC_X);
   const bool cl = !(k.flags & F_NO_REACTION) && z >= k.z_cl0;
-  const bool inlet = open && x == 0 && z < k.nz_ch;
-  const bool outlet = open && x == k.nx - 1;
-  const int xp = inlet ? 1 : (outlet ? k.nx - 2 : x);
-  const int row = (z * k.ny + y) * k.pitch;
-  const int o = row + x;
-
-  R p[33];
-  pull(S, k, xp, y, z, p);
-  const Mat3<R> mxp = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xp, y, z);
-  MatAdj3<R> ma{};
+  const bool boundary = open && ((x == 0 && z < k.nz_ch) || x == k.nx - 1);
   R mu[33];
-  if (inlet || outlet) {
-    // Boundary node: its collision adjoint and the material part of its
-    // extrapolation; the values of its own pull are never read.
-    Mat3<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y, z);
-    R pre[33];
-#pragma unroll
-    for (int q = 0; q < 33; ++q) pre[q] = p[q];
-    boundary_column(pre, k, y, z, inlet, mxp, mb);
-    if (outlet) {
-      mb.aT = mxp.aT;
-      mb.aC = mxp.aC;
-      mb.rhocp = mxp.rhocp;
-    }
-    node_mu<R, SEED>(pre, mb, k, cl, lam_in, o, w, mu, ma);
-    R dmu[33];
-#pragma unroll
-    for (int q = 0; q < 33; ++q) dmu[q] = R(0);
-    MatAdj3<R> dmaxp{};
-    boundary_adj(p, mxp, mb, k, inlet, inlet ? inlet_velocity(k, y, z) : R(0), mu, dmu, dmaxp, ma);
-    if (outlet) {  // the outlet's scalar material is column nx-2's: that thread takes these terms
-      ma.aT = R(0);
-      ma.aC = R(0);
-      ma.rhocp = R(0);
-    }
-    R g0 = R(0), g1 = R(0), g2 = R(0);
-    material_adj(k, mb, ma, g0, g1, g2);
-    grad[o] += g0;
-    grad[k.plane + o] += g1;
-    grad[2 * k.plane + o] += g2;
+  if (boundary) {
 #pragma unroll
     for (int q = 0; q < 33; ++q) mu[q] = R(0);
   } else {
-    node_mu<R, SEED>(p, mxp, k, cl, lam_in, o, w, mu, ma);
-    // A column feeding a boundary node adds that node's adjoint through the
-    // extrapolation (recomputed here: every thread writes only its own data).
-    const bool feeds_inlet = open && x == 1 && z < k.nz_ch;
-    const bool feeds_outlet = open && x == k.nx - 2;
-    if (feeds_inlet || feeds_outlet) {
-      const int xb = feeds_inlet ? 0 : k.nx - 1;
-      Mat3<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xb, y, z);
-      R pre[33];
-#pragma unroll
-      for (int q = 0; q < 33; ++q) pre[q] = p[q];
-      boundary_column(pre, k, y, z, feeds_inlet, mxp, mb);
-      if (feeds_outlet) {
-        mb.aT = mxp.aT;
-        mb.aC = mxp.aC;
-        mb.rhocp = mxp.rhocp;
-      }
-      R mub[33];
-      MatAdj3<R> dmab{};
-      node_mu<R, SEED>(pre, mb, k, cl, lam_in, row + xb, w, mub, dmab);
-      if (feeds_outlet) {  // the outlet node collides with this column's scalar material
-        ma.aT += dmab.aT;
-        ma.aC += dmab.aC;
-        ma.rhocp += dmab.rhocp;
-      }
-      MatAdj3<R> dmab2{};
-      boundary_adj(p, mxp, mb, k, feeds_inlet, feeds_inlet ? inlet_velocity(k, y, z) : R(0), mub, mu, ma, dmab2);
-    }
+    const int o = (z * k.ny + y) * k.pitch + x;
+    R p[33];
+    pull(S, k, x, y, z, p);
+    const Mat3<R> mt = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y, z);
+    MatAdj3<R> ma{};
+    node_mu<R, SEED>(p, mt, k, cl, lam_in, o, w, mu, ma);
     R g0 = R(0), g1 = R(0), g2 = R(0);
-    material_adj(k, mxp, ma, g0, g1, g2);
+    material_adj(k, mt, ma, g0, g1, g2);
     grad[o] += g0;
     grad[k.plane + o] += g1;
     grad[2 * k.plane + o] += g2;
   }
-  // Push: the adjoint of the pulled element (x - e_q, q), or of the
-  // bounced-back (x, opp q), is mu[q].
+  push<R, false>(lam_out, k, x, y, z, mu);
+}
+
+// Values per boundary slot in the side buffer: the feeding column's share of
+// the adjoint (33) and of its gradient (3).  Slots are [side][row], side 0
+// the inlet node of the row, side 1 the outlet node; stored plane by plane.
+constexpr int kSideVals = 36;
+
+// One reverse step, boundary pass (open x only; reads what the interior
+// pass reads, writes only the boundary nodes' gradient and the side buffer,
+// so it may run concurrently with the interior pass): one thread per
+// boundary node b fed by column xp computes b's collision adjoint on b's
+// pre-collision populations and the transposed extrapolation.
+template <typename R, bool SEED>
+__global__ __launch_bounds__(64) void k3_adj_bnd(const R* __restrict__ S, const R* __restrict__ lam_in,
+                                                 R* __restrict__ grad, R* __restrict__ side,
+                                                 const R* __restrict__ phi_f, const R* __restrict__ invk_f,
+                                                 const R* __restrict__ d_f, Consts3<R> k, R w) {
+  const int nrows = k.ny * k.nz;
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= 2 * nrows) return;
+  const bool inlet = t < nrows;
+  const int r = inlet ? t : t - nrows;
+  const int z = r / k.ny, y = r - z * k.ny;
+  if (inlet && z >= k.nz_ch) return;
+  const bool cl = !(k.flags & F_NO_REACTION) && z >= k.z_cl0;
+  const int xb = inlet ? 0 : k.nx - 1, xp = inlet ? 1 : k.nx - 2;
+  const int row = (z * k.ny + y) * k.pitch;
+  R p[33];
+  pull(S, k, xp, y, z, p);
+  const Mat3<R> mxp = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xp, y, z);
+  Mat3<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xb, y, z);
+  if (!inlet) {  // the outlet node collides with column nx-2's scalar material
+    mb.aT = mxp.aT;
+    mb.aC = mxp.aC;
+    mb.rhocp = mxp.rhocp;
+  }
+  MatAdj3<R> mab{}, maxp{};
+  R mub[33];
+  {
+    R pre[33];
+#pragma unroll
+    for (int q = 0; q < 33; ++q) pre[q] = p[q];
+    boundary_column(pre, k, y, z, inlet, mxp, mb);
+    node_mu<R, SEED>(pre, mb, k, cl, lam_in, row + xb, w, mub, mab);
+  }
+  R dmu[33];
+#pragma unroll
+  for (int q = 0; q < 33; ++q) dmu[q] = R(0);
+  boundary_adj(p, mxp, mb, k, inlet, inlet ? inlet_velocity(k, y, z) : R(0), mub, dmu, maxp, mab);
+  if (!inlet) {
+    maxp.aT += mab.aT;
+    maxp.aC += mab.aC;
+    maxp.rhocp += mab.rhocp;
+    mab.aT = mab.aC = mab.rhocp = R(0);
+  }
+  R g0 = R(0), g1 = R(0), g2 = R(0);
+  material_adj(k, mb, mab, g0, g1, g2);
+  grad[row + xb] += g0;
+  grad[k.plane + row + xb] += g1;
+  grad[2 * k.plane + row + xb] += g2;
+  g0 = g1 = g2 = R(0);
+  material_adj(k, mxp, maxp, g0, g1, g2);
+  const int slots = 2 * nrows;
+#pragma unroll
+  for (int q = 0; q < 33; ++q) side[q * slots + t] = dmu[q];
+  side[33 * slots + t] = g0;
+  side[34 * slots + t] = g1;
+  side[35 * slots + t] = g2;
+}
+
+// One reverse step, apply pass (after both): one thread per (row,
+// population) adds the inlet and then the outlet slot to the element the
+// feeding column pushed (one after the other, so nx = 3, where both feed
+// column 1, is safe); population 0's thread also adds the gradient shares.
+template <typename R>
+__global__ __launch_bounds__(kBlock3) void k3_adj_apply(const R* __restrict__ side, R* __restrict__ lam_out,
+                                                        R* __restrict__ grad, Consts3<R> k) {
+  const int nrows = k.ny * k.nz;
+  const int t = blockIdx.x * kBlock3 + threadIdx.x;
+  if (t >= 33 * nrows) return;
+  const int q = t / nrows, r = t - q * nrows;
+  const int z = r / k.ny, y = r - z * k.ny;
+  const int slots = 2 * nrows;
   const bool px = k.flags & F_PERIODIC_X, py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
   const int rowp = k.pitch * k.ny;
-#pragma unroll
-  for (int q = 0; q < 33; ++q) {
-    int xs = x - EX[q], ys = y - EY[q], zs = z - EZ[q];
+  for (int s = 0; s < 2; ++s) {
+    if (s == 0 && z >= k.nz_ch) continue;
+    const int slot = s * nrows + r;
+    const int xp = s == 0 ? 1 : k.nx - 2;
+    int xs = xp - EX[q], ys = y - EY[q], zs = z - EZ[q];
     if (px) xs = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
     if (py) ys = ys < 0 ? ys + k.ny : (ys >= k.ny ? ys - k.ny : ys);
     if (pz) zs = zs < 0 ? zs + k.nz : (zs >= k.nz ? zs - k.nz : zs);
     const bool in = (unsigned)xs < (unsigned)k.nx && (unsigned)ys < (unsigned)k.ny && (unsigned)zs < (unsigned)k.nz;
+    const int o = z * rowp + y * k.pitch + xp;
     const int off = in ? (q * k.plane + zs * rowp + ys * k.pitch + xs) : (OPP[q] * k.plane + o);
-    lam_out[off] = mu[q];
+    lam_out[off] += side[q * slots + slot];
+    if (q == 0) {
+      grad[o] += side[33 * slots + slot];
+      grad[k.plane + o] += side[34 * slots + slot];
+      grad[2 * k.plane + o] += side[35 * slots + slot];
+    }
   }
 }
 

@@ -102,6 +102,9 @@ struct lbm3d_ctx {
   int32_t adj_every = 0;
   int64_t adj_step = -1;
   bool adj_ready = false;
+  // second stream for the boundary pass of the reverse sweep, and its events
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_in = nullptr, ev_bnd = nullptr;
 
   void* state(int i) { return ws + L.off_state[i]; }
   void* mat_plane(int i) { return ws + L.off_mat + size_t(i) * L.plane * L.esize; }
@@ -479,7 +482,16 @@ lbm_status lbm3d_synchronize(lbm3d_ctx* c) {
   return LBM_OK;
 }
 
-void lbm3d_destroy(lbm3d_ctx* c) { delete c; }
+void lbm3d_destroy(lbm3d_ctx* c) {
+  if (!c) return;
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+  }
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_bnd) (void)hipEventDestroy(c->ev_bnd);
+  delete c;
+}
 
 const char* lbm3d_last_error(const lbm3d_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
@@ -496,7 +508,7 @@ namespace {
 struct AdjLayout3 {
   size_t state = 0;
   int nck = 0;
-  size_t off_ck = 0, off_replay = 0, off_lam = 0, off_grad = 0, total = 0;
+  size_t off_ck = 0, off_replay = 0, off_lam = 0, off_grad = 0, off_side = 0, total = 0;
 };
 
 AdjLayout3 adj_layout3(const lbm3d_ctx* c, int64_t nsteps, int32_t every) {
@@ -512,8 +524,37 @@ AdjLayout3 adj_layout3(const lbm3d_ctx* c, int64_t nsteps, int32_t every) {
   o += 2 * A.state;
   A.off_grad = o;
   o += align3(size_t(3) * c->L.plane * c->L.esize);
+  A.off_side = o;
+  o += align3(size_t(kSideVals) * 2 * c->g.ny * c->g.nz * c->L.esize);
   A.total = o;
   return A;
+}
+
+// One reverse step: interior pass on the context stream and, for an open
+// channel, the boundary pass on the second stream at the same time (both
+// wait for what precedes on the context stream), then the apply pass.
+template <typename R, bool SEED>
+lbm_status reverse_step3(lbm3d_ctx* c, const R* S, const R* lam_in, R* lam_out, R* grad, R* side, R w) {
+  const Mat3Ptrs<R> m = mat3_ptrs<R>(c);
+  const Consts3<R>& k = consts3<R>(c);
+  const bool open = !(c->g.flags & LBM_PERIODIC_X);
+  const int nrows = c->g.ny * c->g.nz;
+  if (open) {
+    if (hipEventRecord(c->ev_in, c->stream) != hipSuccess || hipStreamWaitEvent(c->aux, c->ev_in, 0) != hipSuccess)
+      return fail3(c, LBM_ERR_DEVICE, "boundary pass ordering failed");
+    hipLaunchKernelGGL((k3_adj_bnd<R, SEED>), dim3(unsigned((2 * nrows + 63) / 64)), dim3(64), 0, c->aux, S, lam_in,
+                       grad, side, m.phi, m.invk, m.d, k, w);
+    if (hipEventRecord(c->ev_bnd, c->aux) != hipSuccess) return fail3(c, LBM_ERR_DEVICE, "boundary pass event failed");
+  }
+  hipLaunchKernelGGL((k3_adj_step<R, SEED>), dim3(unsigned(c->L.nblocks_obs)), dim3(kBlock3), 0, c->stream, S, lam_in,
+                     lam_out, grad, m.phi, m.invk, m.d, k, w);
+  if (open) {
+    if (hipStreamWaitEvent(c->stream, c->ev_bnd, 0) != hipSuccess)
+      return fail3(c, LBM_ERR_DEVICE, "boundary pass join failed");
+    hipLaunchKernelGGL(k3_adj_apply<R>, dim3(unsigned((33 * int64_t(nrows) + kBlock3 - 1) / kBlock3)), dim3(kBlock3), 0,
+                       c->stream, side, lam_out, grad, k);
+  }
+  return LBM_OK;
 }
 
 template <typename R>
@@ -524,16 +565,27 @@ lbm_status backward3_t(lbm3d_ctx* c, double dJ, void* g_invk, void* g_phi, void*
   const Consts3<R> k = consts3<R>(c);
   const dim3 grid(unsigned(c->L.nblocks_obs));
   R* grad = reinterpret_cast<R*>(ws + A.off_grad);
+  R* side = reinterpret_cast<R*>(ws + A.off_side);
   R* lam[2] = {reinterpret_cast<R*>(ws + A.off_lam), reinterpret_cast<R*>(ws + A.off_lam + A.state)};
+  if (!c->aux) {
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+      c->aux = nullptr;
+      return fail3(c, LBM_ERR_DEVICE, "second stream creation failed");
+    }
+    if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_bnd, hipEventDisableTiming) != hipSuccess)
+      return fail3(c, LBM_ERR_DEVICE, "event creation failed");
+  }
   const int64_t ngrad = int64_t(3) * c->L.plane;
   hipLaunchKernelGGL(k3_fill<R>, dim3(unsigned((ngrad + kBlock3 - 1) / kBlock3)), dim3(kBlock3), 0, c->stream, grad,
                      ngrad, R(0));
   // Seed: adjoint of J = mean over (x, y) of sum_CL 4 F C_ref s_c / dt * dx.
   const lbm_params& p = c->p;
   const double w = dJ * c->d.dx / (double(c->g.nx) * c->g.ny) * 4.0 * p.faraday * p.C_ref / c->d.dt;
-  hipLaunchKernelGGL((k3_adj_step<R, true>), grid, dim3(kBlock3), 0, c->stream,
-                     static_cast<const R*>(c->state(c->cur)), static_cast<const R*>(nullptr), lam[0], grad, m.phi,
-                     m.invk, m.d, k, R(w));
+  if (lbm_status st = reverse_step3<R, true>(c, static_cast<const R*>(c->state(c->cur)), nullptr, lam[0], grad, side,
+                                             R(w));
+      st != LBM_OK)
+    return st;
   int cur = 0;
   for (int seg = A.nck - 1; seg >= 0; --seg) {
     const int64_t start = int64_t(seg) * c->adj_every;
@@ -547,9 +599,10 @@ lbm_status backward3_t(lbm3d_ctx* c, double dJ, void* g_invk, void* g_phi, void*
                          reinterpret_cast<const R*>(replay + size_t(j - 1) * A.state),
                          reinterpret_cast<R*>(replay + size_t(j) * A.state), m.phi, m.invk, m.d, k);
     for (int j = len - 1; j >= 0; --j) {
-      hipLaunchKernelGGL((k3_adj_step<R, false>), grid, dim3(kBlock3), 0, c->stream,
-                         reinterpret_cast<const R*>(replay + size_t(j) * A.state), lam[cur], lam[cur ^ 1], grad,
-                         m.phi, m.invk, m.d, k, R(0));
+      if (lbm_status st = reverse_step3<R, false>(c, reinterpret_cast<const R*>(replay + size_t(j) * A.state),
+                                                  lam[cur], lam[cur ^ 1], grad, side, R(0));
+          st != LBM_OK)
+        return st;
       cur ^= 1;
     }
   }
