@@ -544,9 +544,13 @@ class Model:
         inflow = (self.inlet_velocity() * self.p.c_in).sum() if self.g.ny_channel > 0 else torch.zeros((), dtype=DT)
         util = s_c.sum() / inflow if float(inflow) > 0 else torch.zeros((), dtype=DT)
         ycl = self.g.ny - self.g.ny_cl
+        if self.g.ny_cl > 0:
+            c_prof, T_prof = c[ycl], self.p.T_in + theta[ycl]
+        else:  # no CL row: the profiles are defined as zeros
+            c_prof = T_prof = torch.zeros(self.g.nx, dtype=DT)
         return dict(
             current_density=I, power_density=self.p.V_op * I, heat_rate=H, o2_utilisation=util,
             T_max=(self.p.T_in + theta).max(), sum_f=pre[0:9].sum(), sum_theta=theta.sum(),
             sum_c=c.sum(), consumed_c=s_c.sum(), heat_added=S_T.sum(),
-            i_profile=i_x, c_profile=c[ycl], T_profile=self.p.T_in + theta[ycl],
+            i_profile=i_x, c_profile=c_prof, T_profile=T_prof,
         )

@@ -1,0 +1,148 @@
+"""Degenerate geometries against the FP64 oracles: the smallest lattice
+(nx = 3, where one column feeds both the inlet and the outlet node), no
+channel (no inlet), a channel with no porous layers, no CL, and a single
+row / layer.  Runs from equilibrium, one step of an arbitrary state, and the
+adjoint at nx = 3."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint2d as A
+from oracle import adjoint3d as A3
+from oracle import lbm2d as L
+from oracle import lbm3d as L3
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+
+CASES_2D = [(3, 6, (3, 2, 1)), (24, 5, (0, 4, 1)), (24, 4, (4, 0, 0)), (17, 1, (1, 0, 0)), (20, 6, (3, 3, 0))]
+CASES_3D = [(3, 4, 6, (3, 2, 1)), (10, 4, 5, (0, 4, 1)), (12, 3, 4, (4, 0, 0)), (9, 3, 1, (1, 0, 0))]
+
+
+def _lbm():
+    from paper_2103_01444_amd import lbm
+    return lbm
+
+
+def _w2(nx, ny, layers):
+    w = W.cathode2d_200x40()
+    w.update(nx=nx, ny=ny, ny_channel=layers[0], ny_gdl=layers[1], ny_cl=layers[2], Re=0.2 * max(layers[0], 1))
+    return w
+
+
+def _compare(fg, fo, vel, others, label):
+    """Velocity components relative to the largest velocity of the field (a
+    component that is zero by symmetry carries only round-off); other
+    fields relative to their own maximum."""
+    u_scale = max(max(float(fo[k].abs().max()) for k in vel), 1e-300)
+    for key in vel:
+        err = float((fg[key].cpu() - fo[key]).abs().max()) / u_scale
+        print(f"{label} {key}: rel {err:.1e}", flush=True)
+        assert err < 1e-11, key
+    for key in others:
+        scale = float(fo[key].abs().max())
+        err = float((fg[key].cpu() - fo[key]).abs().max()) / max(scale, 1e-300)
+        print(f"{label} {key}: rel {err:.1e}", flush=True)
+        assert err < 1e-11 or scale == 0.0, key
+
+
+def _max_rel(a, b):
+    a = torch.as_tensor(a, dtype=DT).cpu()
+    b = torch.as_tensor(b, dtype=DT).cpu()
+    return float((a - b).abs().max()) / max(float(b.abs().max()), 1e-300)
+
+
+@pytest.mark.parametrize("case", CASES_2D)
+def test_degenerate_2d(case):
+    lbm = _lbm()
+    nx, ny, layers = case
+    w = _w2(nx, ny, layers)
+    gpu = lbm.Cathode.from_workload(w, dx_cm=1e-3)
+    p = L.Params.from_workload(w)
+    p.dx_cm = 1e-3
+    m = L.Model(L.Geometry(nx, ny, *layers), p)
+    s = m.run(m.initial_state(), 25)
+    gpu.step(25)
+    fg, fo = gpu.fields(), m.fields(s)
+    _compare(fg, fo, ("ux", "uy"), ("p", "theta", "c"), f"2d {case}")
+    og, oo = gpu.observables(), m.observables(s)
+    for key in ("current_density", "heat_rate", "o2_utilisation", "T_max", "sum_c", "sum_theta", "consumed_c"):
+        ref = float(oo[key])
+        assert abs(og[key] - ref) <= 1e-12 * max(abs(ref), 1e-30) + 1e-300, (key, og[key], ref)
+    for key in ("i_profile", "c_profile", "T_profile"):
+        assert _max_rel(og[key], oo[key]) < 1e-12 or float(oo[key].abs().max()) == 0.0, key
+    pops = torch.from_numpy(W.random_populations(ny, nx, 11 + nx))
+    gpu.set_populations(pops)
+    gpu.step(1)
+    err = float((gpu.populations().cpu() - m.step(pops)).abs().max())
+    print(f"2d {case} one step: {err:.1e}", flush=True)
+    assert err < 1e-13
+
+
+@pytest.mark.parametrize("case", CASES_3D)
+def test_degenerate_3d(case):
+    lbm = _lbm()
+    nx, ny, nz, layers = case
+    w = W.cathode3d_scaled(nx, ny, nz, precision=64, nz_channel=layers[0], nz_gdl=layers[1], nz_cl=layers[2],
+                           Re=0.2 * max(layers[0], 1), dp_lat=0.0, Da_gdl=1e-3)
+    gpu = lbm.Cathode3D.from_workload(w, dx_cm=1e-3)
+    p = L3.params_from_workload(w)
+    p.dx_cm = 1e-3
+    m = L3.Model3D(L3.Geometry3D(nx, ny, nz, *layers), p)
+    s = m.run(m.initial_state(), 20)
+    gpu.step(20)
+    fg, fo = gpu.fields(), m.fields(s)
+    _compare(fg, fo, ("ux", "uy", "uz"), ("p", "theta", "c"), f"3d {case}")
+    og, oo = gpu.observables(), m.observables(s)
+    for key in ("current_density", "o2_utilisation", "T_max", "sum_c", "consumed_c"):
+        ref = float(oo[key])
+        assert abs(og[key] - ref) <= 1e-12 * max(abs(ref), 1e-30) + 1e-300, (key, og[key], ref)
+    pops = torch.from_numpy(W.random_populations3d(nz, ny, nx, 13 + nx))
+    gpu.set_populations(pops)
+    gpu.step(1)
+    err = float((gpu.populations().cpu() - m.step(pops)).abs().max())
+    print(f"3d {case} one step: {err:.1e}", flush=True)
+    assert err < 1e-13
+
+
+def _fields2(w, phi):
+    m = L.Model(L.geometry_from_workload(w), L.Params.from_workload(w), phi=torch.as_tensor(phi, dtype=DT))
+    return [torch.as_tensor(phi, dtype=DT), m.inv_k.detach().clone(), m.d_eff.detach().clone()]
+
+
+def test_adjoint_nx3_2d():
+    """nx = 3: column 1 feeds both the inlet and the outlet node."""
+    lbm = _lbm()
+    w = W.adjoint2d(3, 8)
+    w.update(ny_channel=4, ny_gdl=3, ny_cl=1, Re=0.8, V_op=0.45, precision=64)
+    phi = W.porosity_field(w)
+    fields = _fields2(w, phi)
+    sim = lbm.Cathode.from_workload(w, phi=fields[0], inv_k=fields[1], d_eff=fields[2])
+    J = sim.forward_checkpointed(30, 7)
+    g = sim.backward(1.0)
+    Jo, gphi, gk, gd = A.gradient(L.geometry_from_workload(w), L.Params.from_workload(w), *fields, nsteps=30, every=7)
+    assert abs(J / float(Jo) - 1) < 1e-12
+    for name, ref in (("phi", gphi), ("inv_k", gk), ("d_eff", gd)):
+        err = _max_rel(g[name], ref)
+        print(f"2d nx=3 adjoint d/d{name}: rel {err:.1e}", flush=True)
+        assert err < 1e-9, name
+
+
+def test_adjoint_nx3_3d():
+    lbm = _lbm()
+    w = W.cathode3d_scaled(3, 4, 6, precision=64, nz_channel=3, nz_gdl=2, nz_cl=1, Re=0.6, V_op=0.45,
+                           sphere_radius=1.0, filter_box=3)
+    phi = np.clip(W.sphere_pack_porosity(w), 0.3, 1.0)
+    m = L3.Model3D(L3.geometry_from_workload(w), L3.params_from_workload(w), phi=torch.as_tensor(phi, dtype=DT))
+    fields = [torch.as_tensor(phi, dtype=DT), m.inv_k.detach().clone(), m.d_eff.detach().clone()]
+    sim = lbm.Cathode3D.from_workload(w, phi=fields[0], inv_k=fields[1], d_eff=fields[2])
+    J = sim.forward_checkpointed(24, 5)
+    g = sim.backward(1.0)
+    Jo, gphi, gk, gd = A3.gradient(L3.geometry_from_workload(w), L3.params_from_workload(w), *fields, nsteps=24,
+                                   every=5)
+    assert abs(J / float(Jo) - 1) < 1e-12
+    for name, ref in (("phi", gphi), ("inv_k", gk), ("d_eff", gd)):
+        err = _max_rel(g[name], ref)
+        print(f"3d nx=3 adjoint d/d{name}: rel {err:.1e}", flush=True)
+        assert err < 1e-9, name
