@@ -159,14 +159,17 @@ class Params:
     rhocp_s: float = 1.6         # J/(cm^3 K) [R1]
     body_force: tuple = (0.0, 0.0)  # test mode only: acceleration in lattice units [R5]
     reaction: bool = True
+    pressure_inlet: bool = False  # Section 4's pressure-driven flow: inlet pressure p_in, outlet 0 [R17]
+    p_in: float = 0.0            # lattice inlet pressure when pressure_inlet (Re is then an output)
 
     @staticmethod
     def from_workload(w: dict) -> "Params":
         p = Params()
         for k in ("tau_f", "D_f_lat", "Re", "T_in", "c_in", "V_op", "phi_gdl",
-                  "Da_gdl", "deff_ratio_gdl"):
+                  "Da_gdl", "deff_ratio_gdl", "p_in"):
             if k in w:
                 setattr(p, k, float(w[k]))
+        p.pressure_inlet = bool(w.get("pressure_inlet", False))
         if w.get("dp_over_hgdl", 0.0) > 0:
             p.dp_lat = w["dp_over_hgdl"] * w["ny_gdl"]
         return p
@@ -232,7 +235,8 @@ class Model:
         else:
             self.dx = prm.gdl_thickness_cm / geom.ny_gdl
         self.dt = prm.D_f_lat * self.dx ** 2 / prm.D_O2
-        self.u_avg = prm.Re * self.nu / geom.ny_channel if geom.ny_channel > 0 else 0.0
+        self.u_avg = (prm.Re * self.nu / geom.ny_channel
+                      if geom.ny_channel > 0 and not prm.pressure_inlet else 0.0)
 
         rows = torch.arange(ny).view(ny, 1).expand(ny, nx)
         self.is_channel = rows < geom.ny_channel
@@ -415,15 +419,22 @@ class Model:
             ux1, uy1, p1, _, _ = self.flow_macros(
                 f1, self.phi[:H, 1], self.l0[:H, 1], self.l1[:H, 1], self.inv_k[:H, 1],
                 self.sqrt_inv_k[:H, 1], self.F_phi[:H, 1])
-            uin = self.inlet_velocity()
-            zero = torch.zeros_like(uin)
-            out[0:9, :H, 0] = self.feq(p1, uin, zero, self.phi[:H, 0]) + f1 - self.feq(p1, ux1, uy1, self.phi[:H, 1])
+            # [R17] Section 4 drives the flow by a pressure difference between
+            # inlet and outlet: the inlet nodes get the pressure p_in with the
+            # velocity of column 1 (non-equilibrium extrapolation, as the
+            # outlet), the outlet keeps p = 0; the scalars stay Dirichlet.
+            if self.p.pressure_inlet:
+                ubx, uby, pb = ux1, uy1, torch.full_like(p1, self.p.p_in)
+            else:  # [R7]: parabolic velocity, pressure of column 1
+                ubx, uby, pb = self.inlet_velocity(), torch.zeros_like(p1), p1
+            zero = torch.zeros_like(p1)
+            out[0:9, :H, 0] = self.feq(pb, ubx, uby, self.phi[:H, 0]) + f1 - self.feq(p1, ux1, uy1, self.phi[:H, 1])
             gT1, gC1 = pre[9:14, :H, 1], pre[14:19, :H, 1]
             th1, c1 = gT1.sum(0), gC1.sum(0)
-            out[9:14, :H, 0] = (self.geq(zero, uin, zero, self.b_T[:H, 0]) + gT1
+            out[9:14, :H, 0] = (self.geq(zero, ubx, uby, self.b_T[:H, 0]) + gT1
                                 - self.geq(th1, ux1, uy1, self.b_T[:H, 1]))
-            cin = torch.full_like(uin, self.p.c_in)
-            out[14:19, :H, 0] = (self.geq(cin, uin, zero, self.b_C[:H, 0]) + gC1
+            cin = torch.full_like(p1, self.p.c_in)
+            out[14:19, :H, 0] = (self.geq(cin, ubx, uby, self.b_C[:H, 0]) + gC1
                                  - self.geq(c1, ux1, uy1, self.b_C[:H, 1]))
         c2 = nx - 2
         f2 = pre[0:9, :, c2]
@@ -527,7 +538,9 @@ class Model:
 
         i(x) = sum over CL rows of (-j_eff) dx [A/cm^2]; I = mean_x i(x);
         P = V I; H = mean_x sum_CL Q dx [W/cm^2];
-        O2 utilisation = sum_CL s_c / sum_inlet u_in c_in (per step);
+        O2 utilisation = sum_CL s_c / sum_inlet u_in c_in (per step; with the
+        pressure inlet [R17] the inlet velocities are those of the state);
+        inlet flux = sum over the inlet nodes of u_x (lattice units);
         T_max; CL profiles of c and T on the CL row next to the GDL;
         population sums and the per-step consumption / heating.
         """
@@ -541,7 +554,18 @@ class Model:
         i_x = (-j_eff).sum(0) * self.dx
         I = i_x.mean()
         H = (Q.sum(0) * self.dx).mean()
-        inflow = (self.inlet_velocity() * self.p.c_in).sum() if self.g.ny_channel > 0 else torch.zeros((), dtype=DT)
+        hc = self.g.ny_channel
+        if hc > 0 and not self.g.periodic_x:
+            u_in, _, _, _, _ = self.flow_macros(pre[0:9, :hc, 0], self.phi[:hc, 0], self.l0[:hc, 0],
+                                                self.l1[:hc, 0], self.inv_k[:hc, 0], self.sqrt_inv_k[:hc, 0],
+                                                self.F_phi[:hc, 0])
+            flux = u_in.sum()
+        else:
+            flux = torch.zeros((), dtype=DT)
+        if self.p.pressure_inlet:
+            inflow = flux * self.p.c_in
+        else:
+            inflow = (self.inlet_velocity() * self.p.c_in).sum() if hc > 0 else torch.zeros((), dtype=DT)
         util = s_c.sum() / inflow if float(inflow) > 0 else torch.zeros((), dtype=DT)
         ycl = self.g.ny - self.g.ny_cl
         if self.g.ny_cl > 0:
@@ -552,5 +576,5 @@ class Model:
             current_density=I, power_density=self.p.V_op * I, heat_rate=H, o2_utilisation=util,
             T_max=(self.p.T_in + theta).max(), sum_f=pre[0:9].sum(), sum_theta=theta.sum(),
             sum_c=c.sum(), consumed_c=s_c.sum(), heat_added=S_T.sum(),
-            i_profile=i_x, c_profile=c_prof, T_profile=T_prof,
+            i_profile=i_x, c_profile=c_prof, T_profile=T_prof, inlet_flux=flux,
         )
