@@ -196,6 +196,43 @@ def bench_3d(steps: int, warmup: int = 50) -> dict:
                             "o2_utilisation": obs["o2_utilisation"]}}
 
 
+def bench_polarisation(steps: int) -> dict:
+    """Polarisation / power / heat curves of the pressure-driven 200x40
+    cathode (3 inlet pressures x 13 voltages = 39 cases in one batch)."""
+    import workloads as W
+    from paper_2103_01444_amd import BatchedSweep
+
+    cases = W.polarisation_sweep(steps)
+    cells = sum(w["nx"] * w["ny"] for w in cases)
+    b = BatchedSweep(cases)
+    tune = b.autotune(trial_steps=10, cache_path=os.environ.get(
+        "LBMPEM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lbmpem_tune.json")))
+    head = steps - steps // 10
+    wall, ev = _timed(b.stream, lambda: b.step(head))
+    prev = [o["current_density"] for o in b.observables()]
+    wall2, ev2 = _timed(b.stream, lambda: b.step(steps - head))
+    wall, ev = wall + wall2, ev + ev2
+    obs = b.observables()
+    del b
+    drift = max(abs(o["current_density"] - p) / abs(o["current_density"]) for o, p in zip(obs, prev))
+    nu = (cases[0]["tau_f"] - 0.5) / 3.0
+    nv = len(W.POLARISATION_V)
+    curves = []
+    for j, p_in in enumerate(W.POLARISATION_P_IN):
+        o = obs[j * nv:(j + 1) * nv]
+        curves.append({"p_in": p_in, "Re": round(o[-1]["inlet_flux"] / nu, 3), "V": list(W.POLARISATION_V),
+                       "I_A_cm2": [round(x["current_density"], 4) for x in o],
+                       "P_W_cm2": [round(x["power_density"], 4) for x in o],
+                       "heat_W_cm2": [round(x["heat_rate"], 4) for x in o]})
+    achieved = cells * BYTES_PER_LU_POPS * steps / ev / 1e9
+    return {"workload": "polarisation_sweep_39", "cases": len(cases), "cells": cells, "steps": steps,
+            "value": round(cells * steps / wall / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(wall * 1e3 / steps, 4),
+            "schedule": {k: tune[k] for k in ("tile_x", "tile_y", "persistent")},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_lattice_update": BYTES_PER_LU_POPS},
+            "curves_after_steps": steps, "max_rel_change_I_last_tenth": round(drift, 6), "curves": curves}
+
+
 ADJ3_BYTES_PER_LU = 33 * 4 * 3 + 3 * 4 + 3 * 4 * 2  # 3D reverse step, same streams as in 2D
 FWD3_FULL_BYTES_PER_LU = 33 * 4 * 2 + 3 * 4         # replayed 3D forward step with three per-cell fields
 
@@ -241,6 +278,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint")
     ap.add_argument("--steps3d", type=int, default=5000, help="0 skips the 3D cathode")
     ap.add_argument("--adjoint3d-steps", type=int, default=5000, help="0 skips the 3D adjoint")
+    ap.add_argument("--polarisation-steps", type=int, default=100000, help="0 skips the polarisation sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write copy kernel 5 times (counter calibration)")
     args = ap.parse_args()
@@ -329,6 +367,10 @@ def main():
         line["adjoint"] = bench_adjoint(args.adjoint_steps)
         print(f"bench: adjoint {line['adjoint']['adjoint']['value']} MLUPS, "
               f"{line['adjoint']['adjoint_over_forward_time']}x forward time", file=sys.stderr, flush=True)
+    if args.polarisation_steps > 0:
+        print("bench: polarisation sweep", file=sys.stderr, flush=True)
+        line["polarisation"] = bench_polarisation(args.polarisation_steps)
+        print(f"bench: polarisation {line['polarisation']['value']} MLUPS", file=sys.stderr, flush=True)
     if args.steps3d > 0:
         print("bench: 3D cathode", file=sys.stderr, flush=True)
         line["cathode3d"] = bench_3d(args.steps3d)

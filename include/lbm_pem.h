@@ -73,6 +73,10 @@ typedef enum lbm_status {
 #define LBM_PERIODIC_Y 2u  /* no y walls: y wraps (test configurations) */
 #define LBM_BODY_FORCE 4u  /* add phi * (body_force_x, body_force_y) to the flow force */
 #define LBM_NO_REACTION 8u /* switch the CL reaction off */
+#define LBM_PRESSURE_INLET 32u /* 2D: pressure-driven flow (Section 4): the inlet nodes of the channel rows
+                                * take the pressure lbm_params.p_inlet with the velocity of column 1 (non-
+                                * equilibrium extrapolation), the outlet keeps p = 0; Re is then an output
+                                * (lbm_obs.inlet_flux / nu) and lbm_params.Re is ignored */
 
 typedef struct lbm_geometry {
   int32_t nx, ny;                      /* nx >= 3, ny >= 1 */
@@ -116,6 +120,7 @@ typedef struct lbm_params {
   double body_force_y;
   int32_t independent_fields; /* nonzero: keep porosity, 1/K and D_eff as three per-cell fields */
   int32_t reserved;
+  double p_inlet;          /* inlet pressure, lattice units (LBM_PRESSURE_INLET only; outlet p = 0) */
 } lbm_params;
 
 /* Observables of Section 5 on the current state (see Conventions). */
@@ -131,6 +136,9 @@ typedef struct lbm_obs {
   double sum_c;            /* sum of the O2 lattice */
   double consumed_c;       /* O2 the next step removes (sum over CL) */
   double heat_added;       /* temperature rise the next step adds (sum over CL, K x cells) */
+  double inlet_flux;       /* sum of u_x over the inlet nodes (lattice units); the mean inlet velocity times the
+                            * channel height, so Re = inlet_flux / nu.  With LBM_PRESSURE_INLET the O2
+                            * utilisation divides by inlet_flux * c_in (the prescribed profile's otherwise) */
 } lbm_obs;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -155,7 +163,8 @@ lbm_status lbm_create(const lbm_geometry* g, void* dev_ws, size_t ws_bytes, void
  * them afterwards.  Synchronous.  Errors: LBM_ERR_INVALID_ARG,
  * LBM_ERR_UNSTABLE_PARAMS (tau_f <= 0.5, a diffusivity outside
  * (0, 1/(4 sqrt 3)], porosity outside (0, 1], 1/K < 0, inlet peak velocity
- * above 0.1). */
+ * above 0.1; with LBM_PRESSURE_INLET: the plane-Poiseuille peak velocity
+ * p_inlet H^2 / (8 nu (nx - 1)) of the channel above 0.1). */
 lbm_status lbm_set_params(lbm_ctx* ctx, const lbm_params* p, const void* phi, const void* inv_k,
                           const void* d_eff);
 
@@ -229,7 +238,8 @@ size_t lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int64_t nsteps, int32_t e
 /* Initialise to equilibrium, run nsteps steps storing a checkpoint every
  * `every` steps in dev_ws (caller-owned, kept until lbm_backward), and
  * return J in *J_out.  Synchronous.  LBM_ERR_STATE if the context does not
- * hold independent per-cell fields. */
+ * hold independent per-cell fields or uses LBM_PRESSURE_INLET (the adjoint
+ * covers the velocity inlet). */
 lbm_status lbm_forward_checkpointed(lbm_ctx* ctx, int64_t nsteps, int32_t every, void* dev_ws, size_t ws_bytes,
                                     double* J_out);
 

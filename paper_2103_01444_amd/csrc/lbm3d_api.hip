@@ -333,6 +333,7 @@ lbm_status observables3_t(lbm3d_ctx* c, lbm_obs* o) {
   r.power_density = p.V_op * r.current_density;
   r.heat_rate = h[5] * i_scale / ncol;
   r.o2_utilisation = c->d.inflow > 0 ? h[3] / c->d.inflow : 0.0;
+  r.inlet_flux = h[8];
   r.T_max = p.T_in_K + h[6];
   r.sum_f = h[0] + ncol * c->g.nz;  // the rest population is stored as f0 - rho0
   r.sum_theta = h[1];

@@ -8,7 +8,7 @@
 namespace lbm3 {
 
 constexpr int kBlock3 = 256;
-constexpr int kObsQ3 = 8;
+constexpr int kObsQ3 = 9;
 
 // Row order of the launch.  Rows (y, z) are visited in chunks of `ty`
 // consecutive y: all z of the first chunk, then all z of the next, so the
@@ -76,17 +76,18 @@ __global__ __launch_bounds__(kBlock3) void k3_init(R* __restrict__ dst, const R*
 
 // Per-workgroup observable partials of the pre-collision state: sum f
 // (shifted), sum theta, sum c, sum s_c, sum S_T, sum s_c (eta + T dU0/dT),
-// max theta, count of non-finite populations.
+// max theta, count of non-finite populations, sum of u_x over the inlet nodes.
 template <typename R, int MAT>
 __global__ __launch_bounds__(kBlock3) void k3_obs_cells(const R* __restrict__ src, const R* __restrict__ phi_f,
                                                         const R* __restrict__ invk_f, const R* __restrict__ d_f,
                                                         Consts3<R> k, double* __restrict__ partial) {
   const int x = blockIdx.x * kBlock3 + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
-  double v[kObsQ3] = {0, 0, 0, 0, 0, 0, -1e300, 0};
+  double v[kObsQ3] = {0, 0, 0, 0, 0, 0, -1e300, 0, 0};
   if (x < k.nx) {
     R f[33];
     const Mat3<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, z, f);
+    if (x == 0 && z < k.nz_ch && !(k.flags & F_PERIODIC_X)) v[8] = double(flow_macros(f, mt, k).ux);
     double sf = 0, th = 0, c = 0;
 #pragma unroll
     for (int q = 0; q < 19; ++q) sf += double(f[q]);

@@ -313,7 +313,9 @@ lbm_status observables_t(lbm_ctx* c, lbm_obs* o, double* pi, double* pc, double*
   r.current_density = sum_sc * i_scale / c->g.nx;
   r.power_density = p.V_op * r.current_density;
   r.heat_rate = h[5] * i_scale / c->g.nx;
-  r.o2_utilisation = c->d.inflow > 0 ? sum_sc / c->d.inflow : 0.0;
+  r.inlet_flux = h[8];
+  const double inflow = (c->g.flags & LBM_PRESSURE_INLET) ? h[8] * p.c_in : c->d.inflow;
+  r.o2_utilisation = inflow > 0 ? sum_sc / inflow : 0.0;
   r.T_max = p.T_in_K + h[6];
   r.sum_f = h[0] + ncell;  // the rest population is stored as f0 - rho0
   r.sum_theta = h[1];
@@ -633,6 +635,8 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, v
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
   if (c->mat != MAT_FULL)
     return fail(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
+  if (c->g.flags & LBM_PRESSURE_INLET)
+    return fail(c, LBM_ERR_STATE, "the adjoint covers the velocity inlet, not LBM_PRESSURE_INLET");
   const AdjLayout A = adj_layout(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign != 0)
     return fail(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

@@ -238,7 +238,9 @@ lbm_status observables_t(lbm_batch* b, lbm_obs* out) {
     r.current_density = h[3] * i_scale / g.nx;
     r.power_density = p.V_op * r.current_density;
     r.heat_rate = h[5] * i_scale / g.nx;
-    r.o2_utilisation = b->d[i].inflow > 0 ? h[3] / b->d[i].inflow : 0.0;
+    r.inlet_flux = h[8];
+    const double inflow = (g.flags & LBM_PRESSURE_INLET) ? h[8] * p.c_in : b->d[i].inflow;
+    r.o2_utilisation = inflow > 0 ? h[3] / inflow : 0.0;
     r.T_max = p.T_in_K + h[6];
     r.sum_f = h[0] + double(g.nx) * g.ny;
     r.sum_theta = h[1];

@@ -18,6 +18,7 @@ constexpr uint32_t F_PERIODIC_X = 1u;
 constexpr uint32_t F_PERIODIC_Y = 2u;
 constexpr uint32_t F_BODY_FORCE = 4u;
 constexpr uint32_t F_NO_REACTION = 8u;
+constexpr uint32_t F_PRESSURE_INLET = 32u;
 
 // Velocity sets of Eq. 2 (planes 0-8) and Eq. 9 (planes 9-13 and 14-18).
 constexpr int EX[19] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 0, 1, 0, -1, 0, 0, 1, 0, -1, 0};
@@ -46,6 +47,7 @@ struct Consts {
   R ln_k0;              // ln(aj0_ref dt / (4 F C_ref))
   R E_over_R, inv_T_arrh, aF_over_R;
   R four_f_cref;        // 4 F C_ref, C / cm^3
+  R p_in;               // inlet pressure of the pressure-driven mode
 };
 
 template <typename R>
@@ -279,14 +281,20 @@ __device__ __forceinline__ R inlet_velocity(const Consts<R>& k, int y) {
 
 // Turn the pulled populations f of the column next to a boundary node into
 // the boundary node's pre-collision populations (inlet: velocity u_in(y)
-// with the pressure of the neighbour, Dirichlet theta = 0 and c = c_in;
-// outlet: zero pressure with the neighbour's velocity, scalars copied).
+// with the pressure of the neighbour, or in the pressure-driven mode the
+// pressure p_in with the neighbour's velocity; Dirichlet theta = 0 and
+// c = c_in; outlet: zero pressure with the neighbour's velocity, scalars
+// copied).
 template <typename R>
 __device__ __forceinline__ void boundary_column(R (&f)[19], const Consts<R>& k, int y, bool inlet, const Mat<R>& mp,
                                                 const Mat<R>& mb) {
   const Macro<R> a = flow_macros(f, mp, k);
   R ubx, uby, pb;
-  if (inlet) {
+  if (inlet && (k.flags & F_PRESSURE_INLET)) {
+    ubx = a.ux;
+    uby = a.uy;
+    pb = k.p_in;
+  } else if (inlet) {
     ubx = inlet_velocity(k, y);
     uby = R(0);
     pb = a.p;

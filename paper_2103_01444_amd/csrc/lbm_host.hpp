@@ -24,7 +24,8 @@ inline bool geometry_ok(const lbm_geometry* g) {
   if (g->ny_channel < 0 || g->ny_gdl < 0 || g->ny_cl < 0) return false;
   if (g->ny_channel + g->ny_gdl + g->ny_cl != g->ny) return false;
   if (g->precision != 32 && g->precision != 64) return false;
-  if (g->flags & ~(LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_BODY_FORCE | LBM_NO_REACTION)) return false;
+  if (g->flags & ~(LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_BODY_FORCE | LBM_NO_REACTION | LBM_PRESSURE_INLET))
+    return false;
   const int64_t pitch = (int64_t(g->nx) + 63) / 64 * 64;
   if (pitch * g->ny * 19 >= (int64_t(1) << 31)) return false;  // 32-bit element offsets
   return true;
@@ -73,10 +74,20 @@ inline lbm_status derive(const lbm_geometry& g, const lbm_params& p, Derived& d,
   }
   d.dt = p.D_f_lat * d.dx * d.dx / p.D_O2_cm2s;
   d.nu = (p.tau_f - 0.5) / 3.0;
-  d.u_avg = g.ny_channel > 0 ? p.Re * d.nu / g.ny_channel : 0.0;
+  const bool pressure = g.flags & LBM_PRESSURE_INLET;
+  d.u_avg = (g.ny_channel > 0 && !pressure) ? p.Re * d.nu / g.ny_channel : 0.0;
   if (!(g.flags & LBM_PERIODIC_X) && 1.5 * std::fabs(d.u_avg) > 0.1) {
     err = "inlet peak velocity above 0.1";
     return LBM_ERR_UNSTABLE_PARAMS;
+  }
+  if (pressure && !(g.flags & LBM_PERIODIC_X)) {
+    // plane Poiseuille estimate of the channel's peak velocity
+    const double H = g.ny_channel;
+    const double umax = std::fabs(p.p_inlet) / (g.nx - 1) * H * H / (8.0 * d.nu);
+    if (!std::isfinite(p.p_inlet) || umax > 0.1) {
+      err = "inlet pressure drives a channel peak velocity above 0.1";
+      return LBM_ERR_UNSTABLE_PARAMS;
+    }
   }
   if (p.dp_lat > 0) {  // Kozeny-Carman (Eq. 7) at the layered porosity
     const double ph = p.phi_gdl, om = 1.0 - ph;
@@ -145,6 +156,7 @@ void fill_consts(Consts<R>& k, const lbm_geometry& g, const lbm_params& p, const
   k.inv_T_arrh = R(1.0 / p.T_arrh);
   k.aF_over_R = R(p.alpha_c * p.faraday / p.R_gas);
   k.four_f_cref = R(4.0 * p.faraday * p.C_ref);
+  k.p_in = R(p.p_inlet);
 }
 
 }  // namespace lbm

@@ -6,7 +6,7 @@
 namespace lbm {
 
 constexpr int kBlock = 256;     // 4 wavefronts of 64 lanes along x
-constexpr int kObsQ = 8;        // per-block observable partials
+constexpr int kObsQ = 9;        // per-block observable partials
 
 // Map a 2D launch (blocks along x, rows along y) so that the eight XCDs
 // (which receive consecutive workgroups round-robin) each get a contiguous
@@ -77,7 +77,8 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Observable partial sums over the pre-collision state, one row of partials
 // per workgroup: sum f (shifted), sum theta, sum c, sum s_c, sum S_T,
-// sum s_c (eta + T dU0/dT), max theta, count of non-finite values.
+// sum s_c (eta + T dU0/dT), max theta, count of non-finite values, sum of
+// u_x over the inlet nodes.
 template <typename R, int MAT>
 __global__ __launch_bounds__(kBlock) void k_obs_cells(const R* __restrict__ src,
                                                       const R* __restrict__ phi_f,
@@ -86,10 +87,11 @@ __global__ __launch_bounds__(kBlock) void k_obs_cells(const R* __restrict__ src,
                                                       double* __restrict__ partial) {
   const int x = blockIdx.x * kBlock + threadIdx.x;
   const int y = blockIdx.y;
-  double v[kObsQ] = {0, 0, 0, 0, 0, 0, -1e300, 0};
+  double v[kObsQ] = {0, 0, 0, 0, 0, 0, -1e300, 0, 0};
   if (x < k.nx) {
     R f[19];
     const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);
+    if (x == 0 && y < k.ny_ch && !(k.flags & F_PERIODIC_X)) v[8] = double(flow_macros(f, mt, k).ux);
     double sf = 0, th = 0, c = 0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) sf += double(f[q]);

@@ -22,6 +22,7 @@ LBM_PERIODIC_Y = 2
 LBM_BODY_FORCE = 4
 LBM_NO_REACTION = 8
 LBM_PERIODIC_Z = 16
+LBM_PRESSURE_INLET = 32
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "parameters outside the stable range", 3: "device error",
           4: "non-finite result", 5: "call out of order"}
@@ -47,13 +48,13 @@ class Geometry3D(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in _PARAM_NAMES] + [
-        ("independent_fields", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+        ("independent_fields", ctypes.c_int32), ("reserved", ctypes.c_int32), ("p_inlet", ctypes.c_double)]
 
 
 class Obs(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64)] + [(n, ctypes.c_double) for n in (
         "current_density", "power_density", "heat_rate", "o2_utilisation", "T_max", "sum_f", "sum_theta",
-        "sum_c", "consumed_c", "heat_added")]
+        "sum_c", "consumed_c", "heat_added", "inlet_flux")]
 
 
 class Schedule(ctypes.Structure):
@@ -171,9 +172,16 @@ def params_from_workload(w: dict, **over) -> Params:
         p.dp_lat = float(w["dp_over_hgdl"] * w.get("ny_gdl", w.get("nz_gdl")))
     if w.get("dp_lat", 0.0) > 0:
         p.dp_lat = float(w["dp_lat"])
+    if "p_in" in w:
+        p.p_inlet = float(w["p_in"])
     for k, v in over.items():
         setattr(p, k, v)
     return p
+
+
+def workload_flags(w: dict) -> int:
+    """Geometry flags a workload dictionary asks for (pressure-driven inlet)."""
+    return LBM_PRESSURE_INLET if w.get("pressure_inlet", False) else 0
 
 
 def _ptr(t):
@@ -215,6 +223,7 @@ class Cathode:
 
     @classmethod
     def from_workload(cls, w: dict, phi=None, inv_k=None, d_eff=None, flags=0, **over):
+        flags |= workload_flags(w)
         return cls(w["nx"], w["ny"], w["ny_channel"], w["ny_gdl"], w["ny_cl"], params_from_workload(w, **over),
                    precision=w.get("precision", 32), flags=flags, phi=phi, inv_k=inv_k, d_eff=d_eff)
 
@@ -477,7 +486,7 @@ class BatchedSweep:
         self.dtype = torch.float64 if prec == 64 else torch.float32
         self.shapes = [(w["nx"], w["ny"]) for w in cases]
         self.geoms = (Geometry * n)(*[Geometry(w["nx"], w["ny"], w["ny_channel"], w["ny_gdl"], w["ny_cl"],
-                                               w.get("precision", 32), 0) for w in cases])
+                                               w.get("precision", 32), workload_flags(w)) for w in cases])
         self.params = (Params * n)(*[params_from_workload(w) for w in cases])
         self.n = n
         nbytes = self.lib.lbm_batch_workspace_bytes(self.geoms, n)

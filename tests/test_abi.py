@@ -48,10 +48,10 @@ def test_binding_names_match_header():
 
 def test_struct_layouts_match_header():
     from paper_2103_01444_amd import lbm
-    # lbm_geometry: 7 x 4 bytes; lbm_params: 28 doubles + 2 int32; lbm_obs: int64 + 10 doubles.
+    # lbm_geometry: 7 x 4 bytes; lbm_params: 28 doubles + 2 int32 + 1 double; lbm_obs: int64 + 11 doubles.
     assert ctypes.sizeof(lbm.Geometry) == 28
-    assert ctypes.sizeof(lbm.Params) == 28 * 8 + 8
-    assert ctypes.sizeof(lbm.Obs) == 8 + 10 * 8
+    assert ctypes.sizeof(lbm.Params) == 28 * 8 + 8 + 8
+    assert ctypes.sizeof(lbm.Obs) == 8 + 11 * 8
     assert ctypes.sizeof(lbm.Geometry3D) == 32  # lbm3d_geometry: 8 x 4 bytes
 
 

@@ -27,6 +27,13 @@ rate, permeability, porosity and effective diffusivity, Section 5):
 * ``adjoint2d_1024x256``: 1024x256, porosity field U[0.4,0.8] (seed
   21030146), 4000 steps, checkpoint every 200; 32 finite-difference cells
   drawn from the GDL (seed 21030147); a 64x16 copy for the oracle.
+* ``polarisation_sweep``: the paper's own flow driving (Section 4: a
+  pressure difference between inlet and outlet) on the 200x40 cathode with
+  GDL porosity 0.4 and permeability 0.176e-6 cm^2 (Darcy number 2.73e-4 on
+  the 254 um GDL; the Fig. 5 base case), 353 K: 3 inlet pressures x 13
+  voltages 0.30..0.90 V = 39 cases in one batch, FP32, O2 lattice
+  diffusivity 0.025 (so that the GDL approaches steady state within a few
+  10^4 steps), 20000 steps.  No randomness.
 * ``cathode3d_256x128x64``: 256 (x, along the channel) x 128 (y, across)
   x 64 (z, through the layers): channel 32 layers, GDL 29, CL 3.  GDL
   porosity from a seeded sphere pack (seed 21030148): spheres of radius 4
@@ -47,6 +54,11 @@ SEED_ADJOINT_PHI = 21030146
 SEED_ADJOINT_FD = 21030147
 SEED_SPHERE_PACK = 21030148
 SEED_ADJOINT3D_FD = 21030149
+
+# Inlet pressures (lattice units) of the polarisation sweep: plane-Poiseuille
+# channel peak velocities of about 0.01, 0.02 and 0.04 on the 200x40 lattice.
+POLARISATION_P_IN = (2e-3, 4e-3, 8e-3)
+POLARISATION_V = tuple(round(0.30 + 0.05 * i, 2) for i in range(13))
 
 
 def scaled_layers(ny: int) -> tuple[int, int, int]:
@@ -293,3 +305,17 @@ def fd_cells3d(w: dict, n: int = 8, seed: int = SEED_ADJOINT3D_FD, depth: int = 
         y, x = divmod(r, nx_in)
         out.append((z0 + z, y, x + 2))
     return out
+
+
+def polarisation_sweep(steps: int = 20000) -> list[dict]:
+    """Cases of the polarisation / power / heat curves (order: inlet
+    pressure, then voltage)."""
+    cases = []
+    for p_in in POLARISATION_P_IN:
+        for v in POLARISATION_V:
+            w = base_case()
+            w.update(name=f"pol_p{p_in:g}_V{v:.2f}", nx=200, ny=40, ny_channel=20, ny_gdl=18, ny_cl=2,
+                     precision=32, steps=steps, T_in=353.0, V_op=v, phi_gdl=0.4, Da_gdl=2.73e-4,
+                     D_f_lat=0.025, pressure_inlet=True, p_in=p_in)
+            cases.append(w)
+    return cases
