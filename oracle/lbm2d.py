@@ -159,14 +159,15 @@ class Params:
     rhocp_s: float = 1.6         # J/(cm^3 K) [R1]
     body_force: tuple = (0.0, 0.0)  # test mode only: acceleration in lattice units [R5]
     reaction: bool = True
-    pressure_inlet: bool = False  # Section 4's pressure-driven flow: inlet pressure p_in, outlet 0 [R17]
+    pressure_inlet: bool = False  # Section 4's pressure-driven flow: inlet pressure p_in, outlet p_out [R17]
     p_in: float = 0.0            # lattice inlet pressure when pressure_inlet (Re is then an output)
+    p_out: float = 0.0           # lattice outlet pressure (Section 5 varies it to set the flow rate) [R17]
 
     @staticmethod
     def from_workload(w: dict) -> "Params":
         p = Params()
         for k in ("tau_f", "D_f_lat", "Re", "T_in", "c_in", "V_op", "phi_gdl",
-                  "Da_gdl", "deff_ratio_gdl", "p_in"):
+                  "Da_gdl", "deff_ratio_gdl", "p_in", "p_out"):
             if k in w:
                 setattr(p, k, float(w[k]))
         p.pressure_inlet = bool(w.get("pressure_inlet", False))
@@ -405,7 +406,7 @@ class Model:
         Inlet (x = 0, channel rows): f = f_eq(p_1, u_in) + (f_1 - f_eq(p_1, u_1));
         scalars g = g_eq(X_in, u_in) + (g_1 - g_eq(X_1, u_1)), X_in = 0 for the
         temperature rise and c_in for O2 (Dirichlet, Section 4).
-        Outlet (x = nx-1, all rows): f = f_eq(0, u_2) + (f_2 - f_eq(p_2, u_2)),
+        Outlet (x = nx-1, all rows): f = f_eq(p_out, u_2) + (f_2 - f_eq(p_2, u_2)),
         with column 2 = nx-2; scalars copied from column nx-2 (fully
         developed, Section 4), and collided with column nx-2's scalar
         material [R10].
@@ -422,7 +423,7 @@ class Model:
             # [R17] Section 4 drives the flow by a pressure difference between
             # inlet and outlet: the inlet nodes get the pressure p_in with the
             # velocity of column 1 (non-equilibrium extrapolation, as the
-            # outlet), the outlet keeps p = 0; the scalars stay Dirichlet.
+            # outlet), the outlet has p_out; the scalars stay Dirichlet.
             if self.p.pressure_inlet:
                 ubx, uby, pb = ux1, uy1, torch.full_like(p1, self.p.p_in)
             else:  # [R7]: parabolic velocity, pressure of column 1
@@ -441,7 +442,7 @@ class Model:
         ux2, uy2, p2, _, _ = self.flow_macros(
             f2, self.phi[:, c2], self.l0[:, c2], self.l1[:, c2], self.inv_k[:, c2],
             self.sqrt_inv_k[:, c2], self.F_phi[:, c2])
-        out[0:9, :, nx - 1] = (self.feq(torch.zeros_like(p2), ux2, uy2, self.phi[:, nx - 1]) + f2
+        out[0:9, :, nx - 1] = (self.feq(torch.full_like(p2, self.p.p_out), ux2, uy2, self.phi[:, nx - 1]) + f2
                                - self.feq(p2, ux2, uy2, self.phi[:, c2]))
         out[9:19, :, nx - 1] = pre[9:19, :, c2]
         return out

@@ -1,5 +1,6 @@
 """Pins of the pressure-driven inlet (Section 4: flow induced by a pressure
 difference between inlet and outlet) in the oracle.  CPU only."""
+import pytest
 import torch
 
 from oracle import lbm2d as L
@@ -7,19 +8,20 @@ from oracle import lbm2d as L
 DT = torch.float64
 
 
-def test_pressure_driven_channel_is_exact_poiseuille():
-    # Clear channel, inlet pressure p_in at x = 0, zero at x = nx - 1: the
-    # steady state is plane Poiseuille flow with gradient p_in / (nx - 1)
-    # and a linear pressure, to round-off.
-    nx, H, p_in = 40, 9, 2e-3
+@pytest.mark.parametrize("p_in,p_out", [(2e-3, 0.0), (5e-3, 3e-3)])
+def test_pressure_driven_channel_is_exact_poiseuille(p_in, p_out):
+    # Clear channel, inlet pressure p_in at x = 0, p_out at x = nx - 1: the
+    # steady state is plane Poiseuille flow with gradient (p_in - p_out) /
+    # (nx - 1) and a linear pressure, to round-off.
+    nx, H = 40, 9
     m = L.Model(L.Geometry(nx, H, H, 0, 0),
-                L.Params(tau_f=1.0, reaction=False, pressure_inlet=True, p_in=p_in, dx_cm=1e-3))
+                L.Params(tau_f=1.0, reaction=False, pressure_inlet=True, p_in=p_in, p_out=p_out, dx_cm=1e-3))
     f = m.fields(m.run(m.initial_state(), 6000))
     y = torch.arange(H, dtype=DT)
-    exact = p_in / (nx - 1) / (2 * m.nu) * (y + 0.5) * (H - 0.5 - y)
+    exact = (p_in - p_out) / (nx - 1) / (2 * m.nu) * (y + 0.5) * (H - 0.5 - y)
     assert float((f["ux"] - exact.view(H, 1)).abs().max() / exact.max()) < 1e-11
     x = torch.arange(nx, dtype=DT)
-    assert float((f["p"] - p_in * (1 - x / (nx - 1))).abs().max()) < 1e-13
+    assert float((f["p"] - (p_in + (p_out - p_in) * x / (nx - 1))).abs().max()) < 1e-13
     assert float(f["uy"].abs().max()) < 1e-15
 
 
