@@ -198,7 +198,7 @@ def bench_3d(steps: int, warmup: int = 50) -> dict:
 
 def bench_polarisation(steps: int) -> dict:
     """Polarisation / power / heat curves of the pressure-driven 200x40
-    cathode (3 inlet pressures x 13 voltages = 39 cases in one batch)."""
+    cathode (3 outlet pressures x 13 voltages = 39 cases in one batch)."""
     import workloads as W
     from paper_2103_01444_amd import BatchedSweep
 
@@ -218,9 +218,9 @@ def bench_polarisation(steps: int) -> dict:
     nu = (cases[0]["tau_f"] - 0.5) / 3.0
     nv = len(W.POLARISATION_V)
     curves = []
-    for j, p_in in enumerate(W.POLARISATION_P_IN):
+    for j, p_out in enumerate(W.POLARISATION_P_OUT):
         o = obs[j * nv:(j + 1) * nv]
-        curves.append({"p_in": p_in, "Re": round(o[-1]["inlet_flux"] / nu, 3), "V": list(W.POLARISATION_V),
+        curves.append({"p_in": W.POLARISATION_P_IN, "p_out": p_out, "Re": round(o[-1]["inlet_flux"] / nu, 3), "V": list(W.POLARISATION_V),
                        "I_A_cm2": [round(x["current_density"], 4) for x in o],
                        "P_W_cm2": [round(x["power_density"], 4) for x in o],
                        "heat_W_cm2": [round(x["heat_rate"], 4) for x in o]})

@@ -75,7 +75,7 @@ typedef enum lbm_status {
 #define LBM_NO_REACTION 8u /* switch the CL reaction off */
 #define LBM_PRESSURE_INLET 32u /* 2D: pressure-driven flow (Section 4): the inlet nodes of the channel rows
                                 * take the pressure lbm_params.p_inlet with the velocity of column 1 (non-
-                                * equilibrium extrapolation), the outlet keeps p = 0; Re is then an output
+                                * equilibrium extrapolation), the outlet has lbm_params.p_outlet; Re is then an output
                                 * (lbm_obs.inlet_flux / nu) and lbm_params.Re is ignored */
 
 typedef struct lbm_geometry {
@@ -120,7 +120,10 @@ typedef struct lbm_params {
   double body_force_y;
   int32_t independent_fields; /* nonzero: keep porosity, 1/K and D_eff as three per-cell fields */
   int32_t reserved;
-  double p_inlet;          /* inlet pressure, lattice units (LBM_PRESSURE_INLET only; outlet p = 0) */
+  double p_inlet;          /* inlet pressure, lattice units (LBM_PRESSURE_INLET only) */
+  double p_outlet;         /* outlet pressure, lattice units (2D; default 0).  Section 5 sets the flow rate
+                            * by the outlet pressure: with LBM_PRESSURE_INLET the channel is driven by
+                            * p_inlet - p_outlet.  The 3D variant requires 0. */
 } lbm_params;
 
 /* Observables of Section 5 on the current state (see Conventions). */
@@ -164,7 +167,7 @@ lbm_status lbm_create(const lbm_geometry* g, void* dev_ws, size_t ws_bytes, void
  * LBM_ERR_UNSTABLE_PARAMS (tau_f <= 0.5, a diffusivity outside
  * (0, 1/(4 sqrt 3)], porosity outside (0, 1], 1/K < 0, inlet peak velocity
  * above 0.1; with LBM_PRESSURE_INLET: the plane-Poiseuille peak velocity
- * p_inlet H^2 / (8 nu (nx - 1)) of the channel above 0.1). */
+ * |p_inlet - p_outlet| H^2 / (8 nu (nx - 1)) of the channel above 0.1). */
 lbm_status lbm_set_params(lbm_ctx* ctx, const lbm_params* p, const void* phi, const void* inv_k,
                           const void* d_eff);
 

@@ -237,6 +237,7 @@ void launch_step3(lbm3d_ctx* c, int64_t n) {
 template <typename R>
 lbm_status set_params3_t(lbm3d_ctx* c, const lbm_params* p, const void* phi, const void* inv_k, const void* d_eff) {
   const lbm3d_geometry& g = c->g;
+  if (p->p_outlet != 0.0) return fail3(c, LBM_ERR_INVALID_ARG, "the 3D variant's outlet pressure is 0 (p_outlet)");
   c->p = *p;
   std::string msg;
   const lbm_geometry lg = as_layers(g);

@@ -322,13 +322,13 @@ __device__ __forceinline__ void boundary_adj(const R (&pre_xp)[19], const Mat<R>
   minvt_times(mu_b, ldm);
   ldm[0] = R(0);
   R lp1 = R(0), lux1 = R(0), luy1 = R(0);
-  // + meq(pb, ub; phi_b): inlet pb = p1 (ub fixed); outlet pb = 0, ub = u1.
+  // + meq(pb, ub; phi_b): inlet pb = p1 (ub fixed); outlet pb = p_out, ub = u1.
   R dumx = R(0), dumy = R(0);
   if (inlet) {
     meq_adj(t.p, ubx, uby, mb.phi, ldm, lp1, dumx, dumy, mab.phi);
   } else {
     R dp = R(0);
-    meq_adj(R(0), t.ux, t.uy, mb.phi, ldm, dp, lux1, luy1, mab.phi);
+    meq_adj(k.p_out, t.ux, t.uy, mb.phi, ldm, dp, lux1, luy1, mab.phi);
   }
   // - meq(p1, u1; phi_xp)
   R nldm[9];

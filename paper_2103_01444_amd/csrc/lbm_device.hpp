@@ -48,6 +48,7 @@ struct Consts {
   R E_over_R, inv_T_arrh, aF_over_R;
   R four_f_cref;        // 4 F C_ref, C / cm^3
   R p_in;               // inlet pressure of the pressure-driven mode
+  R p_out;              // outlet pressure
 };
 
 template <typename R>
@@ -283,8 +284,8 @@ __device__ __forceinline__ R inlet_velocity(const Consts<R>& k, int y) {
 // the boundary node's pre-collision populations (inlet: velocity u_in(y)
 // with the pressure of the neighbour, or in the pressure-driven mode the
 // pressure p_in with the neighbour's velocity; Dirichlet theta = 0 and
-// c = c_in; outlet: zero pressure with the neighbour's velocity, scalars
-// copied).
+// c = c_in; outlet: the outlet pressure p_out with the neighbour's velocity,
+// scalars copied).
 template <typename R>
 __device__ __forceinline__ void boundary_column(R (&f)[19], const Consts<R>& k, int y, bool inlet, const Mat<R>& mp,
                                                 const Mat<R>& mb) {
@@ -301,7 +302,7 @@ __device__ __forceinline__ void boundary_column(R (&f)[19], const Consts<R>& k, 
   } else {
     ubx = a.ux;
     uby = a.uy;
-    pb = R(0);
+    pb = k.p_out;
   }
   R m1[9], m2[9], dm[9], df[9];
   meq_shifted(pb, ubx, uby, mb.phi, m1);

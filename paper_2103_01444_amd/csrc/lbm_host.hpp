@@ -80,10 +80,14 @@ inline lbm_status derive(const lbm_geometry& g, const lbm_params& p, Derived& d,
     err = "inlet peak velocity above 0.1";
     return LBM_ERR_UNSTABLE_PARAMS;
   }
+  if (!std::isfinite(p.p_outlet)) {
+    err = "p_outlet is not finite";
+    return LBM_ERR_INVALID_ARG;
+  }
   if (pressure && !(g.flags & LBM_PERIODIC_X)) {
     // plane Poiseuille estimate of the channel's peak velocity
     const double H = g.ny_channel;
-    const double umax = std::fabs(p.p_inlet) / (g.nx - 1) * H * H / (8.0 * d.nu);
+    const double umax = std::fabs(p.p_inlet - p.p_outlet) / (g.nx - 1) * H * H / (8.0 * d.nu);
     if (!std::isfinite(p.p_inlet) || umax > 0.1) {
       err = "inlet pressure drives a channel peak velocity above 0.1";
       return LBM_ERR_UNSTABLE_PARAMS;
@@ -157,6 +161,7 @@ void fill_consts(Consts<R>& k, const lbm_geometry& g, const lbm_params& p, const
   k.aF_over_R = R(p.alpha_c * p.faraday / p.R_gas);
   k.four_f_cref = R(4.0 * p.faraday * p.C_ref);
   k.p_in = R(p.p_inlet);
+  k.p_out = R(p.p_outlet);
 }
 
 }  // namespace lbm

@@ -48,7 +48,8 @@ class Geometry3D(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in _PARAM_NAMES] + [
-        ("independent_fields", ctypes.c_int32), ("reserved", ctypes.c_int32), ("p_inlet", ctypes.c_double)]
+        ("independent_fields", ctypes.c_int32), ("reserved", ctypes.c_int32), ("p_inlet", ctypes.c_double),
+        ("p_outlet", ctypes.c_double)]
 
 
 class Obs(ctypes.Structure):
@@ -174,6 +175,8 @@ def params_from_workload(w: dict, **over) -> Params:
         p.dp_lat = float(w["dp_lat"])
     if "p_in" in w:
         p.p_inlet = float(w["p_in"])
+    if "p_out" in w:
+        p.p_outlet = float(w["p_out"])
     for k, v in over.items():
         setattr(p, k, v)
     return p

@@ -46,13 +46,27 @@ def test_binding_names_match_header():
     assert set(lbm.EXPORTED) <= _declared()
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every binding struct has the size and field offsets that a C compiler
+    gives the header's struct of the same name."""
     from paper_2103_01444_amd import lbm
-    # lbm_geometry: 7 x 4 bytes; lbm_params: 28 doubles + 2 int32 + 1 double; lbm_obs: int64 + 11 doubles.
-    assert ctypes.sizeof(lbm.Geometry) == 28
-    assert ctypes.sizeof(lbm.Params) == 28 * 8 + 8 + 8
-    assert ctypes.sizeof(lbm.Obs) == 8 + 11 * 8
-    assert ctypes.sizeof(lbm.Geometry3D) == 32  # lbm3d_geometry: 8 x 4 bytes
+    pairs = [(lbm.Geometry, "lbm_geometry"), (lbm.Params, "lbm_params"), (lbm.Obs, "lbm_obs"),
+             (lbm.Geometry3D, "lbm3d_geometry"), (lbm.Schedule, "lbm_schedule")]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "lbm_pem.h"', "int main(void) {"]
+    expect = []
+    for cls, cname in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(cls))
+        for name, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {name}));')
+            expect.append(getattr(cls, name).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == expect
 
 
 def test_defaults_are_the_paper_constants(lib):

@@ -59,6 +59,22 @@ def test_fp64_adjoint_matches_oracle_gradient(size, nsteps, every):
     _compare(g, (gphi, gk, gd), w["ny_channel"], 1e-9, f"{nx}x{ny} fp64")
 
 
+def test_fp64_adjoint_with_outlet_pressure_matches_oracle_gradient():
+    # a nonzero outlet pressure enters the outlet column's equilibrium through its porosity
+    lbm = _lbm()
+    w = W.adjoint2d(14, 10)
+    w.update(ny_channel=5, ny_gdl=4, ny_cl=1, Re=2.0, V_op=0.45, precision=64, p_out=3e-3)
+    phi = W.porosity_field(w)
+    sim = lbm.Cathode.from_workload(w, phi=phi, independent_fields=1)
+    J = sim.forward_checkpointed(40, 15)
+    g = sim.backward(1.0)
+    fields = _oracle_fields(w, phi)
+    Jo, gphi, gk, gd = A.gradient(L.geometry_from_workload(w), L.Params.from_workload(w), *fields, nsteps=40,
+                                  every=15)
+    assert abs(J / float(Jo) - 1) < 1e-12
+    _compare(g, (gphi, gk, gd), w["ny_channel"], 1e-9, "14x10 fp64 p_out")
+
+
 # Relative finite-difference steps: J is about 1e3 times less sensitive to
 # 1/K than to porosity, so a 1e-5 step for 1/K would leave the difference
 # quotient dominated by the ~1e-14 relative rounding of J.

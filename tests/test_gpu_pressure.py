@@ -25,19 +25,22 @@ def _case(precision=64, **over):
     return w
 
 
-def test_pressure_driven_channel_is_exact_poiseuille_on_gpu():
+@pytest.mark.parametrize("p_in,p_out", [(2e-3, 0.0), (5e-3, 3e-3)])
+def test_pressure_driven_channel_is_exact_poiseuille_on_gpu(p_in, p_out):
     lbm = _lbm()
-    nx, H, p_in = 40, 9, 2e-3
-    w = dict(_case(), nx=nx, ny=H, ny_channel=H, ny_gdl=0, ny_cl=0, p_in=p_in, tau_f=1.0)
+    nx, H = 40, 9
+    w = dict(_case(), nx=nx, ny=H, ny_channel=H, ny_gdl=0, ny_cl=0, p_in=p_in, p_out=p_out, tau_f=1.0)
     gpu = lbm.Cathode.from_workload(w, flags=lbm.LBM_NO_REACTION, dx_cm=1e-3)
     gpu.step(6000)
     f = gpu.fields()
     nu = (1.0 - 0.5) / 3.0
     y = torch.arange(H, dtype=DT)
-    exact = p_in / (nx - 1) / (2 * nu) * (y + 0.5) * (H - 0.5 - y)
+    exact = (p_in - p_out) / (nx - 1) / (2 * nu) * (y + 0.5) * (H - 0.5 - y)
     err = float((f["ux"].cpu() - exact.view(H, 1)).abs().max() / exact.max())
-    print(f"pressure-driven Poiseuille on GPU: rel err {err:.1e}", flush=True)
-    assert err < 1e-11
+    x = torch.arange(nx, dtype=DT)
+    perr = float((f["p"].cpu() - (p_in + (p_out - p_in) * x / (nx - 1))).abs().max())
+    print(f"pressure-driven Poiseuille on GPU: rel err {err:.1e}, pressure err {perr:.1e}", flush=True)
+    assert err < 1e-11 and perr < 1e-13
 
 
 @pytest.mark.parametrize("mode", ["layered", "phi", "full"])
@@ -45,7 +48,7 @@ def test_pressure_driven_channel_is_exact_poiseuille_on_gpu():
 def test_one_step_from_arbitrary_state_pressure_inlet(mode, precision):
     lbm = _lbm()
     nx, ny, layers = 203, 37, (18, 15, 4)
-    w = _case(precision, nx=nx, ny=ny, ny_channel=layers[0], ny_gdl=layers[1], ny_cl=layers[2], p_in=3e-3)
+    w = _case(precision, nx=nx, ny=ny, ny_channel=layers[0], ny_gdl=layers[1], ny_cl=layers[2], p_in=3e-3, p_out=1e-3)
     rng = np.random.default_rng(500 + precision)
     phi = inv_k = d_eff = None
     if mode != "layered":
@@ -122,17 +125,60 @@ def test_adjoint_rejects_the_pressure_inlet():
 
 
 def test_polarisation_sweep_trends():
-    """Section 5 trends on the 39-case sweep after 6000 steps: the current
-    density rises as the voltage falls, and at low voltage it rises with
-    the flow rate (inlet pressure)."""
+    """Section 5 trends on the 39-case sweep after 30000 steps: from 0.6 V up
+    the current density falls with the voltage (kinetic region); below it
+    the curve flattens at a transport-limited plateau; at every voltage up
+    to 0.55 V the current rises with the flow rate (lower outlet pressure)."""
     lbm = _lbm()
     cases = W.polarisation_sweep()
     b = lbm.BatchedSweep(cases)
     b.autotune(trial_steps=5)
-    b.step(6000)
-    I = np.array([o["current_density"] for o in b.observables()]).reshape(len(W.POLARISATION_P_IN), -1)
-    flux = np.array([o["inlet_flux"] for o in b.observables()]).reshape(len(W.POLARISATION_P_IN), -1)
-    print("I(V) per inlet pressure:", np.array2string(I, precision=3), flush=True)
-    assert np.all(np.diff(I, axis=1) < 0)          # voltages ascend along axis 1
-    assert np.all(np.diff(I[:, 0]) > 0)            # more flow, more current at 0.30 V
-    assert np.all(np.diff(flux[:, 0]) > 0)         # more pressure, more flow
+    b.step(30000)
+    obs = b.observables()
+    I = np.array([o["current_density"] for o in obs]).reshape(len(W.POLARISATION_P_OUT), -1)
+    flux = np.array([o["inlet_flux"] for o in obs]).reshape(len(W.POLARISATION_P_OUT), -1)
+    print("I(V) per outlet pressure:", np.array2string(I, precision=3), flush=True)
+    v = np.array(W.POLARISATION_V)
+    kinetic, plateau = v >= 0.599, v <= 0.551
+    assert np.all(np.diff(I[:, kinetic], axis=1) < 0)              # voltages ascend along axis 1
+    assert np.all(I[:, plateau].min(1) > 0.9 * I.max(1))            # mass-transport plateau
+    assert np.all(np.diff(I[:, plateau], axis=0) > 0)               # more flow, more current
+    assert np.all(np.diff(flux[:, 0]) > 0)                           # larger pressure drop, more flow
+
+
+def test_section5_parameter_trends():
+    """Section 5 trends at 0.5 V (mid flow rate, 30000 steps, one batch):
+    the current density rises with the operating temperature and with the
+    GDL O2 diffusivity, hardly changes with the GDL porosity at fixed
+    diffusivity, and changes far less than the permeability; at low
+    voltage the CL O2 concentration and the local current fall toward the
+    outlet."""
+    lbm = _lbm()
+    base = dict(W.polarisation_sweep()[len(W.POLARISATION_V) + 4], deff_ratio_gdl=0.4 ** 1.5)
+    assert base["V_op"] == 0.5 and base["p_out"] == W.POLARISATION_P_OUT[1]
+    variants = [{}, dict(T_in=323.0), dict(T_in=373.0), dict(deff_ratio_gdl=0.5 * 0.4 ** 1.5),
+                dict(deff_ratio_gdl=2 * 0.4 ** 1.5), dict(phi_gdl=0.3), dict(phi_gdl=0.6),
+                dict(Da_gdl=0.1 * base["Da_gdl"]), dict(Da_gdl=10 * base["Da_gdl"])]
+    b = lbm.BatchedSweep([dict(base, **v) for v in variants])
+    b.step(30000)
+    I = [o["current_density"] for o in b.observables()]
+    print("I:", np.round(I, 4), flush=True)
+    i0, t323, t373, dlo, dhi, plo, phi_hi, klo, khi = I
+    assert t323 < i0 < t373
+    assert dlo < i0 < dhi
+    assert abs(plo / i0 - 1) < 0.05 and abs(phi_hi / i0 - 1) < 0.05
+    assert abs(klo / i0 - 1) < 0.1 and abs(khi / i0 - 1) < 0.5       # 100x in K
+    s = lbm.Cathode.from_workload(base)
+    s.step(30000)
+    o = s.observables()
+    n = len(o["c_profile"])
+    head, tail = slice(1, n // 10), slice(n - n // 10, n - 1)
+    assert o["c_profile"][head].mean() > o["c_profile"][tail].mean()
+    assert o["i_profile"][head].mean() > o["i_profile"][tail].mean()
+
+
+def test_3d_rejects_an_outlet_pressure():
+    lbm = _lbm()
+    w3 = W.cathode3d_scaled(16, 6, 10, precision=64, sphere_radius=1.5, filter_box=3, Re=1.0)
+    with pytest.raises(lbm.LbmError, match="p_outlet"):
+        lbm.Cathode3D.from_workload(dict(w3, p_out=1e-3))

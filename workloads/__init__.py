@@ -55,9 +55,11 @@ SEED_ADJOINT_FD = 21030147
 SEED_SPHERE_PACK = 21030148
 SEED_ADJOINT3D_FD = 21030149
 
-# Inlet pressures (lattice units) of the polarisation sweep: plane-Poiseuille
+# Polarisation sweep: fixed inlet pressure, three outlet pressures (lattice
+# units); the pressure drops 2e-3, 4e-3 and 8e-3 give plane-Poiseuille
 # channel peak velocities of about 0.01, 0.02 and 0.04 on the 200x40 lattice.
-POLARISATION_P_IN = (2e-3, 4e-3, 8e-3)
+POLARISATION_P_IN = 8e-3                   # fixed inlet pressure (lattice units)
+POLARISATION_P_OUT = (6e-3, 4e-3, 0.0)     # outlet pressures: rising flow rate
 POLARISATION_V = tuple(round(0.30 + 0.05 * i, 2) for i in range(13))
 
 
@@ -308,14 +310,15 @@ def fd_cells3d(w: dict, n: int = 8, seed: int = SEED_ADJOINT3D_FD, depth: int = 
 
 
 def polarisation_sweep(steps: int = 20000) -> list[dict]:
-    """Cases of the polarisation / power / heat curves (order: inlet
-    pressure, then voltage)."""
+    """Cases of the polarisation / power / heat curves: the flow rate is set
+    by the outlet pressure at a fixed inlet pressure (order: outlet pressure,
+    then voltage)."""
     cases = []
-    for p_in in POLARISATION_P_IN:
+    for p_out in POLARISATION_P_OUT:
         for v in POLARISATION_V:
             w = base_case()
-            w.update(name=f"pol_p{p_in:g}_V{v:.2f}", nx=200, ny=40, ny_channel=20, ny_gdl=18, ny_cl=2,
+            w.update(name=f"pol_pout{p_out:g}_V{v:.2f}", nx=200, ny=40, ny_channel=20, ny_gdl=18, ny_cl=2,
                      precision=32, steps=steps, T_in=353.0, V_op=v, phi_gdl=0.4, Da_gdl=2.73e-4,
-                     D_f_lat=0.025, pressure_inlet=True, p_in=p_in)
+                     D_f_lat=0.025, pressure_inlet=True, p_in=POLARISATION_P_IN, p_out=p_out)
             cases.append(w)
     return cases
