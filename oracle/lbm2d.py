@@ -162,15 +162,18 @@ class Params:
     pressure_inlet: bool = False  # Section 4's pressure-driven flow: inlet pressure p_in, outlet p_out [R17]
     p_in: float = 0.0            # lattice inlet pressure when pressure_inlet (Re is then an output)
     p_out: float = 0.0           # lattice outlet pressure (Section 5 varies it to set the flow rate) [R17]
+    butler_volmer: bool = False  # Eq. 13 with its anodic branch [R18]; False: the printed Tafel form
+    alpha_a: float = 1.0         # anodic transfer coefficient (not given by the paper) [R18]
 
     @staticmethod
     def from_workload(w: dict) -> "Params":
         p = Params()
         for k in ("tau_f", "D_f_lat", "Re", "T_in", "c_in", "V_op", "phi_gdl",
-                  "Da_gdl", "deff_ratio_gdl", "p_in", "p_out"):
+                  "Da_gdl", "deff_ratio_gdl", "p_in", "p_out", "alpha_a"):
             if k in w:
                 setattr(p, k, float(w[k]))
         p.pressure_inlet = bool(w.get("pressure_inlet", False))
+        p.butler_volmer = bool(w.get("butler_volmer", False))
         if w.get("dp_over_hgdl", 0.0) > 0:
             p.dp_lat = w["dp_over_hgdl"] * w["ny_gdl"]
         return p
@@ -192,7 +195,15 @@ def _safe_sqrt(a: torch.Tensor) -> torch.Tensor:
 
 def catalyst_reaction(pr: "Params", dt: float, theta, c, rhocp):
     """Catalyst-layer oxygen reduction over one step of length dt (s); see
-    Model.reaction for the definitions (Eqs. 12-17, [R11], [R12])."""
+    Model.reaction for the definitions (Eqs. 12-17, [R11], [R12]).
+
+    [R18] Butler-Volmer option: Eq. 13 with the anodic branch,
+    j = -a j0 [ c exp(-alpha_c F eta / (R T)) - exp(alpha_a F eta / (R T)) ],
+    concentration dependence on the cathodic branch only.  The O2 balance
+    4 F C_ref dc/dt = -(k c - k_a) is again integrated exactly over the
+    step: c relaxes toward c_eq = k_a / k = exp((alpha_a + alpha_c) F eta
+    / (R T)) at the rate kappa, s_c = (c - c_eq)(1 - exp(-kappa)).
+    """
     T = pr.T_in + theta
     U0 = pr.U0_slope * T + pr.U0_icept
     eta = pr.V_op - U0
@@ -200,7 +211,11 @@ def catalyst_reaction(pr: "Params", dt: float, theta, c, rhocp):
     k = aj0 * torch.exp(-pr.alpha_c * pr.faraday * eta / (pr.R_gas * T))
     four_f_cref = 4.0 * pr.faraday * pr.C_ref
     kappa = k * dt / four_f_cref
-    s_c = -c * torch.expm1(-kappa)
+    if pr.butler_volmer:
+        c_eq = torch.exp((pr.alpha_a + pr.alpha_c) * pr.faraday * eta / (pr.R_gas * T))
+        s_c = -(c - c_eq) * torch.expm1(-kappa)
+    else:
+        s_c = -c * torch.expm1(-kappa)
     j_eff = -four_f_cref * s_c / dt
     Q = -j_eff * (eta + T * pr.U0_slope)
     S_T = Q * dt / rhocp
