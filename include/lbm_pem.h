@@ -90,7 +90,17 @@ typedef struct lbm_geometry {
  * (Nomenclature, Eqs. 7, 13-19) and the solver defaults; the operating point
  * (V_op, T_in_K, Re) and the porous-layer properties are what a user varies
  * (Section 5).
+ *
+ * Kinetics (lbm_params.kinetics): LBM_KINETICS_TAFEL is Eq. 13 as printed,
+ * j = -a j0(T) (C/C_ref) exp(-alpha_c F eta / (R T)).  LBM_KINETICS_BUTLER_VOLMER
+ * adds the anodic branch, j = -a j0(T) [(C/C_ref) exp(-alpha_c F eta / (R T))
+ * - exp(alpha_a F eta / (R T))]; the O2 in a CL cell then relaxes over a step
+ * toward exp((alpha_a + alpha_c) F eta / (R T)) instead of 0.  The adjoint
+ * entry points accept the Tafel form only.
  */
+#define LBM_KINETICS_TAFEL 0
+#define LBM_KINETICS_BUTLER_VOLMER 1
+
 typedef struct lbm_params {
   double tau_f;            /* flow relaxation time, nu = (tau_f - 1/2)/3 (Section 2.1); > 0.5 */
   double D_f_lat;          /* O2 diffusivity in the clear gas, lattice units; sets dt */
@@ -119,11 +129,13 @@ typedef struct lbm_params {
   double body_force_x;     /* acceleration, lattice units (LBM_BODY_FORCE only) */
   double body_force_y;
   int32_t independent_fields; /* nonzero: keep porosity, 1/K and D_eff as three per-cell fields */
-  int32_t reserved;
+  int32_t kinetics;        /* LBM_KINETICS_TAFEL (default: Eq. 13 as printed) or LBM_KINETICS_BUTLER_VOLMER */
   double p_inlet;          /* inlet pressure, lattice units (LBM_PRESSURE_INLET only) */
   double p_outlet;         /* outlet pressure, lattice units (2D; default 0).  Section 5 sets the flow rate
                             * by the outlet pressure: with LBM_PRESSURE_INLET the channel is driven by
                             * p_inlet - p_outlet.  The 3D variant requires 0. */
+  double alpha_a;          /* anodic transfer coefficient of LBM_KINETICS_BUTLER_VOLMER (the paper gives
+                            * none; default 1.0, equal to alpha_c) */
 } lbm_params;
 
 /* Observables of Section 5 on the current state (see Conventions). */

@@ -169,7 +169,7 @@ class Params:
     def from_workload(w: dict) -> "Params":
         p = Params()
         for k in ("tau_f", "D_f_lat", "Re", "T_in", "c_in", "V_op", "phi_gdl",
-                  "Da_gdl", "deff_ratio_gdl", "p_in", "p_out", "alpha_a"):
+                  "Da_gdl", "deff_ratio_gdl", "p_in", "p_out", "alpha_a", "aj0_ref"):
             if k in w:
                 setattr(p, k, float(w[k]))
         p.pressure_inlet = bool(w.get("pressure_inlet", False))

@@ -139,7 +139,7 @@ void fill_consts3(Consts3<R>& k, const lbm3d_geometry& g, const lbm_params& p, c
   k.flags = g.flags;
   k.plane = int32_t(int64_t(pitch) * g.ny * g.nz);
   k.ty = std::min(kChunkY, g.ny);
-  k.pad_ = 0;
+  k.bv = k2.bv;
   k.s_plus = k2.s_e;
   k.s_minus = k2.s_q;
   k.nu = k2.nu;
@@ -168,6 +168,7 @@ void fill_consts3(Consts3<R>& k, const lbm3d_geometry& g, const lbm_params& p, c
   k.inv_T_arrh = k2.inv_T_arrh;
   k.aF_over_R = k2.aF_over_R;
   k.four_f_cref = k2.four_f_cref;
+  k.aFsum_over_R = k2.aFsum_over_R;
 }
 
 template <typename R>
@@ -634,6 +635,8 @@ lbm_status lbm3d_forward_checkpointed(lbm3d_ctx* c, int64_t nsteps, int32_t ever
   if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
   if (c->mat != MAT_FULL)
     return fail3(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
+  if (c->p.kinetics != LBM_KINETICS_TAFEL)
+    return fail3(c, LBM_ERR_STATE, "the adjoint covers the Tafel kinetics only (kinetics = LBM_KINETICS_TAFEL)");
   const AdjLayout3 A = adj_layout3(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign3 != 0)
     return fail3(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

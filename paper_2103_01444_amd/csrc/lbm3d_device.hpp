@@ -47,11 +47,12 @@ struct Consts3 {
   uint32_t flags;
   int32_t plane;  // pitch * ny * nz elements
   int32_t ty;     // y rows per chunk of the launch order
-  int32_t pad_;
+  int32_t bv;     // nonzero: Butler-Volmer kinetics
   R s_plus, s_minus, nu, u_in_coef, ax, ay;
   R phi_gdl, invk_gdl, d_gdl, D_f, kc_inv, deff_ratio;
   R k_f, k_s, rhocp_f, rhocp_s, alpha_scale;
   R T_in, c_in, V_op, U0_slope, U0_icept, ln_k0, E_over_R, inv_T_arrh, aF_over_R, four_f_cref;
+  R aFsum_over_R;  // (alpha_a + alpha_c) F / R, Butler-Volmer only
 };
 
 template <typename R>

@@ -366,6 +366,8 @@ void lbm_default_params(lbm_params* p) {
   p->k_s = 1.5;
   p->rhocp_f = 1.0e-3;
   p->rhocp_s = 1.6;
+  p->kinetics = LBM_KINETICS_TAFEL;
+  p->alpha_a = 1.0;
 }
 
 size_t lbm_workspace_bytes(const lbm_geometry* g) {
@@ -637,6 +639,8 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, v
     return fail(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
   if (c->g.flags & LBM_PRESSURE_INLET)
     return fail(c, LBM_ERR_STATE, "the adjoint covers the velocity inlet, not LBM_PRESSURE_INLET");
+  if (c->p.kinetics != LBM_KINETICS_TAFEL)
+    return fail(c, LBM_ERR_STATE, "the adjoint covers the Tafel kinetics only (kinetics = LBM_KINETICS_TAFEL)");
   const AdjLayout A = adj_layout(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign != 0)
     return fail(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

@@ -31,7 +31,7 @@ struct Consts {
   int32_t nx, ny, pitch, ny_ch, y_cl0;
   uint32_t flags;
   int32_t plane;        // elements per population plane (pitch * ny)
-  int32_t pad_;
+  int32_t bv;           // nonzero: Butler-Volmer kinetics (anodic branch), else the printed Tafel form
   // flow (Section 2.1)
   R s_e, s_q, nu;       // s_e: rate of rho, e, zeta, pxx, pxy; s_q: energy flux
   R u_in_coef;          // 6 U_avg / H_channel^2
@@ -49,6 +49,7 @@ struct Consts {
   R four_f_cref;        // 4 F C_ref, C / cm^3
   R p_in;               // inlet pressure of the pressure-driven mode
   R p_out;              // outlet pressure
+  R aFsum_over_R;       // (alpha_a + alpha_c) F / R, Butler-Volmer only
 };
 
 template <typename R>
@@ -330,6 +331,9 @@ struct React {
 // CL oxygen reduction over one step (Eqs. 12-17), integrated exactly in time:
 // kappa = a j0(T) exp(-alpha_c F eta / (R T)) dt / (4 F C_ref),
 // s_c = c (1 - exp(-kappa)), heat source 4 F C_ref s_c (eta + T dU0/dT) / (rho c_p).
+// Butler-Volmer (Eq. 13 with the anodic branch, O2 dependence on the
+// cathodic branch only): c relaxes toward c_eq = exp((alpha_a + alpha_c) F
+// eta / (R T)) instead of 0, s_c = (c - c_eq)(1 - exp(-kappa)).
 // K: the launch constants (2D or 3D), which carry the same reaction fields.
 template <typename R, typename K>
 __device__ __forceinline__ React<R> reaction(R theta, R c, R rhocp, const K& k) {
@@ -338,7 +342,8 @@ __device__ __forceinline__ React<R> reaction(R theta, R c, R rhocp, const K& k) 
   const R eta = k.V_op - (k.U0_slope * T + k.U0_icept);
   const R kappa = exp(k.ln_k0 - k.E_over_R * (iT - k.inv_T_arrh) - k.aF_over_R * eta * iT);
   React<R> r;
-  r.s_c = -c * expm1(-kappa);
+  const R ceq = k.bv ? exp(k.aFsum_over_R * eta * iT) : R(0);
+  r.s_c = -(c - ceq) * expm1(-kappa);
   r.ehs = eta + T * k.U0_slope;
   r.S_T = k.four_f_cref * r.s_c * r.ehs / rhocp;
   return r;

@@ -80,6 +80,14 @@ inline lbm_status derive(const lbm_geometry& g, const lbm_params& p, Derived& d,
     err = "inlet peak velocity above 0.1";
     return LBM_ERR_UNSTABLE_PARAMS;
   }
+  if (p.kinetics != LBM_KINETICS_TAFEL && p.kinetics != LBM_KINETICS_BUTLER_VOLMER) {
+    err = "kinetics must be LBM_KINETICS_TAFEL or LBM_KINETICS_BUTLER_VOLMER";
+    return LBM_ERR_INVALID_ARG;
+  }
+  if (p.kinetics == LBM_KINETICS_BUTLER_VOLMER && !(p.alpha_a >= 0 && std::isfinite(p.alpha_a))) {
+    err = "alpha_a must be finite and non-negative";
+    return LBM_ERR_INVALID_ARG;
+  }
   if (!std::isfinite(p.p_outlet)) {
     err = "p_outlet is not finite";
     return LBM_ERR_INVALID_ARG;
@@ -131,7 +139,7 @@ void fill_consts(Consts<R>& k, const lbm_geometry& g, const lbm_params& p, const
   k.y_cl0 = g.ny_channel + g.ny_gdl;
   k.flags = g.flags;
   k.plane = int32_t(int64_t(pitch) * g.ny);
-  k.pad_ = 0;
+  k.bv = p.kinetics == LBM_KINETICS_BUTLER_VOLMER;
   const double se = 1.0 / p.tau_f;
   k.s_e = R(se);
   k.s_q = R(8.0 * (2.0 - se) / (8.0 - se));
@@ -162,6 +170,7 @@ void fill_consts(Consts<R>& k, const lbm_geometry& g, const lbm_params& p, const
   k.four_f_cref = R(4.0 * p.faraday * p.C_ref);
   k.p_in = R(p.p_inlet);
   k.p_out = R(p.p_outlet);
+  k.aFsum_over_R = R((p.alpha_a + p.alpha_c) * p.faraday / p.R_gas);
 }
 
 }  // namespace lbm

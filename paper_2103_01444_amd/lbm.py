@@ -23,6 +23,8 @@ LBM_BODY_FORCE = 4
 LBM_NO_REACTION = 8
 LBM_PERIODIC_Z = 16
 LBM_PRESSURE_INLET = 32
+LBM_KINETICS_TAFEL = 0
+LBM_KINETICS_BUTLER_VOLMER = 1
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "parameters outside the stable range", 3: "device error",
           4: "non-finite result", 5: "call out of order"}
@@ -48,8 +50,8 @@ class Geometry3D(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in _PARAM_NAMES] + [
-        ("independent_fields", ctypes.c_int32), ("reserved", ctypes.c_int32), ("p_inlet", ctypes.c_double),
-        ("p_outlet", ctypes.c_double)]
+        ("independent_fields", ctypes.c_int32), ("kinetics", ctypes.c_int32), ("p_inlet", ctypes.c_double),
+        ("p_outlet", ctypes.c_double), ("alpha_a", ctypes.c_double)]
 
 
 class Obs(ctypes.Structure):
@@ -177,6 +179,12 @@ def params_from_workload(w: dict, **over) -> Params:
         p.p_inlet = float(w["p_in"])
     if "p_out" in w:
         p.p_outlet = float(w["p_out"])
+    if w.get("butler_volmer", False):
+        p.kinetics = LBM_KINETICS_BUTLER_VOLMER
+    if "alpha_a" in w:
+        p.alpha_a = float(w["alpha_a"])
+    if "aj0_ref" in w:
+        p.aj0_ref = float(w["aj0_ref"])
     for k, v in over.items():
         setattr(p, k, v)
     return p

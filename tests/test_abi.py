@@ -75,6 +75,7 @@ def test_defaults_are_the_paper_constants(lib):
     assert (p.aj0_ref, p.C_ref, p.alpha_c, p.faraday, p.R_gas) == (1e-4, 17.808e-6, 1.0, 96487.0, 8.314)
     assert (p.D_O2_cm2s, p.k_f, p.k_s, p.U0_slope, p.U0_icept) == (5.2197e-2, 0.026, 1.5, 0.0025, 0.2329)
     assert (p.E_over_R, p.T_arrh) == (16456.0, 353.15)
+    assert (p.kinetics, p.alpha_a, p.p_inlet, p.p_outlet) == (lbm.LBM_KINETICS_TAFEL, 1.0, 0.0, 0.0)
 
 
 def test_workspace_size_and_geometry_checks(lib):
