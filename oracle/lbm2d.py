@@ -164,16 +164,19 @@ class Params:
     p_out: float = 0.0           # lattice outlet pressure (Section 5 varies it to set the flow rate) [R17]
     butler_volmer: bool = False  # Eq. 13 with its anodic branch [R18]; False: the printed Tafel form
     alpha_a: float = 1.0         # anodic transfer coefficient (not given by the paper) [R18]
+    thin_cl: bool = False        # CL of negligible thickness: a reactive wall under the GDL [R19]
+    thin_cl_cm: float = 0.0      # thickness whose volumetric a j0 the film carries; <= 0: one lattice spacing
 
     @staticmethod
     def from_workload(w: dict) -> "Params":
         p = Params()
         for k in ("tau_f", "D_f_lat", "Re", "T_in", "c_in", "V_op", "phi_gdl",
-                  "Da_gdl", "deff_ratio_gdl", "p_in", "p_out", "alpha_a", "aj0_ref"):
+                  "Da_gdl", "deff_ratio_gdl", "p_in", "p_out", "alpha_a", "aj0_ref", "thin_cl_cm"):
             if k in w:
                 setattr(p, k, float(w[k]))
         p.pressure_inlet = bool(w.get("pressure_inlet", False))
         p.butler_volmer = bool(w.get("butler_volmer", False))
+        p.thin_cl = bool(w.get("thin_cl", False))
         if w.get("dp_over_hgdl", 0.0) > 0:
             p.dp_lat = w["dp_over_hgdl"] * w["ny_gdl"]
         return p
@@ -253,6 +256,9 @@ class Model:
         self.dt = prm.D_f_lat * self.dx ** 2 / prm.D_O2
         self.u_avg = (prm.Re * self.nu / geom.ny_channel
                       if geom.ny_channel > 0 and not prm.pressure_inlet else 0.0)
+        if prm.thin_cl and (geom.ny_cl != 0 or geom.ny_gdl < 1 or geom.periodic_y):
+            raise ValueError("the thin-film CL lies under the GDL: ny_cl = 0, ny_gdl >= 1, walls in y")
+        self.thin = prm.thin_cl * (prm.thin_cl_cm if prm.thin_cl_cm > 0 else self.dx)
 
         rows = torch.arange(ny).view(ny, 1).expand(ny, nx)
         self.is_channel = rows < geom.ny_channel
@@ -413,7 +419,47 @@ class Model:
             for q, (ex, ey) in enumerate(E):
                 src = torch.roll(post[base + q], shifts=(ey, ex), dims=(0, 1))
                 out[base + q] = torch.where(inside[q], src, post[base + OPP[q]])
+        if self.p.thin_cl and self.p.reaction:
+            d_c, d_t, _, _ = self.surface_reaction(post)
+            y = self.g.ny - 1
+            out[9 + 4, y] = out[9 + 4, y] + d_t      # reflected temperature population (-y)
+            out[14 + 4, y] = out[14 + 4, y] - d_c    # reflected O2 population (-y)
         return out
+
+    def surface_reaction(self, post: torch.Tensor):
+        """[R19] Thin-film CL (the paper's CL of negligible thickness): the
+        wall half a cell below the last GDL row reacts.  Each bottom node's
+        populations that cross that wall (index 2 of Eq. 9, moving +y) are
+        reflected minus the O2 the film consumes and plus the heat it
+        releases.  The film carries the volumetric rate of Eq. 13 over a
+        thickness delta: k_s = a j0(T) delta exp(-alpha_c F eta / (R T))
+        [A/cm^2 per unit c].  Wall values: c_w = g_in / a and theta_w =
+        g_T,in / a_T with a = (4 + b)/20 the equilibrium weight of a moving
+        population (zero wall-normal velocity).  Over one step, exactly in
+        time for the incident population: kappa_s = k_s dt / (4 F C_ref dx),
+        d_c = (g_in - a c_eq)(1 - exp(-kappa_s / a)) (c_eq = 0 for Tafel, the
+        Butler-Volmer value [R18] otherwise); heat d_T = 4 F C_ref d_c
+        (eta + T dU0/dT) / (rho c_p) (Eq. 15).  Returns per column (d_c, d_T,
+        i_s [A/cm^2], Q_s [W/cm^2])."""
+        pr, y = self.p, self.g.ny - 1
+        a_t = (4.0 + self.b_T[y]) / 20.0
+        a_c = (4.0 + self.b_C[y]) / 20.0
+        g_t, g_c = post[9 + 2, y], post[14 + 2, y]
+        T = pr.T_in + g_t / a_t
+        eta = pr.V_op - (pr.U0_slope * T + pr.U0_icept)
+        aj0 = pr.aj0_ref * torch.exp(-pr.E_over_R * (1.0 / T - 1.0 / pr.T_arrh))
+        k_s = aj0 * self.thin * torch.exp(-pr.alpha_c * pr.faraday * eta / (pr.R_gas * T))
+        four_f_cref = 4.0 * pr.faraday * pr.C_ref
+        kappa_s = k_s * self.dt / (four_f_cref * self.dx)
+        if pr.butler_volmer:
+            c_eq = torch.exp((pr.alpha_a + pr.alpha_c) * pr.faraday * eta / (pr.R_gas * T))
+        else:
+            c_eq = torch.zeros_like(T)
+        d_c = -(g_c - a_c * c_eq) * torch.expm1(-kappa_s / a_c)
+        ehs = eta + T * pr.U0_slope
+        d_t = four_f_cref * d_c * ehs / self.rhocp[y]
+        i_s = four_f_cref * self.dx * d_c / self.dt
+        return d_c, d_t, i_s, i_s * ehs
 
     def open_boundaries(self, pre: torch.Tensor) -> torch.Tensor:
         """Inlet and outlet columns by non-equilibrium extrapolation [R7].
@@ -558,7 +604,10 @@ class Model:
         pressure inlet [R17] the inlet velocities are those of the state);
         inlet flux = sum over the inlet nodes of u_x (lattice units);
         T_max; CL profiles of c and T on the CL row next to the GDL;
-        population sums and the per-step consumption / heating.
+        population sums and the per-step consumption / heating.  With the
+        thin-film CL [R19], i(x) and the heat are the film's, taken in the
+        streaming that produced the pre-collision populations, and the
+        profiles are those of the row above the film.
         """
         pre = self.pre_collision(post)
         theta, c = pre[9:14].sum(0), pre[14:19].sum(0)
@@ -568,8 +617,20 @@ class Model:
         s_c, S_T = torch.where(cl, s_c, zero), torch.where(cl, S_T, zero)
         j_eff, Q = torch.where(cl, j_eff, zero), torch.where(cl, Q, zero)
         i_x = (-j_eff).sum(0) * self.dx
+        q_x = Q.sum(0) * self.dx
+        if self.p.thin_cl and self.p.reaction:
+            # [R19] the film's consumption and heat in the streaming that
+            # produced these pre-collision populations; the outlet column
+            # carries the copy of column nx-2 [R10].
+            d_c, d_t, i_x, q_x = self.surface_reaction(post)
+            if not self.g.periodic_x:
+                last = lambda a: torch.cat([a[:-1], a[-2:-1]])
+                d_c, d_t, i_x, q_x = last(d_c), last(d_t), last(i_x), last(q_x)
+            s_c = torch.zeros_like(theta)
+            S_T = torch.zeros_like(theta)
+            s_c[-1], S_T[-1] = d_c, d_t
         I = i_x.mean()
-        H = (Q.sum(0) * self.dx).mean()
+        H = q_x.mean()
         hc = self.g.ny_channel
         if hc > 0 and not self.g.periodic_x:
             u_in, _, _, _, _ = self.flow_macros(pre[0:9, :hc, 0], self.phi[:hc, 0], self.l0[:hc, 0],
@@ -584,7 +645,9 @@ class Model:
             inflow = (self.inlet_velocity() * self.p.c_in).sum() if hc > 0 else torch.zeros((), dtype=DT)
         util = s_c.sum() / inflow if float(inflow) > 0 else torch.zeros((), dtype=DT)
         ycl = self.g.ny - self.g.ny_cl
-        if self.g.ny_cl > 0:
+        if self.p.thin_cl:  # [R19] the row above the film
+            c_prof, T_prof = c[-1], self.p.T_in + theta[-1]
+        elif self.g.ny_cl > 0:
             c_prof, T_prof = c[ycl], self.p.T_in + theta[ycl]
         else:  # no CL row: the profiles are defined as zeros
             c_prof = T_prof = torch.zeros(self.g.nx, dtype=DT)
