@@ -233,6 +233,34 @@ def bench_polarisation(steps: int) -> dict:
             "curves_after_steps": steps, "max_rel_change_I_last_tenth": round(drift, 6), "curves": curves}
 
 
+def bench_variants(steps: int) -> dict:
+    """The 4096x1024 FP32 benchmark lattice under the model options, same
+    porosity field: pressure-driven inlet and outlet pressure, Butler-Volmer
+    kinetics, thin-film CL (CL rows merged into the GDL, film below)."""
+    import workloads as W
+    from paper_2103_01444_amd import Cathode
+
+    base = W.cathode2d_4096x1024()
+    phi = W.porosity_field(base)
+    thin = dict(base, thin_cl=True, ny_gdl=base["ny_gdl"] + base["ny_cl"], ny_cl=0)
+    variants = {"pressure_inlet": dict(base, pressure_inlet=True, p_in=2e-4, p_out=5e-5),
+                "butler_volmer": dict(base, butler_volmer=True),
+                "thin_cl": thin}
+    cells = base["nx"] * base["ny"]
+    out = {}
+    for name, w in variants.items():
+        sim = Cathode.from_workload(w, phi=phi)
+        sim.step(50)
+        wall, ev = _timed(sim.stream, lambda: sim.step(steps))
+        o = sim.observables()
+        del sim
+        achieved = cells * (BYTES_PER_LU_POPS + BYTES_PER_LU_PHI) * steps / ev / 1e9
+        out[name] = {"value": round(cells * steps / wall / 1e6, 1), "unit": "MLUPS", "steps": steps,
+                     "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "current_density_A_cm2": o["current_density"]}
+    return out
+
+
 ADJ3_BYTES_PER_LU = 33 * 4 * 3 + 3 * 4 + 3 * 4 * 2  # 3D reverse step, same streams as in 2D
 FWD3_FULL_BYTES_PER_LU = 33 * 4 * 2 + 3 * 4         # replayed 3D forward step with three per-cell fields
 
@@ -279,6 +307,7 @@ def main():
     ap.add_argument("--steps3d", type=int, default=5000, help="0 skips the 3D cathode")
     ap.add_argument("--adjoint3d-steps", type=int, default=5000, help="0 skips the 3D adjoint")
     ap.add_argument("--polarisation-steps", type=int, default=100000, help="0 skips the polarisation sweep")
+    ap.add_argument("--variant-steps", type=int, default=2000, help="0 skips the model-option variants")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write copy kernel 5 times (counter calibration)")
     args = ap.parse_args()
@@ -357,6 +386,11 @@ def main():
                         "o2_utilisation": obs["o2_utilisation"]},
     }
     del sim
+    if args.variant_steps > 0:
+        print("bench: model-option variants", file=sys.stderr, flush=True)
+        line["variants"] = bench_variants(args.variant_steps)
+        print("bench: variants " + ", ".join(f"{k} {v['value']} MLUPS" for k, v in line["variants"].items()),
+              file=sys.stderr, flush=True)
     if args.batched_steps > 0:
         print("bench: batched sweep", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(args.batched_steps, max(1, args.batched_steps // 2))

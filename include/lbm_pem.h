@@ -77,6 +77,12 @@ typedef enum lbm_status {
                                 * take the pressure lbm_params.p_inlet with the velocity of column 1 (non-
                                 * equilibrium extrapolation), the outlet has lbm_params.p_outlet; Re is then an output
                                 * (lbm_obs.inlet_flux / nu) and lbm_params.Re is ignored */
+#define LBM_THIN_CL 64u /* 2D: the CL has negligible thickness (Section 1): a reactive wall half a cell
+                         * below the last GDL row (requires ny_cl = 0, ny_gdl >= 1, no LBM_PERIODIC_Y).  The
+                         * temperature and O2 populations that cross it are reflected minus the O2 the film
+                         * consumes and plus the heat it releases; the film carries the volumetric rate of
+                         * Eq. 13 over the thickness lbm_params.thin_cl_cm.  Observables: i(x) is the film's
+                         * current, the c and T profiles are those of the last row. */
 
 typedef struct lbm_geometry {
   int32_t nx, ny;                      /* nx >= 3, ny >= 1 */
@@ -136,6 +142,7 @@ typedef struct lbm_params {
                             * p_inlet - p_outlet.  The 3D variant requires 0. */
   double alpha_a;          /* anodic transfer coefficient of LBM_KINETICS_BUTLER_VOLMER (the paper gives
                             * none; default 1.0, equal to alpha_c) */
+  double thin_cl_cm;       /* LBM_THIN_CL film thickness, cm; <= 0: one lattice spacing */
 } lbm_params;
 
 /* Observables of Section 5 on the current state (see Conventions). */

@@ -641,6 +641,8 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, v
     return fail(c, LBM_ERR_STATE, "the adjoint covers the velocity inlet, not LBM_PRESSURE_INLET");
   if (c->p.kinetics != LBM_KINETICS_TAFEL)
     return fail(c, LBM_ERR_STATE, "the adjoint covers the Tafel kinetics only (kinetics = LBM_KINETICS_TAFEL)");
+  if (c->g.flags & LBM_THIN_CL)
+    return fail(c, LBM_ERR_STATE, "the adjoint covers the volumetric CL, not LBM_THIN_CL");
   const AdjLayout A = adj_layout(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign != 0)
     return fail(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

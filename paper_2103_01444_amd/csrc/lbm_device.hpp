@@ -19,6 +19,7 @@ constexpr uint32_t F_PERIODIC_Y = 2u;
 constexpr uint32_t F_BODY_FORCE = 4u;
 constexpr uint32_t F_NO_REACTION = 8u;
 constexpr uint32_t F_PRESSURE_INLET = 32u;
+constexpr uint32_t F_THIN_CL = 64u;
 
 // Velocity sets of Eq. 2 (planes 0-8) and Eq. 9 (planes 9-13 and 14-18).
 constexpr int EX[19] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 0, 1, 0, -1, 0, 0, 1, 0, -1, 0};
@@ -50,6 +51,7 @@ struct Consts {
   R p_in;               // inlet pressure of the pressure-driven mode
   R p_out;              // outlet pressure
   R aFsum_over_R;       // (alpha_a + alpha_c) F / R, Butler-Volmer only
+  R ln_thin;            // ln(film thickness / dx), thin-film CL only
 };
 
 template <typename R>
@@ -241,6 +243,10 @@ __device__ __forceinline__ void boundary_column(R (&f)[19], const Consts<R>& k, 
                                                 const Mat<R>& mb);
 template <typename R>
 __device__ __forceinline__ void outlet_scalar_material(Mat<R>& mb, const Mat<R>& mp);
+template <typename R>
+struct React;
+template <typename R>
+__device__ __forceinline__ React<R> surface_reaction(R g_t, R g_c, const Mat<R>& m, const Consts<R>& k);
 
 template <typename R, int MAT>
 __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const Consts<R>& k,
@@ -254,6 +260,13 @@ __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const
   const int xp = inlet ? 1 : (outlet ? k.nx - 2 : x);
   pull(src, k, xp, y, f);
   Mat<R> mp = material<R, MAT>(k, phi_f, invk_f, d_f, xp, y);
+  if ((k.flags & F_THIN_CL) && !(k.flags & F_NO_REACTION) && y == k.ny - 1) {
+    // thin-film CL: planes 13 and 18 hold the bounced-back populations that
+    // crossed the reactive wall below this row
+    const React<R> r = surface_reaction(f[13], f[18], mp, k);
+    f[13] += r.S_T;
+    f[18] -= r.s_c;
+  }
   if (!(inlet || outlet)) return mp;
   Mat<R> mb = material<R, MAT>(k, phi_f, invk_f, d_f, x, y);
   boundary_column(f, k, y, inlet, mp, mb);
@@ -346,6 +359,31 @@ __device__ __forceinline__ React<R> reaction(R theta, R c, R rhocp, const K& k) 
   r.s_c = -(c - ceq) * expm1(-kappa);
   r.ehs = eta + T * k.U0_slope;
   r.S_T = k.four_f_cref * r.s_c * r.ehs / rhocp;
+  return r;
+}
+
+// Thin-film CL (the CL of negligible thickness): the wall half a cell below
+// the last row reacts with the Eq. 13 kinetics carried over a film of
+// thickness delta, k_s = a j0(T) delta exp(-alpha_c F eta / (R T)).  The wall
+// values come from the populations that cross it, c_w = g_c / a_c and
+// theta_w = g_t / a_t, a = (4 + b) / 20 being the equilibrium weight of a
+// moving population at zero wall-normal velocity.  Exactly in time for the
+// incident population: s_c = (g_c - a_c c_eq)(1 - exp(-kappa_s / a_c)),
+// kappa_s = k_s dt / (4 F C_ref dx); heat 4 F C_ref s_c (eta + T dU0/dT) / (rho c_p).
+template <typename R>
+__device__ __forceinline__ React<R> surface_reaction(R g_t, R g_c, const Mat<R>& m, const Consts<R>& k) {
+  const R a_t = (R(4) + m.bT) / R(20);
+  const R a_c = (R(4) + m.bC) / R(20);
+  const R T = k.T_in + g_t / a_t;
+  const R iT = R(1) / T;
+  const R eta = k.V_op - (k.U0_slope * T + k.U0_icept);
+  const R kappa_a =
+      exp(k.ln_k0 + k.ln_thin - k.E_over_R * (iT - k.inv_T_arrh) - k.aF_over_R * eta * iT) / a_c;
+  const R ceq = k.bv ? exp(k.aFsum_over_R * eta * iT) : R(0);
+  React<R> r;
+  r.s_c = -(g_c - a_c * ceq) * expm1(-kappa_a);
+  r.ehs = eta + T * k.U0_slope;
+  r.S_T = k.four_f_cref * r.s_c * r.ehs / m.rhocp;
   return r;
 }
 

@@ -79,6 +79,17 @@ __device__ __forceinline__ double wave_max(double v) {
 // per workgroup: sum f (shifted), sum theta, sum c, sum s_c, sum S_T,
 // sum s_c (eta + T dU0/dT), max theta, count of non-finite values, sum of
 // u_x over the inlet nodes.
+// The thin-film CL's reaction at the bottom node of column x, as the last
+// streaming applied it: from the populations of the pulled column (column
+// nx - 2 for the outlet, whose scalars are that column's) that crossed the
+// wall, with the scalar material the node collides with.
+template <typename R>
+__device__ __forceinline__ React<R> film(const R* __restrict__ src, const Consts<R>& k, int x, const Mat<R>& mt) {
+  const int xp = (!(k.flags & F_PERIODIC_X) && x == k.nx - 1) ? k.nx - 2 : x;
+  const int o = (k.ny - 1) * k.pitch + xp;
+  return surface_reaction(src[11 * k.plane + o], src[16 * k.plane + o], mt, k);
+}
+
 template <typename R, int MAT>
 __global__ __launch_bounds__(kBlock) void k_obs_cells(const R* __restrict__ src,
                                                       const R* __restrict__ phi_f,
@@ -104,6 +115,11 @@ __global__ __launch_bounds__(kBlock) void k_obs_cells(const R* __restrict__ src,
     v[2] = c;
     if (y >= k.y_cl0 && !(k.flags & F_NO_REACTION)) {
       const React<R> r = reaction(R(th), R(c), mt.rhocp, k);
+      v[3] = double(r.s_c);
+      v[4] = double(r.S_T);
+      v[5] = double(r.s_c) * double(r.ehs);
+    } else if ((k.flags & F_THIN_CL) && !(k.flags & F_NO_REACTION) && y == k.ny - 1) {
+      const React<R> r = film(src, k, x, mt);
       v[3] = double(r.s_c);
       v[4] = double(r.S_T);
       v[5] = double(r.s_c) * double(r.ehs);
@@ -171,6 +187,13 @@ __global__ __launch_bounds__(kBlock) void k_obs_profiles(const R* __restrict__ s
   if (x >= k.nx) return;
   double isum = 0, c0 = 0, t0 = 0;
   const bool react = !(k.flags & F_NO_REACTION);
+  if (k.flags & F_THIN_CL) {  // the film's current, the profiles of the row above it
+    R f[19];
+    const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, k.ny - 1, f);
+    c0 = double(f[14] + f[15] + f[16] + f[17] + f[18]);
+    t0 = double(k.T_in) + double(f[9] + f[10] + f[11] + f[12] + f[13]);
+    if (react) isum = double(film(src, k, x, mt).s_c);
+  }
   for (int y = k.y_cl0; y < k.ny; ++y) {
     R f[19];
     const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);

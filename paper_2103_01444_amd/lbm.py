@@ -23,6 +23,7 @@ LBM_BODY_FORCE = 4
 LBM_NO_REACTION = 8
 LBM_PERIODIC_Z = 16
 LBM_PRESSURE_INLET = 32
+LBM_THIN_CL = 64
 LBM_KINETICS_TAFEL = 0
 LBM_KINETICS_BUTLER_VOLMER = 1
 
@@ -51,7 +52,7 @@ class Geometry3D(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in _PARAM_NAMES] + [
         ("independent_fields", ctypes.c_int32), ("kinetics", ctypes.c_int32), ("p_inlet", ctypes.c_double),
-        ("p_outlet", ctypes.c_double), ("alpha_a", ctypes.c_double)]
+        ("p_outlet", ctypes.c_double), ("alpha_a", ctypes.c_double), ("thin_cl_cm", ctypes.c_double)]
 
 
 class Obs(ctypes.Structure):
@@ -185,6 +186,8 @@ def params_from_workload(w: dict, **over) -> Params:
         p.alpha_a = float(w["alpha_a"])
     if "aj0_ref" in w:
         p.aj0_ref = float(w["aj0_ref"])
+    if "thin_cl_cm" in w:
+        p.thin_cl_cm = float(w["thin_cl_cm"])
     for k, v in over.items():
         setattr(p, k, v)
     return p
@@ -192,7 +195,8 @@ def params_from_workload(w: dict, **over) -> Params:
 
 def workload_flags(w: dict) -> int:
     """Geometry flags a workload dictionary asks for (pressure-driven inlet)."""
-    return LBM_PRESSURE_INLET if w.get("pressure_inlet", False) else 0
+    return ((LBM_PRESSURE_INLET if w.get("pressure_inlet", False) else 0)
+            | (LBM_THIN_CL if w.get("thin_cl", False) else 0))
 
 
 def _ptr(t):
