@@ -158,6 +158,7 @@ class Params:
     rhocp_f: float = 1.0e-3      # J/(cm^3 K) [R1]
     rhocp_s: float = 1.6         # J/(cm^3 K) [R1]
     body_force: tuple = (0.0, 0.0)  # test mode only: acceleration in lattice units [R5]
+    buoyancy: tuple = (0.0, 0.0)    # Boussinesq acceleration per kelvin of T - T_in, lattice units [R20]
     reaction: bool = True
     pressure_inlet: bool = False  # Section 4's pressure-driven flow: inlet pressure p_in, outlet p_out [R17]
     p_in: float = 0.0            # lattice inlet pressure when pressure_inlet (Re is then an output)
@@ -174,6 +175,8 @@ class Params:
                   "Da_gdl", "deff_ratio_gdl", "p_in", "p_out", "alpha_a", "aj0_ref", "thin_cl_cm"):
             if k in w:
                 setattr(p, k, float(w[k]))
+        if "buoyancy" in w:
+            p.buoyancy = tuple(float(v) for v in w["buoyancy"])
         p.pressure_inlet = bool(w.get("pressure_inlet", False))
         p.butler_volmer = bool(w.get("butler_volmer", False))
         p.thin_cl = bool(w.get("thin_cl", False))
@@ -379,17 +382,24 @@ class Model:
         ])
 
     # ---------------------------------------------------------------- macros
-    def flow_macros(self, f, phi, l0, l1, inv_k, sqrt_inv_k, F_phi):
+    def flow_macros(self, f, phi, l0, l1, inv_k, sqrt_inv_k, F_phi, theta=None):
         """Eq. 8 and the pressure relation of Section 2.1.
 
         v = sum e_i f_i / rho0 (+ dt phi a / 2 in body-force test mode [R5]);
         u = v / (l0 + sqrt(l0^2 + l1 |v|));
         F = -phi nu K^-1 u - phi F_phi K^-1/2 |u| u (+ phi a)   (Eq. 7);
         p = (0.6/phi) sum_{i=1..8} f_i - 6 rho0 |u|^2 / (15 phi^2).
+        [R20] Buoyancy: a = body force + b theta, theta = T - T_in of the same
+        node's temperature populations (the Boussinesq force -beta g (T - T_in)
+        of the cavity validations in Section 3, b = -beta g).
         """
         vx = sum(E9[q][0] * f[q] for q in range(9)) / RHO0
         vy = sum(E9[q][1] * f[q] for q in range(9)) / RHO0
         ax, ay = self.p.body_force
+        bx, by = self.p.buoyancy
+        if bx != 0.0 or by != 0.0:
+            ax = ax + bx * theta
+            ay = ay + by * theta
         vx = vx + 0.5 * phi * ax
         vy = vy + 0.5 * phi * ay
         vmag = _safe_sqrt(vx * vx + vy * vy)
@@ -401,11 +411,6 @@ class Model:
         Fy = phi * ay - drag * uy
         p = (0.6 / phi) * sum(f[q] for q in range(1, 9)) - 6.0 * RHO0 * (ux * ux + uy * uy) / (15.0 * phi * phi)
         return ux, uy, p, Fx, Fy
-
-    def _macros_at(self, f, cols):
-        """Flow macros of populations f [9, ny, len(cols)] at lattice columns."""
-        return self.flow_macros(f, self.phi[:, cols], self.l0[:, cols], self.l1[:, cols],
-                                self.inv_k[:, cols], self.sqrt_inv_k[:, cols], self.F_phi[:, cols])
 
     # ------------------------------------------------------------- streaming
     def stream(self, post: torch.Tensor) -> torch.Tensor:
@@ -480,7 +485,7 @@ class Model:
             f1 = pre[0:9, :H, 1]
             ux1, uy1, p1, _, _ = self.flow_macros(
                 f1, self.phi[:H, 1], self.l0[:H, 1], self.l1[:H, 1], self.inv_k[:H, 1],
-                self.sqrt_inv_k[:H, 1], self.F_phi[:H, 1])
+                self.sqrt_inv_k[:H, 1], self.F_phi[:H, 1], pre[9:14, :H, 1].sum(0))
             # [R17] Section 4 drives the flow by a pressure difference between
             # inlet and outlet: the inlet nodes get the pressure p_in with the
             # velocity of column 1 (non-equilibrium extrapolation, as the
@@ -502,7 +507,7 @@ class Model:
         f2 = pre[0:9, :, c2]
         ux2, uy2, p2, _, _ = self.flow_macros(
             f2, self.phi[:, c2], self.l0[:, c2], self.l1[:, c2], self.inv_k[:, c2],
-            self.sqrt_inv_k[:, c2], self.F_phi[:, c2])
+            self.sqrt_inv_k[:, c2], self.F_phi[:, c2], pre[9:14, :, c2].sum(0))
         out[0:9, :, nx - 1] = (self.feq(torch.full_like(p2, self.p.p_out), ux2, uy2, self.phi[:, nx - 1]) + f2
                                - self.feq(p2, ux2, uy2, self.phi[:, c2]))
         out[9:19, :, nx - 1] = pre[9:19, :, c2]
@@ -532,7 +537,7 @@ class Model:
         """Collision of every node (Eq. 1 RHS, Eq. 10 RHS) plus the CL source."""
         f, gT, gC = pre[0:9], pre[9:14], pre[14:19]
         ux, uy, p, Fx, Fy = self.flow_macros(f, self.phi, self.l0, self.l1, self.inv_k,
-                                             self.sqrt_inv_k, self.F_phi)
+                                             self.sqrt_inv_k, self.F_phi, gT.sum(0))
         phi = self.phi
         # Eq. 1 in moment space: m* = m - S (m - m_eq) + (I - S/2) G.
         m = _mv(M9, f)
@@ -590,9 +595,9 @@ class Model:
         """u_x, u_y, p (lattice), T (K), c (relative) of the pre-collision
         populations of a state."""
         pre = self.pre_collision(post)
-        ux, uy, p, _, _ = self.flow_macros(pre[0:9], self.phi, self.l0, self.l1, self.inv_k,
-                                           self.sqrt_inv_k, self.F_phi)
         theta = pre[9:14].sum(0)
+        ux, uy, p, _, _ = self.flow_macros(pre[0:9], self.phi, self.l0, self.l1, self.inv_k,
+                                           self.sqrt_inv_k, self.F_phi, theta)
         return dict(ux=ux, uy=uy, p=p, T=self.p.T_in + theta, theta=theta, c=pre[14:19].sum(0))
 
     def observables(self, post: torch.Tensor) -> dict:
@@ -635,7 +640,7 @@ class Model:
         if hc > 0 and not self.g.periodic_x:
             u_in, _, _, _, _ = self.flow_macros(pre[0:9, :hc, 0], self.phi[:hc, 0], self.l0[:hc, 0],
                                                 self.l1[:hc, 0], self.inv_k[:hc, 0], self.sqrt_inv_k[:hc, 0],
-                                                self.F_phi[:hc, 0])
+                                                self.F_phi[:hc, 0], theta[:hc, 0])
             flux = u_in.sum()
         else:
             flux = torch.zeros((), dtype=DT)
