@@ -77,6 +77,10 @@ typedef enum lbm_status {
                                 * take the pressure lbm_params.p_inlet with the velocity of column 1 (non-
                                 * equilibrium extrapolation), the outlet has lbm_params.p_outlet; Re is then an output
                                 * (lbm_obs.inlet_flux / nu) and lbm_params.Re is ignored */
+#define LBM_BUOYANCY 128u /* 2D: Boussinesq buoyancy (the thermal-to-flow coupling of the Section 3 cavity
+                          * validations): phi * (T - T_in) * (buoyancy_x, buoyancy_y) is added to the flow
+                          * force (Eq. 7) and half of it to Eq. 8's v, T from the node's own temperature
+                          * populations; with LBM_BODY_FORCE both accelerations add */
 #define LBM_THIN_CL 64u /* 2D: the CL has negligible thickness (Section 1): a reactive wall half a cell
                          * below the last GDL row (requires ny_cl = 0, ny_gdl >= 1, no LBM_PERIODIC_Y).  The
                          * temperature and O2 populations that cross it are reflected minus the O2 the film
@@ -143,6 +147,8 @@ typedef struct lbm_params {
   double alpha_a;          /* anodic transfer coefficient of LBM_KINETICS_BUTLER_VOLMER (the paper gives
                             * none; default 1.0, equal to alpha_c) */
   double thin_cl_cm;       /* LBM_THIN_CL film thickness, cm; <= 0: one lattice spacing */
+  double buoyancy_x;       /* LBM_BUOYANCY: acceleration per kelvin of T - T_in, lattice units (-beta g) */
+  double buoyancy_y;
 } lbm_params;
 
 /* Observables of Section 5 on the current state (see Conventions). */

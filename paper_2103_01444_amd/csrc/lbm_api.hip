@@ -643,6 +643,8 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, v
     return fail(c, LBM_ERR_STATE, "the adjoint covers the Tafel kinetics only (kinetics = LBM_KINETICS_TAFEL)");
   if (c->g.flags & LBM_THIN_CL)
     return fail(c, LBM_ERR_STATE, "the adjoint covers the volumetric CL, not LBM_THIN_CL");
+  if (c->g.flags & LBM_BUOYANCY)
+    return fail(c, LBM_ERR_STATE, "the adjoint does not cover LBM_BUOYANCY");
   const AdjLayout A = adj_layout(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign != 0)
     return fail(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

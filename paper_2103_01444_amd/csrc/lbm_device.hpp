@@ -20,6 +20,7 @@ constexpr uint32_t F_BODY_FORCE = 4u;
 constexpr uint32_t F_NO_REACTION = 8u;
 constexpr uint32_t F_PRESSURE_INLET = 32u;
 constexpr uint32_t F_THIN_CL = 64u;
+constexpr uint32_t F_BUOYANCY = 128u;
 
 // Velocity sets of Eq. 2 (planes 0-8) and Eq. 9 (planes 9-13 and 14-18).
 constexpr int EX[19] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 0, 1, 0, -1, 0, 0, 1, 0, -1, 0};
@@ -52,6 +53,7 @@ struct Consts {
   R p_out;              // outlet pressure
   R aFsum_over_R;       // (alpha_a + alpha_c) F / R, Butler-Volmer only
   R ln_thin;            // ln(film thickness / dx), thin-film CL only
+  R bx, by;             // buoyancy: acceleration per kelvin of temperature rise
 };
 
 template <typename R>
@@ -139,15 +141,28 @@ struct Macro {
   R ux, uy, p, Fx, Fy;
 };
 
-// Eq. 8 velocity recovery, Eq. 7 drag, Section 2.1 pressure relation.
+// Eq. 8 velocity recovery, Eq. 7 drag, Section 2.1 pressure relation.  The
+// acceleration a (test-mode body force and/or Boussinesq buoyancy b theta,
+// theta from this node's temperature populations) enters as phi a in F and
+// phi a / 2 in v.
 template <typename R>
 __device__ __forceinline__ Macro<R> flow_macros(const R (&f)[19], const Mat<R>& m, const Consts<R>& k) {
   R vx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
   R vy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-  const bool body = k.flags & F_BODY_FORCE;
+  const bool body = k.flags & (F_BODY_FORCE | F_BUOYANCY);
+  R ax = R(0), ay = R(0);
+  if (k.flags & F_BODY_FORCE) {
+    ax = k.ax;
+    ay = k.ay;
+  }
+  if (k.flags & F_BUOYANCY) {
+    const R th = f[9] + f[10] + f[11] + f[12] + f[13];
+    ax += k.bx * th;
+    ay += k.by * th;
+  }
   if (body) {
-    vx += R(0.5) * m.phi * k.ax;
-    vy += R(0.5) * m.phi * k.ay;
+    vx += R(0.5) * m.phi * ax;
+    vy += R(0.5) * m.phi * ay;
   }
   const R vmag = dsqrt(vx * vx + vy * vy);
   const R den = m.l0 + dsqrt(m.l0 * m.l0 + m.l1 * vmag);
@@ -159,8 +174,8 @@ __device__ __forceinline__ Macro<R> flow_macros(const R (&f)[19], const Mat<R>& 
   o.Fx = -drag * o.ux;
   o.Fy = -drag * o.uy;
   if (body) {
-    o.Fx += m.phi * k.ax;
-    o.Fy += m.phi * k.ay;
+    o.Fx += m.phi * ax;
+    o.Fy += m.phi * ay;
   }
   const R s18 = f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
   const R iphi = R(1) / m.phi;

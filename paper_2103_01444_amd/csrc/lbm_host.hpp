@@ -25,7 +25,7 @@ inline bool geometry_ok(const lbm_geometry* g) {
   if (g->ny_channel + g->ny_gdl + g->ny_cl != g->ny) return false;
   if (g->precision != 32 && g->precision != 64) return false;
   if (g->flags & ~(LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_BODY_FORCE | LBM_NO_REACTION | LBM_PRESSURE_INLET |
-                   LBM_THIN_CL))
+                   LBM_THIN_CL | LBM_BUOYANCY))
     return false;
   if ((g->flags & LBM_THIN_CL) && (g->ny_cl != 0 || g->ny_gdl < 1 || (g->flags & LBM_PERIODIC_Y)))
     return false;  // the film lies under the GDL, at a wall
@@ -89,6 +89,10 @@ inline lbm_status derive(const lbm_geometry& g, const lbm_params& p, Derived& d,
   }
   if (p.kinetics == LBM_KINETICS_BUTLER_VOLMER && !(p.alpha_a >= 0 && std::isfinite(p.alpha_a))) {
     err = "alpha_a must be finite and non-negative";
+    return LBM_ERR_INVALID_ARG;
+  }
+  if (!std::isfinite(p.buoyancy_x) || !std::isfinite(p.buoyancy_y)) {
+    err = "buoyancy is not finite";
     return LBM_ERR_INVALID_ARG;
   }
   if (!std::isfinite(p.thin_cl_cm)) {
@@ -179,6 +183,8 @@ void fill_consts(Consts<R>& k, const lbm_geometry& g, const lbm_params& p, const
   k.p_out = R(p.p_outlet);
   k.aFsum_over_R = R((p.alpha_a + p.alpha_c) * p.faraday / p.R_gas);
   k.ln_thin = R(std::log((p.thin_cl_cm > 0 ? p.thin_cl_cm : d.dx) / d.dx));
+  k.bx = R(p.buoyancy_x);
+  k.by = R(p.buoyancy_y);
 }
 
 }  // namespace lbm

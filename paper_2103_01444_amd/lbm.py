@@ -24,6 +24,7 @@ LBM_NO_REACTION = 8
 LBM_PERIODIC_Z = 16
 LBM_PRESSURE_INLET = 32
 LBM_THIN_CL = 64
+LBM_BUOYANCY = 128
 LBM_KINETICS_TAFEL = 0
 LBM_KINETICS_BUTLER_VOLMER = 1
 
@@ -52,7 +53,8 @@ class Geometry3D(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in _PARAM_NAMES] + [
         ("independent_fields", ctypes.c_int32), ("kinetics", ctypes.c_int32), ("p_inlet", ctypes.c_double),
-        ("p_outlet", ctypes.c_double), ("alpha_a", ctypes.c_double), ("thin_cl_cm", ctypes.c_double)]
+        ("p_outlet", ctypes.c_double), ("alpha_a", ctypes.c_double), ("thin_cl_cm", ctypes.c_double),
+        ("buoyancy_x", ctypes.c_double), ("buoyancy_y", ctypes.c_double)]
 
 
 class Obs(ctypes.Structure):
@@ -188,6 +190,8 @@ def params_from_workload(w: dict, **over) -> Params:
         p.aj0_ref = float(w["aj0_ref"])
     if "thin_cl_cm" in w:
         p.thin_cl_cm = float(w["thin_cl_cm"])
+    if "buoyancy" in w:
+        p.buoyancy_x, p.buoyancy_y = (float(v) for v in w["buoyancy"])
     for k, v in over.items():
         setattr(p, k, v)
     return p
@@ -196,7 +200,8 @@ def params_from_workload(w: dict, **over) -> Params:
 def workload_flags(w: dict) -> int:
     """Geometry flags a workload dictionary asks for (pressure-driven inlet)."""
     return ((LBM_PRESSURE_INLET if w.get("pressure_inlet", False) else 0)
-            | (LBM_THIN_CL if w.get("thin_cl", False) else 0))
+            | (LBM_THIN_CL if w.get("thin_cl", False) else 0)
+            | (LBM_BUOYANCY if "buoyancy" in w else 0))
 
 
 def _ptr(t):
