@@ -159,6 +159,8 @@ class Params:
     rhocp_s: float = 1.6         # J/(cm^3 K) [R1]
     body_force: tuple = (0.0, 0.0)  # test mode only: acceleration in lattice units [R5]
     buoyancy: tuple = (0.0, 0.0)    # Boussinesq acceleration per kelvin of T - T_in, lattice units [R20]
+    sigma_energy: bool = False   # porous energy equation with the heat-capacity ratio sigma [R21]
+    heat_physical: bool = False  # reaction heat with the irreversible part counted positive [R22]
     reaction: bool = True
     pressure_inlet: bool = False  # Section 4's pressure-driven flow: inlet pressure p_in, outlet p_out [R17]
     p_in: float = 0.0            # lattice inlet pressure when pressure_inlet (Re is then an output)
@@ -180,6 +182,8 @@ class Params:
         p.pressure_inlet = bool(w.get("pressure_inlet", False))
         p.butler_volmer = bool(w.get("butler_volmer", False))
         p.thin_cl = bool(w.get("thin_cl", False))
+        p.sigma_energy = bool(w.get("sigma_energy", False))
+        p.heat_physical = bool(w.get("heat_physical", False))
         if w.get("dp_over_hgdl", 0.0) > 0:
             p.dp_lat = w["dp_over_hgdl"] * w["ny_gdl"]
         return p
@@ -223,7 +227,12 @@ def catalyst_reaction(pr: "Params", dt: float, theta, c, rhocp):
     else:
         s_c = -c * torch.expm1(-kappa)
     j_eff = -four_f_cref * s_c / dt
-    Q = -j_eff * (eta + T * pr.U0_slope)
+    if pr.heat_physical:
+        # [R22] with dU0/dT > 0 and eta < 0 the printed -j eta is negative;
+        # the irreversible heat is |j| |eta|, the entropic part stays -j T dU0/dT
+        Q = -j_eff * (T * pr.U0_slope - eta)
+    else:
+        Q = -j_eff * (eta + T * pr.U0_slope)
     S_T = Q * dt / rhocp
     return s_c, S_T, j_eff, Q, k
 
@@ -297,7 +306,15 @@ class Model:
         # (conductivities W/(m K) -> W/(cm K)).
         self.rhocp = phi * prm.rhocp_f + (1.0 - phi) * prm.rhocp_s
         k_eff = (prm.k_f * phi + prm.k_s * (1.0 - phi)) / 100.0
-        self.alpha = k_eff / self.rhocp * self.dt / self.dx ** 2
+        if prm.sigma_energy:
+            # [R21] sigma dT/dt + u.grad T = div(alpha_m grad T) + Q / (rho c_p)_f,
+            # sigma = (rho c_p)_eff / (rho c_p)_f, alpha_m = k_eff / (rho c_p)_f:
+            # the temperature lattice conserves sigma T.
+            self.sigma = self.rhocp / prm.rhocp_f
+            self.alpha = k_eff / prm.rhocp_f * self.dt / self.dx ** 2
+        else:
+            self.sigma = torch.ones_like(self.rhocp)
+            self.alpha = k_eff / self.rhocp * self.dt / self.dx ** 2
         # Eq. 10: b = 20 sqrt(3) alpha - 4 for each scalar lattice.
         self.b_T = 20.0 * _S3 * self.alpha - 4.0
         self.b_C = 20.0 * _S3 * self.d_eff - 4.0
@@ -309,9 +326,11 @@ class Model:
         # outlet becomes a source or sink proportional to X (unstable for
         # porosity fields); for layers uniform in x both choices coincide.
         self.b_T_coll, self.b_C_coll, self.rhocp_coll = self.b_T, self.b_C, self.rhocp
+        self.sigma_coll = self.sigma
         if not geom.periodic_x:
             last = lambda a: torch.cat([a[:, :-1], a[:, -2:-1]], dim=1)
             self.b_T_coll, self.b_C_coll, self.rhocp_coll = last(self.b_T), last(self.b_C), last(self.rhocp)
+            self.sigma_coll = last(self.sigma)
         # Eq. 7 and Eq. 8 coefficients (dt = 1).
         self.F_phi = 0.143 * phi ** (-1.5)
         self.sqrt_inv_k = _safe_sqrt(inv_k)
@@ -359,12 +378,17 @@ class Model:
         return _mv(M9_INV, self.meq(p, ux, uy, phi))
 
     @staticmethod
-    def neq(X, ux, uy, b):
-        """Eq. 10: scalar equilibrium moments (X, u_x X, u_y X, b X, 0) [R8]."""
-        return torch.stack([X, ux * X, uy * X, b * X, torch.zeros_like(X)])
+    def neq(X, ux, uy, b, sigma=None):
+        """Eq. 10: scalar equilibrium moments (X, u_x X, u_y X, b X, 0) [R8].
+        [R21] With the heat-capacity ratio: (sigma X, u_x X, u_y X,
+        (b + 4 (1 - sigma)) X, 0), which keeps the second moments of the
+        moving populations, (4 + b) X / 10, and so the diffusivity."""
+        if sigma is None:
+            return torch.stack([X, ux * X, uy * X, b * X, torch.zeros_like(X)])
+        return torch.stack([sigma * X, ux * X, uy * X, (b + 4.0 * (1.0 - sigma)) * X, torch.zeros_like(X)])
 
-    def geq(self, X, ux, uy, b):
-        return _mv(N5_INV, self.neq(X, ux, uy, b))
+    def geq(self, X, ux, uy, b, sigma=None):
+        return _mv(N5_INV, self.neq(X, ux, uy, b, sigma))
 
     @staticmethod
     def forcing_moments(ux, uy, Fx, Fy, phi):
@@ -427,7 +451,7 @@ class Model:
         if self.p.thin_cl and self.p.reaction:
             d_c, d_t, _, _ = self.surface_reaction(post)
             y = self.g.ny - 1
-            out[9 + 4, y] = out[9 + 4, y] + d_t      # reflected temperature population (-y)
+            out[9 + 4, y] = out[9 + 4, y] + d_t * self.sigma[y]  # reflected temperature population (-y) [R21]
             out[14 + 4, y] = out[14 + 4, y] - d_c    # reflected O2 population (-y)
         return out
 
@@ -461,7 +485,7 @@ class Model:
         else:
             c_eq = torch.zeros_like(T)
         d_c = -(g_c - a_c * c_eq) * torch.expm1(-kappa_s / a_c)
-        ehs = eta + T * pr.U0_slope
+        ehs = (T * pr.U0_slope - eta) if pr.heat_physical else (eta + T * pr.U0_slope)
         d_t = four_f_cref * d_c * ehs / self.rhocp[y]
         i_s = four_f_cref * self.dx * d_c / self.dt
         return d_c, d_t, i_s, i_s * ehs
@@ -485,7 +509,7 @@ class Model:
             f1 = pre[0:9, :H, 1]
             ux1, uy1, p1, _, _ = self.flow_macros(
                 f1, self.phi[:H, 1], self.l0[:H, 1], self.l1[:H, 1], self.inv_k[:H, 1],
-                self.sqrt_inv_k[:H, 1], self.F_phi[:H, 1], pre[9:14, :H, 1].sum(0))
+                self.sqrt_inv_k[:H, 1], self.F_phi[:H, 1], pre[9:14, :H, 1].sum(0) / self.sigma[:H, 1])
             # [R17] Section 4 drives the flow by a pressure difference between
             # inlet and outlet: the inlet nodes get the pressure p_in with the
             # velocity of column 1 (non-equilibrium extrapolation, as the
@@ -497,9 +521,9 @@ class Model:
             zero = torch.zeros_like(p1)
             out[0:9, :H, 0] = self.feq(pb, ubx, uby, self.phi[:H, 0]) + f1 - self.feq(p1, ux1, uy1, self.phi[:H, 1])
             gT1, gC1 = pre[9:14, :H, 1], pre[14:19, :H, 1]
-            th1, c1 = gT1.sum(0), gC1.sum(0)
-            out[9:14, :H, 0] = (self.geq(zero, ubx, uby, self.b_T[:H, 0]) + gT1
-                                - self.geq(th1, ux1, uy1, self.b_T[:H, 1]))
+            th1, c1 = gT1.sum(0) / self.sigma[:H, 1], gC1.sum(0)
+            out[9:14, :H, 0] = (self.geq(zero, ubx, uby, self.b_T[:H, 0], self.sigma[:H, 0]) + gT1
+                                - self.geq(th1, ux1, uy1, self.b_T[:H, 1], self.sigma[:H, 1]))
             cin = torch.full_like(p1, self.p.c_in)
             out[14:19, :H, 0] = (self.geq(cin, ubx, uby, self.b_C[:H, 0]) + gC1
                                  - self.geq(c1, ux1, uy1, self.b_C[:H, 1]))
@@ -507,7 +531,7 @@ class Model:
         f2 = pre[0:9, :, c2]
         ux2, uy2, p2, _, _ = self.flow_macros(
             f2, self.phi[:, c2], self.l0[:, c2], self.l1[:, c2], self.inv_k[:, c2],
-            self.sqrt_inv_k[:, c2], self.F_phi[:, c2], pre[9:14, :, c2].sum(0))
+            self.sqrt_inv_k[:, c2], self.F_phi[:, c2], pre[9:14, :, c2].sum(0) / self.sigma[:, c2])
         out[0:9, :, nx - 1] = (self.feq(torch.full_like(p2, self.p.p_out), ux2, uy2, self.phi[:, nx - 1]) + f2
                                - self.feq(p2, ux2, uy2, self.phi[:, c2]))
         out[9:19, :, nx - 1] = pre[9:19, :, c2]
@@ -537,7 +561,7 @@ class Model:
         """Collision of every node (Eq. 1 RHS, Eq. 10 RHS) plus the CL source."""
         f, gT, gC = pre[0:9], pre[9:14], pre[14:19]
         ux, uy, p, Fx, Fy = self.flow_macros(f, self.phi, self.l0, self.l1, self.inv_k,
-                                             self.sqrt_inv_k, self.F_phi, gT.sum(0))
+                                             self.sqrt_inv_k, self.F_phi, gT.sum(0) / self.sigma_coll)
         phi = self.phi
         # Eq. 1 in moment space: m* = m - S (m - m_eq) + (I - S/2) G.
         m = _mv(M9, f)
@@ -547,7 +571,7 @@ class Model:
         m_post = m - S * (m - meq) + (1.0 - S / 2.0) * G
         f_post = _mv(M9_INV, m_post)
 
-        theta, c = gT.sum(0), gC.sum(0)
+        theta, c = gT.sum(0) / self.sigma_coll, gC.sum(0)
         if self.p.reaction:
             s_c, S_T, _, _, _ = self.reaction(theta, c, self.rhocp_coll)
             zero = torch.zeros_like(theta)
@@ -555,17 +579,17 @@ class Model:
             src_T = torch.where(self.is_cl, S_T, zero)
         else:
             src_C = src_T = torch.zeros_like(theta)
-        gT_post = self._collide_scalar(gT, theta, ux, uy, self.b_T_coll, src_T)
+        gT_post = self._collide_scalar(gT, theta, ux, uy, self.b_T_coll, src_T, self.sigma_coll)
         gC_post = self._collide_scalar(gC, c, ux, uy, self.b_C_coll, src_C)
         return torch.cat([f_post, gT_post, gC_post])
 
-    def _collide_scalar(self, g, X, ux, uy, b, src):
+    def _collide_scalar(self, g, X, ux, uy, b, src, sigma=None):
         """Eq. 10 RHS in moment space, n* = n - Q (n - n_eq), plus the source
-        injected with the rest-equilibrium moments src (1, 0, 0, b, 0) [R14]."""
+        injected with the rest-equilibrium moments src (1, 0, 0, b, 0) [R14]
+        (with sigma [R21]: src (sigma, 0, 0, b + 4 (1 - sigma), 0))."""
         n = _mv(N5, g)
-        n_post = n - Q5.view(5, 1, 1) * (n - self.neq(X, ux, uy, b))
-        n_post = n_post + torch.stack([src, torch.zeros_like(src), torch.zeros_like(src), b * src,
-                                       torch.zeros_like(src)])
+        n_post = n - Q5.view(5, 1, 1) * (n - self.neq(X, ux, uy, b, sigma))
+        n_post = n_post + self.neq(src, torch.zeros_like(src), torch.zeros_like(src), b, sigma)
         return _mv(N5_INV, n_post)
 
     def step(self, post: torch.Tensor) -> torch.Tensor:
@@ -580,7 +604,7 @@ class Model:
     def equilibrium_state(self, p, ux, uy, theta, c) -> torch.Tensor:
         """Post-collision state equal to the equilibria of given fields."""
         return torch.cat([self.feq(p, ux, uy, self.phi),
-                          self.geq(theta, ux, uy, self.b_T),
+                          self.geq(theta, ux, uy, self.b_T, self.sigma),
                           self.geq(c, ux, uy, self.b_C)])
 
     def initial_state(self) -> torch.Tensor:
@@ -595,7 +619,7 @@ class Model:
         """u_x, u_y, p (lattice), T (K), c (relative) of the pre-collision
         populations of a state."""
         pre = self.pre_collision(post)
-        theta = pre[9:14].sum(0)
+        theta = pre[9:14].sum(0) / self.sigma_coll
         ux, uy, p, _, _ = self.flow_macros(pre[0:9], self.phi, self.l0, self.l1, self.inv_k,
                                            self.sqrt_inv_k, self.F_phi, theta)
         return dict(ux=ux, uy=uy, p=p, T=self.p.T_in + theta, theta=theta, c=pre[14:19].sum(0))
@@ -615,7 +639,7 @@ class Model:
         profiles are those of the row above the film.
         """
         pre = self.pre_collision(post)
-        theta, c = pre[9:14].sum(0), pre[14:19].sum(0)
+        theta, c = pre[9:14].sum(0) / self.sigma_coll, pre[14:19].sum(0)
         s_c, S_T, j_eff, Q, _ = self.reaction(theta, c, self.rhocp_coll)
         zero = torch.zeros_like(theta)
         cl = self.is_cl if self.p.reaction else torch.zeros_like(self.is_cl)
