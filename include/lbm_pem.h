@@ -81,6 +81,13 @@ typedef enum lbm_status {
                           * validations): phi * (T - T_in) * (buoyancy_x, buoyancy_y) is added to the flow
                           * force (Eq. 7) and half of it to Eq. 8's v, T from the node's own temperature
                           * populations; with LBM_BODY_FORCE both accelerations add */
+#define LBM_SIGMA_ENERGY 256u /* 2D: porous energy equation with the heat-capacity ratio sigma = (rho c_p)_eff /
+                              * (rho c_p)_f: the temperature lattice conserves sigma T and carries the
+                              * diffusivity k_eff / (rho c_p)_f (equilibrium moments (sigma T, u T,
+                              * (b + 4 (1 - sigma)) T, 0)), so that heat diffuses at Eq. 19's alpha_eff and
+                              * is stored in the solid; the reaction heat is unchanged in kelvin per step */
+#define LBM_PHYSICAL_HEAT 512u /* 2D and 3D: the reaction heat with the irreversible part counted positive,
+                                * Q = -j (T dU0/dT - eta), instead of Eq. 15's printed -j (eta + T dU0/dT) */
 #define LBM_THIN_CL 64u /* 2D: the CL has negligible thickness (Section 1): a reactive wall half a cell
                          * below the last GDL row (requires ny_cl = 0, ny_gdl >= 1, no LBM_PERIODIC_Y).  The
                          * temperature and O2 populations that cross it are reflected minus the O2 the film

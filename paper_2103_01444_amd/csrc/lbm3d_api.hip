@@ -38,7 +38,9 @@ bool geometry3_ok(const lbm3d_geometry* g) {
   if (g->nz_channel < 0 || g->nz_gdl < 0 || g->nz_cl < 0) return false;
   if (g->nz_channel + g->nz_gdl + g->nz_cl != g->nz) return false;
   if (g->precision != 32 && g->precision != 64) return false;
-  if (g->flags & ~(LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_PERIODIC_Z | LBM_BODY_FORCE | LBM_NO_REACTION)) return false;
+  if (g->flags & ~(LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_PERIODIC_Z | LBM_BODY_FORCE | LBM_NO_REACTION |
+                   LBM_PHYSICAL_HEAT))
+    return false;
   const int64_t pitch = (int64_t(g->nx) + 63) / 64 * 64;
   if (pitch * g->ny * g->nz * 33 >= (int64_t(1) << 31)) return false;  // 32-bit element offsets
   return true;
@@ -637,6 +639,8 @@ lbm_status lbm3d_forward_checkpointed(lbm3d_ctx* c, int64_t nsteps, int32_t ever
     return fail3(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
   if (c->p.kinetics != LBM_KINETICS_TAFEL)
     return fail3(c, LBM_ERR_STATE, "the adjoint covers the Tafel kinetics only (kinetics = LBM_KINETICS_TAFEL)");
+  if (c->g.flags & LBM_PHYSICAL_HEAT)
+    return fail3(c, LBM_ERR_STATE, "the adjoint covers Eq. 15's printed heat, not LBM_PHYSICAL_HEAT");
   const AdjLayout3 A = adj_layout3(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign3 != 0)
     return fail3(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

@@ -21,6 +21,8 @@ constexpr uint32_t F_NO_REACTION = 8u;
 constexpr uint32_t F_PRESSURE_INLET = 32u;
 constexpr uint32_t F_THIN_CL = 64u;
 constexpr uint32_t F_BUOYANCY = 128u;
+constexpr uint32_t F_SIGMA_ENERGY = 256u;
+constexpr uint32_t F_PHYSICAL_HEAT = 512u;
 
 // Velocity sets of Eq. 2 (planes 0-8) and Eq. 9 (planes 9-13 and 14-18).
 constexpr int EX[19] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 0, 1, 0, -1, 0, 0, 1, 0, -1, 0};
@@ -59,6 +61,7 @@ struct Consts {
 template <typename R>
 struct Mat {
   R phi, invk, sqk, fphi, l0, l1, bT, bC, rhocp;
+  R sig;  // heat-capacity ratio (rho c_p)_eff / (rho c_p)_f with F_SIGMA_ENERGY, else 1
 };
 
 template <typename R>
@@ -105,7 +108,11 @@ __device__ __forceinline__ Mat<R> material(const Consts<R>& k, const R* __restri
   m.l0 = R(0.5) + phi * k.nu * invk * R(0.25);
   m.l1 = phi * m.fphi * m.sqk * R(0.5);
   m.rhocp = phi * k.rhocp_f + (R(1) - phi) * k.rhocp_s;
-  const R alpha = (k.k_f * phi + k.k_s * (R(1) - phi)) * k.alpha_scale / m.rhocp;
+  // Eq. 19; with the heat-capacity ratio the lattice carries k_eff / (rho c_p)_f
+  // and conserves sigma T
+  const bool sigma = k.flags & F_SIGMA_ENERGY;
+  const R alpha = (k.k_f * phi + k.k_s * (R(1) - phi)) * k.alpha_scale / (sigma ? k.rhocp_f : m.rhocp);
+  m.sig = sigma ? m.rhocp / k.rhocp_f : R(1);
   const R c20s3 = R(34.64101615137754587);  // 20 sqrt(3)
   m.bT = c20s3 * alpha - R(4);
   m.bC = c20s3 * d - R(4);
@@ -136,6 +143,14 @@ __device__ __forceinline__ void pull(const R* __restrict__ src, const Consts<R>&
   }
 }
 
+// Temperature rise of a node from its five temperature populations g (their
+// sum is sigma theta with the heat-capacity ratio, theta otherwise).
+template <typename R, typename K>
+__device__ __forceinline__ R theta_of(const R* g, R sig, const K& k) {
+  const R s = g[0] + g[1] + g[2] + g[3] + g[4];
+  return (k.flags & F_SIGMA_ENERGY) ? s / sig : s;
+}
+
 template <typename R>
 struct Macro {
   R ux, uy, p, Fx, Fy;
@@ -156,7 +171,7 @@ __device__ __forceinline__ Macro<R> flow_macros(const R (&f)[19], const Mat<R>& 
     ay = k.ay;
   }
   if (k.flags & F_BUOYANCY) {
-    const R th = f[9] + f[10] + f[11] + f[12] + f[13];
+    const R th = theta_of(f + 9, m.sig, k);
     ax += k.bx * th;
     ay += k.by * th;
   }
@@ -236,12 +251,14 @@ __device__ __forceinline__ void inv_moments9(const R (&m)[9], R* f) {
   f[8] = b58 + a3 + a4 - a5 - a6 - a8;
 }
 
-// Eq. 10 scalar equilibrium N^-1 (X, u_x X, u_y X, b X, 0), added with sign sgn.
+// Eq. 10 scalar equilibrium N^-1 (X, u_x X, u_y X, b X, 0), added with sign
+// sgn; with the heat-capacity ratio sig: N^-1 (sig X, u_x X, u_y X,
+// (b + 4 (1 - sig)) X, 0) (sig = 1 gives the printed form exactly).
 template <typename R>
-__device__ __forceinline__ void add_geq(R X, R ux, R uy, R b, R sgn, R* g) {
-  const R b0 = X * R(0.2);
+__device__ __forceinline__ void add_geq(R X, R ux, R uy, R b, R sgn, R* g, R sig = R(1)) {
+  const R b0 = sig * X * R(0.2);
   const R b1 = R(0.5) * ux * X, b2 = R(0.5) * uy * X;
-  const R b3 = b * X * R(0.05);
+  const R b3 = (b + R(4) * (R(1) - sig)) * X * R(0.05);
   g[0] += sgn * (b0 - R(4) * b3);
   g[1] += sgn * (b0 + b1 + b3);
   g[2] += sgn * (b0 + b2 + b3);
@@ -279,7 +296,7 @@ __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const
     // thin-film CL: planes 13 and 18 hold the bounced-back populations that
     // crossed the reactive wall below this row
     const React<R> r = surface_reaction(f[13], f[18], mp, k);
-    f[13] += r.S_T;
+    f[13] += r.S_T * mp.sig;  // energy sigma theta with the heat-capacity ratio
     f[18] -= r.s_c;
   }
   if (!(inlet || outlet)) return mp;
@@ -300,6 +317,7 @@ __device__ __forceinline__ void outlet_scalar_material(Mat<R>& mb, const Mat<R>&
   mb.bT = mp.bT;
   mb.bC = mp.bC;
   mb.rhocp = mp.rhocp;
+  mb.sig = mp.sig;
 }
 
 // Inlet velocity of row y (parabolic over the channel rows).
@@ -342,10 +360,10 @@ __device__ __forceinline__ void boundary_column(R (&f)[19], const Consts<R>& k, 
 #pragma unroll
   for (int i = 0; i < 9; ++i) f[i] += df[i];
   if (inlet) {
-    const R th1 = f[9] + f[10] + f[11] + f[12] + f[13];
+    const R th1 = theta_of(f + 9, mp.sig, k);
     const R c1 = f[14] + f[15] + f[16] + f[17] + f[18];
-    add_geq(R(0), ubx, uby, mb.bT, R(1), f + 9);
-    add_geq(th1, a.ux, a.uy, mp.bT, R(-1), f + 9);
+    add_geq(R(0), ubx, uby, mb.bT, R(1), f + 9, mb.sig);
+    add_geq(th1, a.ux, a.uy, mp.bT, R(-1), f + 9, mp.sig);
     add_geq(k.c_in, ubx, uby, mb.bC, R(1), f + 14);
     add_geq(c1, a.ux, a.uy, mp.bC, R(-1), f + 14);
   }
@@ -372,7 +390,10 @@ __device__ __forceinline__ React<R> reaction(R theta, R c, R rhocp, const K& k) 
   React<R> r;
   const R ceq = k.bv ? exp(k.aFsum_over_R * eta * iT) : R(0);
   r.s_c = -(c - ceq) * expm1(-kappa);
-  r.ehs = eta + T * k.U0_slope;
+  // Eq. 15 as printed, or with the irreversible part |j| |eta| counted positive
+  // (the sign goes on eta alone, so both forms are the same expression)
+  const R e = (k.flags & F_PHYSICAL_HEAT) ? -eta : eta;
+  r.ehs = e + T * k.U0_slope;
   r.S_T = k.four_f_cref * r.s_c * r.ehs / rhocp;
   return r;
 }
@@ -397,7 +418,8 @@ __device__ __forceinline__ React<R> surface_reaction(R g_t, R g_c, const Mat<R>&
   const R ceq = k.bv ? exp(k.aFsum_over_R * eta * iT) : R(0);
   React<R> r;
   r.s_c = -(g_c - a_c * ceq) * expm1(-kappa_a);
-  r.ehs = eta + T * k.U0_slope;
+  const R e = (k.flags & F_PHYSICAL_HEAT) ? -eta : eta;
+  r.ehs = e + T * k.U0_slope;
   r.S_T = k.four_f_cref * r.s_c * r.ehs / m.rhocp;
   return r;
 }
@@ -427,7 +449,8 @@ __device__ __forceinline__ void collide(R (&f)[19], const Mat<R>& mt, const Cons
   inv_moments9(m, f);
 
   R srcT = R(0), srcC = R(0);
-  const R th = f[9] + f[10] + f[11] + f[12] + f[13];
+  const R thsum = f[9] + f[10] + f[11] + f[12] + f[13];  // sigma theta with the heat-capacity ratio
+  const R th = (k.flags & F_SIGMA_ENERGY) ? thsum / mt.sig : thsum;
   const R c = f[14] + f[15] + f[16] + f[17] + f[18];
   if (cl) {
     const React<R> r = reaction(th, c, mt.rhocp, k);
@@ -440,14 +463,15 @@ __device__ __forceinline__ void collide(R (&f)[19], const Mat<R>& mt, const Cons
   for (int s = 0; s < 2; ++s) {
     R* g = f + 9 + 5 * s;
     const R X = s == 0 ? th : c;
-    const R b = s == 0 ? mt.bT : mt.bC;
+    const R sg = s == 0 ? mt.sig : R(1);
+    const R b = s == 0 ? mt.bT + R(4) * (R(1) - sg) : mt.bC;  // b + 4 (1 - sigma): unchanged at sigma = 1
     const R src = s == 0 ? srcT : srcC;
-    R n0 = X;
+    R n0 = s == 0 ? thsum : c;
     R n1 = g[1] - g[3];
     R n2 = g[2] - g[4];
     R n3 = R(-4) * g[0] + g[1] + g[2] + g[3] + g[4];
     R n4 = g[1] - g[2] + g[3] - g[4];
-    n0 = n0 + src;
+    n0 = n0 + sg * src;
     n1 = n1 - q1 * (n1 - a.ux * X);
     n2 = n2 - q1 * (n2 - a.uy * X);
     n3 = n3 - q3 * (n3 - b * X) + b * src;

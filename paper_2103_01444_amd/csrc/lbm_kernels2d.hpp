@@ -108,6 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_obs_cells(const R* __restrict__ src,
     for (int q = 0; q < 9; ++q) sf += double(f[q]);
 #pragma unroll
     for (int q = 9; q < 14; ++q) th += double(f[q]);
+    if (k.flags & F_SIGMA_ENERGY) th /= double(mt.sig);
 #pragma unroll
     for (int q = 14; q < 19; ++q) c += double(f[q]);
     v[0] = sf;
@@ -191,13 +192,13 @@ __global__ __launch_bounds__(kBlock) void k_obs_profiles(const R* __restrict__ s
     R f[19];
     const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, k.ny - 1, f);
     c0 = double(f[14] + f[15] + f[16] + f[17] + f[18]);
-    t0 = double(k.T_in) + double(f[9] + f[10] + f[11] + f[12] + f[13]);
+    t0 = double(k.T_in) + double(theta_of(f + 9, mt.sig, k));
     if (react) isum = double(film(src, k, x, mt).s_c);
   }
   for (int y = k.y_cl0; y < k.ny; ++y) {
     R f[19];
     const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);
-    const R th = f[9] + f[10] + f[11] + f[12] + f[13];
+    const R th = theta_of(f + 9, mt.sig, k);
     const R c = f[14] + f[15] + f[16] + f[17] + f[18];
     if (react) isum += double(reaction(th, c, mt.rhocp, k).s_c);
     if (y == k.y_cl0) {
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_fields(const R* __restrict__ src,
   if (ux) ux[o] = a.ux;
   if (uy) uy[o] = a.uy;
   if (p) p[o] = a.p;
-  const R th = f[9] + f[10] + f[11] + f[12] + f[13];
+  const R th = theta_of(f + 9, mt.sig, k);
   if (T) T[o] = k.T_in + th;
   if (theta) theta[o] = th;
   if (c) c[o] = f[14] + f[15] + f[16] + f[17] + f[18];

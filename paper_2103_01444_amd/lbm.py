@@ -25,6 +25,8 @@ LBM_PERIODIC_Z = 16
 LBM_PRESSURE_INLET = 32
 LBM_THIN_CL = 64
 LBM_BUOYANCY = 128
+LBM_SIGMA_ENERGY = 256
+LBM_PHYSICAL_HEAT = 512
 LBM_KINETICS_TAFEL = 0
 LBM_KINETICS_BUTLER_VOLMER = 1
 
@@ -201,7 +203,9 @@ def workload_flags(w: dict) -> int:
     """Geometry flags a workload dictionary asks for (pressure-driven inlet)."""
     return ((LBM_PRESSURE_INLET if w.get("pressure_inlet", False) else 0)
             | (LBM_THIN_CL if w.get("thin_cl", False) else 0)
-            | (LBM_BUOYANCY if "buoyancy" in w else 0))
+            | (LBM_BUOYANCY if "buoyancy" in w else 0)
+            | (LBM_SIGMA_ENERGY if w.get("sigma_energy", False) else 0)
+            | (LBM_PHYSICAL_HEAT if w.get("heat_physical", False) else 0))
 
 
 def _ptr(t):
@@ -390,6 +394,7 @@ class Cathode3D:
 
     @classmethod
     def from_workload(cls, w: dict, phi=None, inv_k=None, d_eff=None, flags=0, **over):
+        flags |= workload_flags(w)
         return cls(w["nx"], w["ny"], w["nz"], w["nz_channel"], w["nz_gdl"], w["nz_cl"],
                    params_from_workload(w, **over), precision=w.get("precision", 32), flags=flags, phi=phi,
                    inv_k=inv_k, d_eff=d_eff)

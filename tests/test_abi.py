@@ -89,7 +89,7 @@ def test_workspace_size_and_geometry_checks(lib):
     for bad in (lbm.Geometry(2, 40, 20, 18, 2, 64, 0),      # nx < 3
                 lbm.Geometry(200, 40, 20, 18, 3, 64, 0),    # layers do not sum to ny
                 lbm.Geometry(200, 40, 20, 18, 2, 16, 0),    # precision
-                lbm.Geometry(200, 40, 20, 18, 2, 32, 256),  # unknown flag
+                lbm.Geometry(200, 40, 20, 18, 2, 32, 1024),  # unknown flag
                 lbm.Geometry(200, 40, 20, 18, 2, 32, 64),   # thin-film CL with CL rows
                 lbm.Geometry(200, 40, 40, 0, 0, 32, 64),    # thin-film CL without a GDL
                 lbm.Geometry(200, 40, 20, 20, 0, 32, 64 | 2),  # thin-film CL with periodic y
