@@ -236,7 +236,8 @@ def bench_polarisation(steps: int) -> dict:
 def bench_variants(steps: int) -> dict:
     """The 4096x1024 FP32 benchmark lattice under the model options, same
     porosity field: pressure-driven inlet and outlet pressure, Butler-Volmer
-    kinetics, thin-film CL (CL rows merged into the GDL, film below)."""
+    kinetics, thin-film CL (CL rows merged into the GDL, film below),
+    buoyancy, heat-capacity-ratio energy equation with the physical heat sign."""
     import workloads as W
     from paper_2103_01444_amd import Cathode
 
@@ -245,7 +246,9 @@ def bench_variants(steps: int) -> dict:
     thin = dict(base, thin_cl=True, ny_gdl=base["ny_gdl"] + base["ny_cl"], ny_cl=0)
     variants = {"pressure_inlet": dict(base, pressure_inlet=True, p_in=2e-4, p_out=5e-5),
                 "butler_volmer": dict(base, butler_volmer=True),
-                "thin_cl": thin}
+                "thin_cl": thin,
+                "buoyancy": dict(base, buoyancy=(0.0, -1e-6)),
+                "sigma_energy_physical_heat": dict(base, sigma_energy=True, heat_physical=True)}
     cells = base["nx"] * base["ny"]
     out = {}
     for name, w in variants.items():

@@ -24,25 +24,36 @@ struct Tile {
   int32_t c, x0, y0, pad;
 };
 
-// Advance the cells of one tile (tx x ty cells, row-major inside the tile).
+// Advance cell i (row-major inside the tile) of a tile.
 template <typename R>
+__device__ __forceinline__ void batch_cell(const R* __restrict__ src, R* __restrict__ dst, const Consts<R>& k,
+                                           const Tile& t, int i, int tx) {
+  const int y = t.y0 + i / tx;
+  const int x = t.x0 + i % tx;
+  if (x >= k.nx || y >= k.ny) return;
+  R f[19];
+  const Mat<R> mt = pre_collision<R, MAT_LAYERED>(src, k, nullptr, nullptr, nullptr, x, y, f);
+  collide(f, mt, k, y >= k.y_cl0 && !(k.flags & F_NO_REACTION));
+  const int o = y * k.pitch + x;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
+}
+
+// Advance the cells of one tile (tx x ty cells).  ONE: the tile has exactly
+// one cell per thread (tx ty = kBlock); without the cell loop the kernel
+// needs 59 instead of 76 VGPRs (8 instead of 6 waves per SIMD in FP32).
+template <typename R, bool ONE>
 __device__ __forceinline__ void batch_tile(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
                                            const Tile& t, int parity, int tx, int ty) {
   const Consts<R> k = cases[t.c].k;
   const int64_t o_src = cases[t.c].off[parity], o_dst = cases[t.c].off[parity ^ 1];
   const R* src = pool + o_src;
   R* dst = pool + o_dst;
-  const int n = tx * ty;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int y = t.y0 + i / tx;
-    const int x = t.x0 + i % tx;
-    if (x >= k.nx || y >= k.ny) continue;
-    R f[19];
-    const Mat<R> mt = pre_collision<R, MAT_LAYERED>(src, k, nullptr, nullptr, nullptr, x, y, f);
-    collide(f, mt, k, y >= k.y_cl0 && !(k.flags & F_NO_REACTION));
-    const int o = y * k.pitch + x;
-#pragma unroll
-    for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
+  if constexpr (ONE) {
+    batch_cell(src, dst, k, t, threadIdx.x, tx);
+  } else {
+    const int n = tx * ty;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) batch_cell(src, dst, k, t, i, tx);
   }
 }
 
@@ -54,15 +65,20 @@ __device__ __forceinline__ int xcd_logical(int flat, int total) {
   return xcd * full + (xcd < rem ? xcd : rem) + slot;
 }
 
-template <typename R>
+template <typename R, bool ONE>
 __global__ __launch_bounds__(kBlock) void k_batch_step(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
                                                        const Tile* __restrict__ tiles, int ntiles, int parity,
                                                        int tx, int ty) {
   const int t = xcd_logical(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
-  batch_tile(pool, cases, tiles[t], parity, tx, ty);
+  batch_tile<R, ONE>(pool, cases, tiles[t], parity, tx, ty);
 }
 
+// The persistent form keeps the cell loop for every tile shape: its grid is
+// sized from the occupancy query, and the one-cell instance sits at the
+// 64-VGPR boundary where the compiler reports 7 waves per SIMD; a grid
+// sized for 8 would leave workgroups that never start and a grid barrier
+// that never completes.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_batch_persistent(R* __restrict__ pool,
                                                              const BatchCase<R>* __restrict__ cases,
@@ -75,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(R* __restrict__ poo
   const int t1 = int((int64_t(lb + 1) * ntiles) / gridDim.x);
   for (int s = 0; s < nsteps; ++s) {
     const int parity = (parity0 + s) & 1;
-    for (int t = t0; t < t1; ++t) batch_tile(pool, cases, tiles[t], parity, tx, ty);
+    for (int t = t0; t < t1; ++t) batch_tile<R, false>(pool, cases, tiles[t], parity, tx, ty);
     grid.sync();
   }
 }

@@ -146,6 +146,11 @@ lbm_status build_tiles(lbm_batch* b, int tx, int ty) {
   return LBM_OK;
 }
 
+// Workgroups of the persistent kernel's grid: every one must be resident at
+// once for its grid barrier.  One workgroup per CU below the occupancy
+// query's figure, so that a query that misses a limit (the compiler's
+// SGPR-bound occupancy can sit one below the VGPR-bound one) still leaves
+// the whole grid resident; the kernel's loop spreads the tiles over it.
 template <typename R>
 int cooperative_grid(lbm_batch* b) {
   int dev = 0, ncu = 0, per_cu = 0;
@@ -154,7 +159,7 @@ int cooperative_grid(lbm_batch* b) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_batch_persistent<R>),
                                                    kBlock, 0) != hipSuccess)
     return 0;
-  const int co = ncu * per_cu;
+  const int co = ncu * std::max(1, per_cu - 1);
   return std::min(co, b->ntiles);
 }
 
@@ -178,9 +183,14 @@ lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
       left -= chunk;
     }
   } else {
+    const bool one = tx * ty == kBlock;
     for (int64_t s = 0; s < nsteps; ++s) {
-      hipLaunchKernelGGL(k_batch_step<R>, dim3(b->ntiles), dim3(kBlock), 0, b->stream, pool, cases, tiles, b->ntiles,
-                         b->parity, tx, ty);
+      if (one)
+        hipLaunchKernelGGL((k_batch_step<R, true>), dim3(b->ntiles), dim3(kBlock), 0, b->stream, pool, cases, tiles,
+                           b->ntiles, b->parity, tx, ty);
+      else
+        hipLaunchKernelGGL((k_batch_step<R, false>), dim3(b->ntiles), dim3(kBlock), 0, b->stream, pool, cases, tiles,
+                           b->ntiles, b->parity, tx, ty);
       b->parity ^= 1;
     }
     const hipError_t e = hipGetLastError();
