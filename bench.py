@@ -309,7 +309,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint")
     ap.add_argument("--steps3d", type=int, default=5000, help="0 skips the 3D cathode")
     ap.add_argument("--adjoint3d-steps", type=int, default=5000, help="0 skips the 3D adjoint")
-    ap.add_argument("--polarisation-steps", type=int, default=100000, help="0 skips the polarisation sweep")
+    ap.add_argument("--polarisation-steps", type=int, default=300000, help="0 skips the polarisation sweep")
     ap.add_argument("--variant-steps", type=int, default=2000, help="0 skips the model-option variants")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write copy kernel 5 times (counter calibration)")
