@@ -32,7 +32,7 @@ __device__ __forceinline__ void batch_cell(const R* __restrict__ src, R* __restr
   const int x = t.x0 + i % tx;
   if (x >= k.nx || y >= k.ny) return;
   R f[19];
-  const Mat<R> mt = pre_collision<R, MAT_LAYERED>(src, k, nullptr, nullptr, nullptr, x, y, f);
+  const Mat<R> mt = pre_collision<R, MAT_LAYERED, false>(src, k, nullptr, nullptr, nullptr, x, y, f);
   collide(f, mt, k, y >= k.y_cl0 && !(k.flags & F_NO_REACTION));
   const int o = y * k.pitch + x;
 #pragma unroll

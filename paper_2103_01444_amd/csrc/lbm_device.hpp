@@ -122,11 +122,14 @@ __device__ __forceinline__ Mat<R> material(const Consts<R>& k, const R* __restri
 // Pull the 19 pre-collision populations of node (x, y) from the
 // post-collision state: f_q(x) = f*_q(x - e_q), or f*_opp(q)(x) where the
 // link crosses a wall (half-way bounce-back).  Every element of the state is
-// read exactly once per step, so the loads carry the non-temporal hint:
-// measured on MI355X the 4096x1024 FP32 step drops from 118.6 us to
-// 112.6 us with it (streamed lines stop displacing the x +- 1 neighbour
-// lines that adjacent wavefronts still need from L2).
-template <typename R>
+// read exactly once per step, so on a large lattice the loads carry the
+// non-temporal hint (NT): measured on MI355X the 4096x1024 FP32 step drops
+// from 118.6 us to 112.6 us with it (streamed lines stop displacing the
+// x +- 1 neighbour lines that adjacent wavefronts still need from L2), and
+// it is 9 % slower with plain loads in the final kernel (119.1 against
+// 109.3 us on one box).  The batched sweep of many narrow lattices is the
+// other way round: plain loads take it from 182.5 to 175.3 us per step.
+template <typename R, bool NT = true>
 __device__ __forceinline__ void pull(const R* __restrict__ src, const Consts<R>& k, int x, int y,
                                      R (&f)[19]) {
   const bool px = k.flags & F_PERIODIC_X;
@@ -139,7 +142,10 @@ __device__ __forceinline__ void pull(const R* __restrict__ src, const Consts<R>&
     if (py) ys = ys < 0 ? ys + k.ny : (ys >= k.ny ? ys - k.ny : ys);
     const bool in = (unsigned)xs < (unsigned)k.nx && (unsigned)ys < (unsigned)k.ny;
     const int off = in ? (q * k.plane + ys * k.pitch + xs) : (OPP[q] * k.plane + y * k.pitch + x);
-    f[q] = __builtin_nontemporal_load(src + off);
+    if constexpr (NT)
+      f[q] = __builtin_nontemporal_load(src + off);
+    else
+      f[q] = src[off];
   }
 }
 
@@ -280,7 +286,7 @@ struct React;
 template <typename R>
 __device__ __forceinline__ React<R> surface_reaction(R g_t, R g_c, const Mat<R>& m, const Consts<R>& k);
 
-template <typename R, int MAT>
+template <typename R, int MAT, bool NT = true>
 __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const Consts<R>& k,
                                                 const R* __restrict__ phi_f,
                                                 const R* __restrict__ invk_f,
@@ -290,7 +296,7 @@ __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const
   const bool inlet = open && x == 0 && y < k.ny_ch;
   const bool outlet = open && x == k.nx - 1;
   const int xp = inlet ? 1 : (outlet ? k.nx - 2 : x);
-  pull(src, k, xp, y, f);
+  pull<R, NT>(src, k, xp, y, f);
   Mat<R> mp = material<R, MAT>(k, phi_f, invk_f, d_f, xp, y);
   if ((k.flags & F_THIN_CL) && !(k.flags & F_NO_REACTION) && y == k.ny - 1) {
     // thin-film CL: planes 13 and 18 hold the bounced-back populations that
