@@ -77,6 +77,12 @@ typedef enum lbm_status {
                                 * take the pressure lbm_params.p_inlet with the velocity of column 1 (non-
                                 * equilibrium extrapolation), the outlet has lbm_params.p_outlet; Re is then an output
                                 * (lbm_obs.inlet_flux / nu) and lbm_params.Re is ignored */
+#define LBM_THIN_CL 64u /* 2D: the CL has negligible thickness (Section 1): a reactive wall half a cell
+                         * below the last GDL row (requires ny_cl = 0, ny_gdl >= 1, no LBM_PERIODIC_Y).  The
+                         * temperature and O2 populations that cross it are reflected minus the O2 the film
+                         * consumes and plus the heat it releases; the film carries the volumetric rate of
+                         * Eq. 13 over the thickness lbm_params.thin_cl_cm.  Observables: i(x) is the film's
+                         * current, the c and T profiles are those of the last row. */
 #define LBM_BUOYANCY 128u /* 2D: Boussinesq buoyancy (the thermal-to-flow coupling of the Section 3 cavity
                           * validations): phi * (T - T_in) * (buoyancy_x, buoyancy_y) is added to the flow
                           * force (Eq. 7) and half of it to Eq. 8's v, T from the node's own temperature
@@ -88,12 +94,6 @@ typedef enum lbm_status {
                               * is stored in the solid; the reaction heat is unchanged in kelvin per step */
 #define LBM_PHYSICAL_HEAT 512u /* 2D and 3D: the reaction heat with the irreversible part counted positive,
                                 * Q = -j (T dU0/dT - eta), instead of Eq. 15's printed -j (eta + T dU0/dT) */
-#define LBM_THIN_CL 64u /* 2D: the CL has negligible thickness (Section 1): a reactive wall half a cell
-                         * below the last GDL row (requires ny_cl = 0, ny_gdl >= 1, no LBM_PERIODIC_Y).  The
-                         * temperature and O2 populations that cross it are reflected minus the O2 the film
-                         * consumes and plus the heat it releases; the film carries the volumetric rate of
-                         * Eq. 13 over the thickness lbm_params.thin_cl_cm.  Observables: i(x) is the film's
-                         * current, the c and T profiles are those of the last row. */
 
 typedef struct lbm_geometry {
   int32_t nx, ny;                      /* nx >= 3, ny >= 1 */

@@ -113,11 +113,27 @@ def test_workspace_size_and_geometry_checks_3d(lib):
     for bad in (lbm.Geometry3D(2, 8, 8, 4, 3, 1, 32, 0),          # nx < 3
                 lbm.Geometry3D(16, 8, 8, 4, 3, 2, 32, 0),         # layers do not sum to nz
                 lbm.Geometry3D(16, 8, 8, 4, 3, 1, 16, 0),         # precision
-                lbm.Geometry3D(16, 8, 8, 4, 3, 1, 32, 32),        # unknown flag
+                lbm.Geometry3D(16, 8, 8, 4, 3, 1, 32, lbm.LBM_PRESSURE_INLET),  # 2D-only options
+                lbm.Geometry3D(16, 8, 8, 4, 3, 1, 32, lbm.LBM_THIN_CL),
+                lbm.Geometry3D(16, 8, 8, 4, 3, 1, 32, lbm.LBM_BUOYANCY),
+                lbm.Geometry3D(16, 8, 8, 4, 3, 1, 32, lbm.LBM_SIGMA_ENERGY),
+                lbm.Geometry3D(16, 8, 8, 4, 3, 1, 32, 1024),      # unknown flag
                 lbm.Geometry3D(16, 0, 8, 4, 3, 1, 32, 0),         # empty y
                 lbm.Geometry3D(1024, 1024, 64, 32, 29, 3, 32, 0)):  # 32-bit offsets
         assert lib.lbm3d_workspace_bytes(ctypes.byref(bad)) == 0
+    # the heat sign and the test-mode flags are 3D options too
+    for ok in (lbm.LBM_PHYSICAL_HEAT, lbm.LBM_PERIODIC_Z | lbm.LBM_BODY_FORCE | lbm.LBM_NO_REACTION):
+        assert lib.lbm3d_workspace_bytes(ctypes.byref(lbm.Geometry3D(16, 8, 8, 4, 3, 1, 32, ok))) > 0
     ctx = ctypes.c_void_p()
     assert lib.lbm3d_create(ctypes.byref(g), None, n, None, ctypes.byref(ctx)) == 1
     assert lib.lbm3d_create(ctypes.byref(g), ctypes.c_void_p(256), 16, None, ctypes.byref(ctx)) == 1
     assert lib.lbm3d_create(ctypes.byref(g), ctypes.c_void_p(300), n, None, ctypes.byref(ctx)) == 1  # misaligned
+
+
+def test_binding_constants_match_header_defines():
+    from paper_2103_01444_amd import lbm
+    txt = open(os.path.join(ROOT, "include", "lbm_pem.h")).read()
+    defines = {name: int(val) for name, val in re.findall(r"#define\s+(LBM_[A-Z0-9_]+)\s+(\d+)u?\b", txt)}
+    assert len(defines) >= 12
+    for name, val in defines.items():
+        assert getattr(lbm, name) == val, name
