@@ -112,6 +112,9 @@ __global__ __launch_bounds__(64) void k3_adj_bnd(const R* __restrict__ S, const 
                                                  R* __restrict__ grad, R* __restrict__ side,
                                                  const R* __restrict__ phi_f, const R* __restrict__ invk_f,
                                                  const R* __restrict__ d_f, Consts3<R> k, R w) {
+  // This pass runs beside the interior pass on the same CUs and is the
+  // longer of the two: its waves take instruction-issue priority.
+  __builtin_amdgcn_s_setprio(3);
   const int nrows = k.ny * k.nz;
   const int t = blockIdx.x * 64 + threadIdx.x;
   if (t >= 2 * nrows) return;
