@@ -146,3 +146,48 @@ def test_adjoint_nx3_3d():
         err = _max_rel(g[name], ref)
         print(f"3d nx=3 adjoint d/d{name}: rel {err:.1e}", flush=True)
         assert err < 1e-9, name
+
+
+# The model options at their smallest geometries: thin film under a single
+# GDL row at nx = 3 (the outlet copies the film column that also feeds the
+# inlet), the pressure inlet at nx = 3, buoyancy and the sigma energy
+# equation over a single porous row, every option together.
+OPTION_CASES = [
+    ("thin_nx3", (3, 4, (3, 1, 0)), dict(thin_cl=True)),
+    ("thin_bv_sigma", (9, 3, (1, 2, 0)), dict(thin_cl=True, butler_volmer=True, alpha_a=0.5, V_op=1.1,
+                                              aj0_ref=1e5, sigma_energy=True, heat_physical=True)),
+    ("pressure_nx3", (3, 6, (3, 2, 1)), dict(pressure_inlet=True, p_in=1e-3, p_out=2e-4)),
+    ("buoyancy_one_gdl_row", (12, 3, (1, 1, 1)), dict(buoyancy=(2e-4, -3e-4), sigma_energy=True)),
+    ("all_options", (16, 7, (3, 4, 0)), dict(thin_cl=True, pressure_inlet=True, p_in=2e-3, p_out=5e-4,
+                                             buoyancy=(0.0, 1e-4), sigma_energy=True, heat_physical=True,
+                                             butler_volmer=True)),
+]
+
+
+@pytest.mark.parametrize("name,case,opts", OPTION_CASES, ids=[c[0] for c in OPTION_CASES])
+def test_degenerate_2d_options(name, case, opts):
+    lbm = _lbm()
+    nx, ny, layers = case
+    w = dict(_w2(nx, ny, layers), **opts)
+    gpu = lbm.Cathode.from_workload(w, dx_cm=1e-3)
+    p = L.Params.from_workload(w)
+    p.dx_cm = 1e-3
+    m = L.Model(L.Geometry(nx, ny, *layers), p)
+    s = m.run(m.initial_state(), 25)
+    gpu.step(25)
+    fg, fo = gpu.fields(), m.fields(s)
+    _compare(fg, fo, ("ux", "uy"), ("p", "theta", "c"), f"2d {name}")
+    og, oo = gpu.observables(), m.observables(s)
+    for key in ("current_density", "heat_rate", "T_max", "sum_c", "sum_theta", "consumed_c", "inlet_flux"):
+        ref = float(oo[key])
+        assert abs(og[key] - ref) <= 1e-12 * max(abs(ref), 1e-30) + 1e-300, (key, og[key], ref)
+    for key in ("i_profile", "c_profile", "T_profile"):
+        assert _max_rel(og[key], oo[key]) < 1e-12 or float(oo[key].abs().max()) == 0.0, key
+    pops = torch.from_numpy(W.random_populations(ny, nx, 31 + nx))
+    gpu.set_populations(pops)
+    gpu.step(1)
+    ref = m.step(pops)
+    err = float((gpu.populations().cpu() - ref).abs().max())
+    print(f"2d {name} one step: {err:.1e} (largest population {float(ref.abs().max()):.1e})", flush=True)
+    # with the heat-capacity ratio the temperature populations carry sigma theta
+    assert err < 1e-13 * max(1.0, float(ref.abs().max()))
