@@ -42,7 +42,7 @@ bool geometry3_ok(const lbm3d_geometry* g) {
                    LBM_PHYSICAL_HEAT))
     return false;
   const int64_t pitch = (int64_t(g->nx) + 63) / 64 * 64;
-  if (pitch * g->ny * g->nz * 33 >= (int64_t(1) << 31)) return false;  // 32-bit element offsets
+  if (lbm::plane_elems(pitch * g->ny * g->nz) * 33 >= (int64_t(1) << 31)) return false;  // 32-bit element offsets
   return true;
 }
 
@@ -50,7 +50,7 @@ Layout3 make_layout3(const lbm3d_geometry* g) {
   Layout3 L;
   L.esize = g->precision == 64 ? 8 : 4;
   L.pitch = (g->nx + 63) / 64 * 64;
-  L.plane = int64_t(L.pitch) * g->ny * g->nz;
+  L.plane = lbm::plane_elems(int64_t(L.pitch) * g->ny * g->nz);
   L.state = align3(size_t(33) * L.plane * L.esize);
   L.nbx = (g->nx + kBlock3 - 1) / kBlock3;
   L.nblocks_obs = L.nbx * g->ny * g->nz;
@@ -139,7 +139,7 @@ void fill_consts3(Consts3<R>& k, const lbm3d_geometry& g, const lbm_params& p, c
   k.nz_ch = g.nz_channel;
   k.z_cl0 = g.nz_channel + g.nz_gdl;
   k.flags = g.flags;
-  k.plane = int32_t(int64_t(pitch) * g.ny * g.nz);
+  k.plane = int32_t(lbm::plane_elems(int64_t(pitch) * g.ny * g.nz));
   k.ty = std::min(kChunkY, g.ny);
   k.bv = k2.bv;
   k.s_plus = k2.s_e;

@@ -39,7 +39,7 @@ Layout make_layout(const lbm_geometry* g) {
   Layout L;
   L.esize = g->precision == 64 ? 8 : 4;
   L.pitch = (g->nx + 63) / 64 * 64;
-  L.plane = int64_t(L.pitch) * g->ny;
+  L.plane = lbm::plane_elems(int64_t(L.pitch) * g->ny);
   const size_t state = align_up(size_t(19) * L.plane * L.esize);
   L.nblocks_obs = ((g->nx + kBlock - 1) / kBlock) * g->ny;
   size_t o = 0;

@@ -45,7 +45,7 @@ BatchLayout make_batch_layout(const lbm_geometry* g, int n) {
   L.state_off[0].resize(n);
   L.state_off[1].resize(n);
   for (int i = 0; i < n; ++i) {
-    const int64_t plane = int64_t(pitch_of(g[i].nx)) * g[i].ny;
+    const int64_t plane = plane_elems(int64_t(pitch_of(g[i].nx)) * g[i].ny);
     for (int s = 0; s < 2; ++s) {
       L.state_off[s][i] = e;
       e += (19 * plane + 63) / 64 * 64;  // 256-byte aligned per buffer
@@ -274,7 +274,7 @@ lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double*
   std::vector<size_t> boff(b->n);
   size_t o = 0;
   for (int i = 0; i < b->n; ++i) {
-    const size_t sz = size_t(19) * pitch_of(b->g[i].nx) * b->g[i].ny * sizeof(R);
+    const size_t sz = size_t(19) * plane_elems(int64_t(pitch_of(b->g[i].nx)) * b->g[i].ny) * sizeof(R);
     boff[i] = o;
     if (hipMemcpyAsync(backup + o, pool + b->L.state_off[b->parity][i] * sizeof(R), sz, hipMemcpyDeviceToDevice,
                        b->stream) != hipSuccess)
@@ -320,7 +320,7 @@ lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double*
   (void)hipEventDestroy(e1);
   // Restore the saved state into the original buffers.
   for (int i = 0; i < b->n; ++i) {
-    const size_t sz = size_t(19) * pitch_of(b->g[i].nx) * b->g[i].ny * sizeof(R);
+    const size_t sz = size_t(19) * plane_elems(int64_t(pitch_of(b->g[i].nx)) * b->g[i].ny) * sizeof(R);
     if (hipMemcpyAsync(pool + b->L.state_off[parity0][i] * sizeof(R), backup + boff[i], sz, hipMemcpyDeviceToDevice,
                        b->stream) != hipSuccess)
       return bfail(b, LBM_ERR_DEVICE, "autotune restore failed");
