@@ -27,9 +27,10 @@ BYTES_PER_LU_PHI = 4            # per-cell porosity read
 # sources of the kernel each one measured.
 COUNTERS = {
     "step2d": (os.path.join(ROOT, "profiles", "step2d_4096x1024_fp32_counters.json"),
-               ("lbm_device.hpp", "lbm_kernels2d.hpp")),
+               ("lbm_device.hpp", "lbm_kernels2d.hpp", "lbm_host.hpp", "lbm_api.hip")),
     "step3d": (os.path.join(ROOT, "profiles", "step3d_256x128x64_fp32_counters.json"),
-               ("lbm_device.hpp", "lbm_kernels2d.hpp", "lbm3d_device.hpp", "lbm3d_kernels.hpp")),
+               ("lbm_device.hpp", "lbm_kernels2d.hpp", "lbm_host.hpp", "lbm3d_device.hpp", "lbm3d_kernels.hpp",
+                "lbm3d_api.hip")),
 }
 
 
