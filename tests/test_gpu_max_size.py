@@ -1,0 +1,56 @@
+"""The largest 2D lattice the C ABI accepts (19 population planes must stay
+within 32-bit element offsets): 8192 x 13790 in FP64, periodic in x with a
+body force along x, so that every column carries the same solution.  The
+GPU run is compared column by column with the FP64 oracle on a 3-column
+periodic lattice of the same rows; the offsets of the last rows of the
+last planes sit just below 2^31."""
+import pytest
+import torch
+
+import workloads as W
+from oracle import lbm2d as L
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+
+
+def test_largest_accepted_lattice_matches_the_oracle():
+    from paper_2103_01444_amd import lbm
+    nx, ny = 8192, 13790
+    layers = (6000, 7000, 790)
+    g_too_big = lbm.Geometry(nx, ny + 8, layers[0], layers[1], layers[2] + 8, 64, 0)
+    lib = lbm.load_library()
+    import ctypes
+    assert lib.lbm_workspace_bytes(ctypes.byref(g_too_big)) == 0  # one more row group crosses 2^31
+    w = dict(W.cathode2d_200x40(), nx=nx, ny=ny, ny_channel=layers[0], ny_gdl=layers[1], ny_cl=layers[2],
+             precision=64, Re=0.0, V_op=0.45)
+    flags = lbm.LBM_PERIODIC_X | lbm.LBM_BODY_FORCE
+    bf = 1e-6
+    gpu = lbm.Cathode.from_workload(w, flags=flags, body_force_x=bf, dx_cm=1e-3)
+    steps = 60
+    gpu.step(steps)
+    f = gpu.fields()
+    cols = [0, 1, nx // 2, nx - 2, nx - 1]
+    fg = {k: f[k][:, cols].double().cpu() for k in ("ux", "uy", "theta", "c")}
+    del f
+    o_gpu = gpu.observables()
+    del gpu
+    torch.cuda.empty_cache()
+    p = L.Params.from_workload(w)
+    p.body_force = (bf, 0.0)
+    p.dx_cm = 1e-3
+    m = L.Model(L.Geometry(3, ny, *layers, periodic_x=True), p)
+    s = m.run(m.initial_state(), steps)
+    fo = m.fields(s)
+    # u is a difference of O(1) populations: its round-off is ~1e-16 absolute
+    for key, tol in (("ux", 1e-10), ("theta", 1e-11), ("c", 1e-11)):
+        ref = fo[key][:, :1].expand(ny, len(cols))
+        scale = float(ref.abs().max())
+        err = float((fg[key] - ref).abs().max()) / scale
+        print(f"max lattice {key}: rel err {err:.1e} (scale {scale:.2e})", flush=True)
+        assert err < tol, key
+    uy_ref = fo["uy"][:, :1].expand(ny, len(cols))  # small but not zero at the layer interfaces
+    assert float((fg["uy"] - uy_ref).abs().max()) < 1e-10 * float(fo["ux"].abs().max())
+    oo = m.observables(s)
+    for key in ("current_density", "heat_rate", "T_max"):
+        assert abs(o_gpu[key] / float(oo[key]) - 1) < 1e-11, key
