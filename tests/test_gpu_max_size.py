@@ -54,3 +54,43 @@ def test_largest_accepted_lattice_matches_the_oracle():
     oo = m.observables(s)
     for key in ("current_density", "heat_rate", "T_max"):
         assert abs(o_gpu[key] / float(oo[key]) - 1) < 1e-11, key
+
+
+def test_largest_accepted_3d_lattice_matches_the_oracle():
+    """512 x 256 x 496 FP64 (33 planes just below 2^31 elements), periodic
+    in x and y with a body force along x: every (x, y) column carries the
+    same z profile, compared with the FP64 3D oracle on a 3 x 3 column."""
+    import ctypes
+
+    from oracle import lbm3d as L3
+    from paper_2103_01444_amd import lbm
+    nx, ny, nz = 512, 256, 496
+    layers = (200, 250, 46)
+    lib = lbm.load_library()
+    too_big = lbm.Geometry3D(nx, ny, nz + 2, layers[0], layers[1], layers[2] + 2, 64, 0)
+    assert lib.lbm3d_workspace_bytes(ctypes.byref(too_big)) == 0
+    w = W.cathode3d_scaled(nx, ny, nz, precision=64, nz_channel=layers[0], nz_gdl=layers[1], nz_cl=layers[2],
+                           Re=0.0, V_op=0.45, dp_lat=0.0, Da_gdl=1e-3)
+    flags = lbm.LBM_PERIODIC_X | lbm.LBM_PERIODIC_Y | lbm.LBM_BODY_FORCE
+    bf = 1e-6
+    gpu = lbm.Cathode3D.from_workload(w, flags=flags, body_force_x=bf, dx_cm=1e-3)
+    steps = 40
+    gpu.step(steps)
+    f = gpu.fields()
+    pts = [(0, 0), (ny - 1, nx - 1), (ny // 2, 7), (ny - 2, nx - 2)]
+    fg = {k: torch.stack([f[k][:, y, x] for y, x in pts], 1).double().cpu() for k in ("ux", "uz", "theta", "c")}
+    del f, gpu
+    torch.cuda.empty_cache()
+    p = L3.params_from_workload(w)
+    p.body_force = (bf, 0.0)
+    p.dx_cm = 1e-3
+    m = L3.Model3D(L3.Geometry3D(3, 3, nz, *layers, periodic_x=True, periodic_y=True), p)
+    fo = m.fields(m.run(m.initial_state(), steps))
+    for key, tol in (("ux", 1e-10), ("theta", 1e-11), ("c", 1e-11)):
+        ref = fo[key][:, :1, 0].expand(nz, len(pts))
+        scale = float(ref.abs().max())
+        err = float((fg[key] - ref).abs().max()) / scale
+        print(f"max 3D lattice {key}: rel err {err:.1e} (scale {scale:.2e})", flush=True)
+        assert err < tol, key
+    uz_ref = fo["uz"][:, :1, 0].expand(nz, len(pts))
+    assert float((fg["uz"] - uz_ref).abs().max()) < 1e-10 * float(fo["ux"].abs().max())
