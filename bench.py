@@ -4,7 +4,10 @@ Workload: the 4096x1024 FP32 cathode (per-cell porosity U[0.4, 0.8],
 Kozeny-Carman permeability, Re 50, 0.5 V, 343 K).  A step is one time step
 of the whole coupled update (stream, boundary columns, macros, MRT flow
 collision with porous drag, CL reaction, two scalar collisions) over the
-whole lattice.  Prints one JSON line.
+whole lattice.  Prints one JSON line; besides the headline it carries the
+model-option variants on the same lattice, the 64-case batched sweep, the
+2D adjoint, the 39-case polarisation sweep, the 3D cathode and its adjoint,
+and the FP64 oracle timed on the host (each can be skipped, see --help).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
