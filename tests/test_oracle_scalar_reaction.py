@@ -214,3 +214,52 @@ def test_effective_thermal_diffusivity_limits():
     a_mix = float(m.alpha[1, 0])
     assert min(a_gas, a_sol) < a_mix < max(a_gas, a_sol)
     assert abs(float(m.rhocp[1, 0]) - (0.6 * pr.rhocp_f + 0.4 * pr.rhocp_s)) < 1e-15
+
+
+def _diffusion_reaction_rates(nx, aj0, eps=1e-3):
+    """One CL row, periodic, isothermal (V = U0 intercept: no reaction heat
+    by Eqs. 15-16), O2 = 1 + eps sin(kx).  The first-order sink is linear
+    and uniform, so c = e^{-kappa t} (1 + eps e^{-D k^2 t} sin kx): the mean
+    decays at kappa, the ratio of the sine amplitude to the mean at D k^2.
+    Returns kappa and (measured / closed-form - 1) for both rates."""
+    m = L.Model(L.Geometry(nx, 1, 0, 0, 1, periodic_x=True, periodic_y=True),
+                L.Params(V_op=0.2329, aj0_ref=aj0, dx_cm=1e-3, phi_gdl=0.5))
+    pr = m.p
+    T = pr.T_in
+    eta = pr.V_op - (pr.U0_slope * T + pr.U0_icept)
+    aj0_T = pr.aj0_ref * math.exp(-pr.E_over_R * (1 / T - 1 / pr.T_arrh))
+    kappa = aj0_T * math.exp(-pr.alpha_c * pr.faraday * eta / (pr.R_gas * T)) * m.dt / (4 * pr.faraday * pr.C_ref)
+    D = 0.5 ** 1.5 * pr.D_f_lat  # Eq. 18
+    k = 2 * math.pi / nx
+    x = torch.arange(nx, dtype=DT).view(1, nx)
+    z = torch.zeros(1, nx, dtype=DT)
+    s = m.equilibrium_state(z, z, z, z, 1.0 + eps * torch.sin(k * x))
+
+    def modes(st):
+        c = m.fields(st)["c"][0]
+        return float(c.mean()), float((c * torch.sin(k * x[0])).sum() * 2 / nx)
+
+    s = m.run(s, 50)  # start-up layer of the equilibrium initial state
+    m0, a0 = modes(s)
+    n = int(0.5 / (D * k * k))
+    s = m.run(s, n)
+    m1, a1 = modes(s)
+    assert float(m.fields(s)["theta"].abs().max()) < 1e-14
+    return kappa, (math.log(m0 / m1) / n) / kappa - 1, (math.log((a0 / m0) / (a1 / m1)) / n) / (D * k * k) - 1
+
+
+def test_diffusion_reaction_closed_form():
+    """The sink is exact in time (mean decay at kappa to round-off); without
+    it the lattice diffusion rate converges to D k^2 at fourth order; the
+    sink, injected with the rest weights, shifts the diffusion rate by a
+    relative error of order kappa (a first-order splitting error: halving
+    kappa halves it)."""
+    _, _, d16 = _diffusion_reaction_rates(16, 1e-20)
+    _, _, d32 = _diffusion_reaction_rates(32, 1e-20)
+    assert 12 < d16 / d32 < 20 and abs(d32) < 1e-5
+    ka, ra, da = _diffusion_reaction_rates(32, 1e-9)
+    kb, rb, db = _diffusion_reaction_rates(32, 0.5e-9)
+    print(f"kappa {ka:.2e}: sink err {ra:.1e}, diffusion err {da:.2e}; kappa {kb:.2e}: {rb:.1e}, {db:.2e}")
+    assert abs(ra) < 1e-10 and abs(rb) < 1e-10 and ka > 1e-4
+    assert 1.8 < (da - d32) / (db - d32) < 2.2
+    assert abs(da - d32) < ka
