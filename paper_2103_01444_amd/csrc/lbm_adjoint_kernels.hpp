@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
   const int xp = inlet ? 1 : (outlet ? k.nx - 2 : x);
 
   R p[19];
-  pull(S, k, xp, y, p);
+  pull<R, true, true>(S, k, xp, y, p);
   const Mat<R> mxp = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xp, y);
   MatAdj<R> ma{};
   R mu[19];

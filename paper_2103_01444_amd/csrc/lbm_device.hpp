@@ -129,9 +129,49 @@ __device__ __forceinline__ Mat<R> material(const Consts<R>& k, const R* __restri
 // it is 9 % slower with plain loads in the final kernel (119.1 against
 // 109.3 us on one box).  The batched sweep of many narrow lattices is the
 // other way round: plain loads take it from 182.5 to 175.3 us per step.
-template <typename R, bool NT = true>
+//
+// Wave-uniform addressing: a base address that is the same for every lane
+// of the wavefront is held as a raw buffer resource in scalar registers and
+// every lane adds one 32-bit byte offset, so a run of loads at one node (or
+// at one neighbour shift) needs no per-lane address arithmetic.  The
+// state holds fewer than 2^31 elements, so a node's byte offset inside a
+// plane fits 32 bits.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base) {
+  // stride 0 (raw), the largest record count, the gfx9 dword-3 format word
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), short(0), -1, 0x00020000);
+}
+
+// aux: the instruction's cache-policy bits; 2 is the non-temporal hint.
+template <typename R, int AUX>
+__device__ __forceinline__ R buffer_load(const R* base, uint32_t byte_off) {
+  if constexpr (sizeof(R) == 4) {
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(buffer_of(base), int(byte_off), 0, AUX));
+  } else {
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(buffer_of(base), int(byte_off), 0, AUX));
+  }
+}
+
+//
+// UNIFORM: a wavefront whose nodes all lie one node or more inside the
+// lattice (no wall link, no periodic wrap) folds each population's plane and
+// neighbour shift into a wave-uniform base.  The reverse step, whose
+// register-bound collision adjoint leaves little issue slack, gains from it
+// (per reverse step of the 1024x256 adjoint 34.3 against 35.0 us, on another
+// box 33.4 against 34.9 us); the forward kernels run 0.5-1.5 % slower with
+// it (A/B on one box) and keep the per-lane form, and in the reverse step
+// the same form for the adjoint loads, the gradient update and the push
+// costs more in spilled registers than it saves (38.3 us).
+template <typename R, bool NT = true, bool UNIFORM = false>
 __device__ __forceinline__ void pull(const R* __restrict__ src, const Consts<R>& k, int x, int y,
                                      R (&f)[19]) {
+  if (UNIFORM && __all(x >= 1 && x <= k.nx - 2 && y >= 1 && y <= k.ny - 2)) {
+    const uint32_t ob = uint32_t(y * k.pitch + x) * uint32_t(sizeof(R));
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      f[q] = buffer_load<R, NT ? 2 : 0>(src + (int64_t(q) * k.plane - int64_t(EY[q]) * k.pitch - EX[q]), ob);
+    }
+    return;
+  }
   const bool px = k.flags & F_PERIODIC_X;
   const bool py = k.flags & F_PERIODIC_Y;
 #pragma unroll
