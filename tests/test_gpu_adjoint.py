@@ -75,6 +75,26 @@ def test_fp64_adjoint_with_outlet_pressure_matches_oracle_gradient():
     _compare(g, (gphi, gk, gd), w["ny_channel"], 1e-9, "14x10 fp64 p_out")
 
 
+def test_fp64_gradient_along_a_dense_direction_equals_forward_mode_derivative():
+    """<grad J, d> of the GPU's reverse sweep, over every porous cell at
+    once, against the oracle's forward-mode derivative of J along d (no
+    reverse pass on either side of the comparison)."""
+    from test_oracle_adjoint import _dense_direction, forward_mode_derivative
+    lbm = _lbm()
+    w = W.adjoint2d(14, 10)
+    w.update(ny_channel=5, ny_gdl=4, ny_cl=1, Re=2.0, V_op=0.45, precision=64)
+    phi = W.porosity_field(w)
+    sim = lbm.Cathode.from_workload(w, phi=phi, independent_fields=1)
+    sim.forward_checkpointed(40, 15)
+    g = sim.backward(1.0)
+    fields = _oracle_fields(w, phi)
+    dirs = _dense_direction(fields, w["ny_channel"])
+    dot = sum(float((g[name].double().cpu() * d).sum()) for name, d in zip(("phi", "inv_k", "d_eff"), dirs))
+    jvp = forward_mode_derivative(L.geometry_from_workload(w), L.Params.from_workload(w), fields, dirs, 40)
+    print(f"gpu <grad, d> {dot:.15e}, oracle forward mode {jvp:.15e}", flush=True)
+    assert abs(dot / jvp - 1) < 1e-10
+
+
 # Relative finite-difference steps: J is about 1e3 times less sensitive to
 # 1/K than to porosity, so a 1e-5 step for 1/K would leave the difference
 # quotient dominated by the ~1e-14 relative rounding of J.

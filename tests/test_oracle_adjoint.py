@@ -54,3 +54,46 @@ def test_checkpoint_segments_do_not_change_the_gradient():
     assert torch.equal(a[0], b[0])  # same forward arithmetic
     for u, v in zip(a[1:], b[1:]):  # gradient terms summed in another order
         assert float((u - v).abs().max()) <= 1e-12 * float(v.abs().max())
+
+
+def _dense_direction(fields, ny_channel, seed=7):
+    """A seeded random direction over every porous cell of the three
+    fields, scaled by each field's own magnitude."""
+    rng = np.random.default_rng(seed)
+    dirs = []
+    for f in fields:
+        porous = torch.zeros_like(f, dtype=torch.bool)
+        porous[ny_channel:] = True
+        d = torch.tensor(rng.standard_normal(tuple(f.shape)), dtype=DT)
+        dirs.append(torch.where(porous, d * f.abs(), torch.zeros_like(f)))
+    return dirs
+
+
+def forward_mode_derivative(g, p, fields, dirs, nsteps):
+    """d/de J(fields + e dirs) at e = 0 by forward-mode differentiation of
+    the oracle's forward map (no reverse pass involved)."""
+    import torch.autograd.forward_ad as fwAD
+    with fwAD.dual_level():
+        duals = [fwAD.make_dual(f.clone(), d) for f, d in zip(fields, dirs)]
+        J = A.mean_current_density(g, p, *duals, nsteps=nsteps)
+        return float(fwAD.unpack_dual(J).tangent)
+
+
+def test_gradient_along_a_dense_direction():
+    """The dot-product identity <grad J, d> = dJ(m + e d)/de over every
+    porous cell at once: against forward-mode differentiation (exact up to
+    rounding) and against a central difference along d (truncation
+    O(h^2))."""
+    g, p, fields = _case()
+    nsteps = 40
+    _, *grads = A.gradient(g, p, *fields, nsteps=nsteps, every=15)
+    dirs = _dense_direction(fields, g.ny_channel)
+    dot = sum(float((gr * d).sum()) for gr, d in zip(grads, dirs))
+    jvp = forward_mode_derivative(g, p, fields, dirs, nsteps)
+    h = 1e-6
+    vals = [float(A.mean_current_density(g, p, *[f + s * h * d for f, d in zip(fields, dirs)], nsteps=nsteps))
+            for s in (1, -1)]
+    fd = (vals[0] - vals[1]) / (2 * h)
+    print(f"<grad, d> {dot:.15e}, forward mode {jvp:.15e}, central difference {fd:.15e}")
+    assert abs(dot / jvp - 1) < 1e-12
+    assert abs(dot / fd - 1) < 1e-6

@@ -45,3 +45,42 @@ def test_gradient_matches_central_differences_3d():
             ad = float(grads[f_idx][z, y, x])
             scale = float(grads[f_idx].abs().max())
             assert abs(ad - fd) <= 1e-6 * scale + 1e-9 * abs(fd), (f_idx, z, y, x, ad, fd, scale)
+
+
+def dense_direction3d(fields, nz_channel, seed=8):
+    """A seeded random direction over the porous layers of the three
+    fields, scaled by each field's own magnitude."""
+    rng = np.random.default_rng(seed)
+    dirs = []
+    for f in fields:
+        d = torch.tensor(rng.standard_normal(tuple(f.shape)), dtype=DT) * f.abs()
+        d[:nz_channel] = 0.0
+        dirs.append(d)
+    return dirs
+
+
+def forward_mode_derivative3d(g, p, fields, dirs, nsteps):
+    """d/de J(fields + e dirs) at e = 0 by forward-mode differentiation."""
+    import torch.autograd.forward_ad as fwAD
+    with fwAD.dual_level():
+        duals = [fwAD.make_dual(f.clone(), d) for f, d in zip(fields, dirs)]
+        J = A3.mean_current_density(g, p, *duals, nsteps=nsteps)
+        return float(fwAD.unpack_dual(J).tangent)
+
+
+def test_gradient_along_a_dense_direction_3d():
+    """<grad J, d> over every porous cell against forward-mode
+    differentiation and a central difference along d."""
+    g, p, fields = _case()
+    nsteps = 24
+    _, *grads = A3.gradient(g, p, *fields, nsteps=nsteps, every=10)
+    dirs = dense_direction3d(fields, g.nz_channel)
+    dot = sum(float((gr * d).sum()) for gr, d in zip(grads, dirs))
+    jvp = forward_mode_derivative3d(g, p, fields, dirs, nsteps)
+    h = 1e-5
+    vals = [float(A3.mean_current_density(g, p, *[f + s * h * d for f, d in zip(fields, dirs)], nsteps=nsteps))
+            for s in (1, -1)]
+    fd = (vals[0] - vals[1]) / (2 * h)
+    print(f"3d <grad, d> {dot:.15e}, forward mode {jvp:.15e}, central difference {fd:.15e}")
+    assert abs(dot / jvp - 1) < 1e-12
+    assert abs(dot / fd - 1) < 1e-6
