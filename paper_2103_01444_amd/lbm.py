@@ -507,6 +507,8 @@ class BatchedSweep:
         self.lib = load_library()
         self.device = torch.device(device or "cuda")
         n = len(cases)
+        if n == 0:
+            raise LbmError("a batch needs at least one case")
         prec = cases[0].get("precision", 32)
         self.dtype = torch.float64 if prec == 64 else torch.float32
         self.shapes = [(w["nx"], w["ny"]) for w in cases]

@@ -102,6 +102,11 @@ def test_workspace_size_and_geometry_checks(lib):
     assert lib.lbm_create(ctypes.byref(g), None, 1 << 30, None, ctypes.byref(ctx)) == 1
     assert lib.lbm_create(ctypes.byref(g), ctypes.c_void_p(256), 16, None, ctypes.byref(ctx)) == 1
     assert lib.lbm_status_string(2) == b"parameters outside the stable range"
+    # an empty batch (or a negative case count) has no workspace
+    gs = (lbm.Geometry * 2)(g32, g32)
+    assert lib.lbm_batch_workspace_bytes(gs, 2) > 0
+    assert lib.lbm_batch_workspace_bytes(gs, 0) == 0
+    assert lib.lbm_batch_workspace_bytes(gs, -1) == 0
 
 
 def test_workspace_size_and_geometry_checks_3d(lib):

@@ -1,8 +1,8 @@
 """Degenerate geometries against the FP64 oracles: the smallest lattice
 (nx = 3, where one column feeds both the inlet and the outlet node), no
 channel (no inlet), a channel with no porous layers, no CL, and a single
-row / layer.  Runs from equilibrium, one step of an arbitrary state, and the
-adjoint at nx = 3."""
+row / layer.  Runs from equilibrium, one step of an arbitrary state, the
+adjoint at nx = 3, and empty and invalid step counts."""
 import numpy as np
 import pytest
 import torch
@@ -191,3 +191,45 @@ def test_degenerate_2d_options(name, case, opts):
     print(f"2d {name} one step: {err:.1e} (largest population {float(ref.abs().max()):.1e})", flush=True)
     # with the heat-capacity ratio the temperature populations carry sigma theta
     assert err < 1e-13 * max(1.0, float(ref.abs().max()))
+
+
+def test_zero_and_negative_step_counts():
+    """Zero steps leave every state bit-identical and count nothing; a
+    negative count, an empty checkpointed run or a zero checkpoint interval
+    is refused with an error (nothing is launched)."""
+    lbm = _lbm()
+    w = _w2(20, 6, (3, 2, 1))
+    sim = lbm.Cathode.from_workload(w)
+    sim.step(3)
+    before = sim.populations().clone()
+    sim.step(0)
+    assert torch.equal(sim.populations(), before) and sim.step_count == 3
+    with pytest.raises(lbm.LbmError):
+        sim.step(-1)
+    assert torch.equal(sim.populations(), before) and sim.step_count == 3
+    wa = W.adjoint2d(14, 10)
+    wa.update(ny_channel=5, ny_gdl=4, ny_cl=1, Re=2.0, precision=64)
+    adj = lbm.Cathode.from_workload(wa, phi=W.porosity_field(wa), independent_fields=1)
+    for n, every in ((0, 5), (10, 0), (-4, 2)):
+        with pytest.raises(lbm.LbmError):
+            adj.forward_checkpointed(n, every)
+
+    w3 = W.cathode3d_scaled(10, 4, 5, precision=64, nz_channel=2, nz_gdl=2, nz_cl=1, Re=0.4)
+    s3 = lbm.Cathode3D.from_workload(w3)
+    s3.step(2)
+    b3 = s3.populations().clone()
+    s3.step(0)
+    assert torch.equal(s3.populations(), b3) and s3.step_count == 2
+    with pytest.raises(lbm.LbmError):
+        s3.step(-2)
+
+    cases = [dict(c) for c in W.batched_cases(2)]
+    b = lbm.BatchedSweep(cases)
+    b.step(2)
+    pops = [b.populations(i).clone() for i in range(2)]
+    b.step(0)
+    assert all(torch.equal(b.populations(i), pops[i]) for i in range(2))
+    with pytest.raises(lbm.LbmError):
+        b.step(-1)
+    with pytest.raises(lbm.LbmError):
+        lbm.BatchedSweep([])
