@@ -75,6 +75,30 @@ def test_fp64_adjoint_with_outlet_pressure_matches_oracle_gradient():
     _compare(g, (gphi, gk, gd), w["ny_channel"], 1e-9, "14x10 fp64 p_out")
 
 
+@pytest.mark.parametrize("nx", [14, 130])
+def test_fp64_periodic_adjoint_matches_oracle_gradient(nx):
+    """Periodic in x with a body force along x (no boundary columns: the
+    reverse sweep runs the interior kernel alone), at a width inside one
+    workgroup and one spanning a ragged second workgroup."""
+    lbm = _lbm()
+    w = W.adjoint2d(nx, 10)
+    w.update(ny_channel=5, ny_gdl=4, ny_cl=1, Re=0.0, V_op=0.45, precision=64)
+    phi = W.porosity_field(w)
+    bf = 2e-5
+    sim = lbm.Cathode.from_workload(w, phi=phi, independent_fields=1, flags=lbm.LBM_PERIODIC_X | lbm.LBM_BODY_FORCE,
+                                    body_force_x=bf)
+    J = sim.forward_checkpointed(40, 15)
+    g = sim.backward(1.0)
+    fields = _oracle_fields(w, phi)
+    p = L.Params.from_workload(w)
+    p.body_force = (bf, 0.0)
+    geo = L.Geometry(nx, 10, 5, 4, 1, periodic_x=True)
+    Jo, gphi, gk, gd = A.gradient(geo, p, *fields, nsteps=40, every=15)
+    print(f"periodic {nx}x10 J gpu {J:.15e} oracle {float(Jo):.15e}", flush=True)
+    assert abs(J / float(Jo) - 1) < 1e-12
+    _compare(g, (gphi, gk, gd), w["ny_channel"], 1e-9, f"periodic {nx}x10 fp64")
+
+
 def test_fp64_gradient_along_a_dense_direction_equals_forward_mode_derivative():
     """<grad J, d> of the GPU's reverse sweep, over every porous cell at
     once, against the oracle's forward-mode derivative of J along d (no
