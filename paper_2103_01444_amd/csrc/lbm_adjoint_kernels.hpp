@@ -48,11 +48,15 @@ __device__ __forceinline__ void node_mu(const R (&pre)[19], const Mat<R>& mt, co
 // One reverse step: lam_out = (dS'/dS)^T lam_in at the state S, gradients
 // accumulated into grad (planes phi, 1/K, D_eff).  SEED: lam_out = dJ/dS
 // (times w = dJ dx / nx * 4 F C_ref / dt), no lam_in.
-// Four waves per SIMD (128 VGPRs; the compiler spills 92 bytes per lane to
-// scratch): 35.0 instead of 36.0 us per reverse step of the 1024x256
-// adjoint against three waves without spills (162 VGPRs).
+// The first and last wavefront of a row carry the boundary nodes, whose
+// chain is the longest, so the boundary block is shared (see below) and the
+// kernel runs at three waves per SIMD without spills (168 VGPRs): 31.1-31.6
+// us per reverse step of the 1024x256 adjoint, against 34.4 us when the
+// boundary node and its feeding column took separate passes (four waves,
+// 92 bytes spilled per lane) and 40.3 us for the shared block at four waves
+// (144 bytes spilled).
 template <typename R, bool SEED>
-__global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
+__global__ __launch_bounds__(kBlock, 3) void k_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
                                                      R* __restrict__ lam_out, R* __restrict__ grad,
                                                      const R* __restrict__ phi_f, const R* __restrict__ invk_f,
                                                      const R* __restrict__ d_f, Consts<R> k, R w) {
@@ -74,72 +78,67 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
   MatAdj<R> ma{};
   R mu[19];
   const int o = y * k.pitch + x;
+  const bool bnode = inlet || outlet;
 
-  if (inlet || outlet) {
-    // Boundary node: own collision adjoint and the material part of its
-    // extrapolation; its pulled sources were never read, so their adjoint is 0.
-    Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y);
+  // Own collision adjoint of every node that is not an inlet / outlet node.
+  if (!bnode) {
+    node_mu<R, SEED>(p, mxp, k, cl, lam_in, x, y, w, mu, ma);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) mu[q] = R(0);
+  }
+  // A boundary node's collision adjoint and the transpose of its
+  // extrapolation from the column next to it.  The boundary node needs them
+  // for its own material, the feeding column for its populations and
+  // material; both pulled that column, so they run this block together (one
+  // pass of the wavefront instead of one per lane kind).
+  if (open && y < k.ny_ch && x <= 1) {  // inlet node (x = 0) and column 1
+    const Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, 0, y);
     R pre[19];
 #pragma unroll
     for (int q = 0; q < 19; ++q) pre[q] = p[q];
-    boundary_column(pre, k, y, inlet, mxp, mb);
-    if (outlet) outlet_scalar_material(mb, mxp);
-    node_mu<R, SEED>(pre, mb, k, cl, lam_in, x, y, w, mu, ma);
-    R dmu[19];
+    boundary_column(pre, k, y, true, mxp, mb);
+    R mub[19];
+    MatAdj<R> mab{};
+    node_mu<R, SEED>(pre, mb, k, cl, lam_in, 0, y, w, mub, mab);
+    boundary_adj(p, mxp, mb, k, true, inlet_velocity(k, y), R(0), mub, mu, ma, mab);
+    if (x == 0) ma = mab;  // the boundary node keeps the terms of its own material
+  }
+  if (open && x >= k.nx - 2) {  // outlet node (x = nx - 1) and column nx - 2
+    Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, k.nx - 1, y);
+    R pre[19];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) dmu[q] = R(0);
-    MatAdj<R> dmaxp{};
-    boundary_adj(p, mxp, mb, k, inlet, inlet ? inlet_velocity(k, y) : R(0), R(0), mu, dmu, dmaxp, ma);
-    if (outlet) {  // the outlet's scalar material is column nx-2's; that thread takes these terms
+    for (int q = 0; q < 19; ++q) pre[q] = p[q];
+    boundary_column(pre, k, y, false, mxp, mb);
+    outlet_scalar_material(mb, mxp);
+    R mub[19];
+    MatAdj<R> mab{};
+    node_mu<R, SEED>(pre, mb, k, cl, lam_in, k.nx - 1, y, w, mub, mab);
+    if (!outlet) {  // the outlet node collides with column nx - 2's scalar material
+      ma.bT += mab.bT;
+      ma.bC += mab.bC;
+      ma.rhocp += mab.rhocp;
+    }
+    boundary_adj(p, mxp, mb, k, false, R(0), R(0), mub, mu, ma, mab);
+    if (outlet) {  // its scalar material terms belong to column nx - 2
+      ma = mab;
       ma.bT = R(0);
       ma.bC = R(0);
       ma.rhocp = R(0);
     }
-    R g0 = R(0), g1 = R(0), g2 = R(0);
-    material_adj(k, mb, ma, g0, g1, g2);
-    grad[o] += g0;
-    grad[k.plane + o] += g1;
-    grad[2 * k.plane + o] += g2;
+  }
+  if (bnode) {  // its pulled sources were never read: their adjoint is 0
 #pragma unroll
     for (int q = 0; q < 19; ++q) mu[q] = R(0);
-  } else {
-    node_mu<R, SEED>(p, mxp, k, cl, lam_in, x, y, w, mu, ma);
-    // Columns feeding a boundary node add that node's adjoint through the
-    // extrapolation (recomputed here so that every node writes only its own data).
-    if (open && x == 1 && y < k.ny_ch) {
-      const Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, 0, y);
-      R pre[19];
-#pragma unroll
-      for (int q = 0; q < 19; ++q) pre[q] = p[q];
-      boundary_column(pre, k, y, true, mxp, mb);
-      R mub[19];
-      MatAdj<R> dmab{};
-      node_mu<R, SEED>(pre, mb, k, cl, lam_in, 0, y, w, mub, dmab);
-      MatAdj<R> dmab2{};
-      boundary_adj(p, mxp, mb, k, true, inlet_velocity(k, y), R(0), mub, mu, ma, dmab2);
-    }
-    if (open && x == k.nx - 2) {
-      Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, k.nx - 1, y);
-      R pre[19];
-#pragma unroll
-      for (int q = 0; q < 19; ++q) pre[q] = p[q];
-      boundary_column(pre, k, y, false, mxp, mb);
-      outlet_scalar_material(mb, mxp);
-      R mub[19];
-      MatAdj<R> dmab{};
-      node_mu<R, SEED>(pre, mb, k, cl, lam_in, k.nx - 1, y, w, mub, dmab);
-      ma.bT += dmab.bT;  // the outlet node collides with this column's scalar material
-      ma.bC += dmab.bC;
-      ma.rhocp += dmab.rhocp;
-      MatAdj<R> dmab2{};
-      boundary_adj(p, mxp, mb, k, false, R(0), R(0), mub, mu, ma, dmab2);
-    }
-    R g0 = R(0), g1 = R(0), g2 = R(0);
-    material_adj(k, mxp, ma, g0, g1, g2);
-    grad[o] += g0;
-    grad[k.plane + o] += g1;
-    grad[2 * k.plane + o] += g2;
   }
+  // The gradient of this node's own material (a boundary node's is read
+  // again; its scalar-material terms are zero, so the outlet's copy of
+  // column nx - 2's scalar material does not enter).
+  R g0 = R(0), g1 = R(0), g2 = R(0);
+  material_adj(k, bnode ? material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y) : mxp, ma, g0, g1, g2);
+  grad[o] += g0;
+  grad[k.plane + o] += g1;
+  grad[2 * k.plane + o] += g2;
   // Push: the adjoint of the pulled element (x - e_q, q) (or of the
   // bounced-back (x, opp q)) is mu[q].
   const bool px = k.flags & F_PERIODIC_X;
