@@ -148,15 +148,26 @@ MatPtrs<R> mat_ptrs(lbm_ctx* c) {
           static_cast<const R*>(c->mat_plane(2))};
 }
 
+// Lattices below this many nodes take the wave-uniform addressing form of
+// the step (their launches are bound by each wavefront's own chain).
+constexpr int64_t kUniformMaxCells = int64_t(1) << 20;
+
+template <typename R, int MAT>
+void launch_step_kernel(lbm_ctx* c, const R* src, R* dst, const MatPtrs<R>& m, const Consts<R>& k) {
+  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
+  if (int64_t(c->g.nx) * c->g.ny < kUniformMaxCells)
+    hipLaunchKernelGGL((k_step<R, MAT, true>), grid, dim3(kBlock), 0, c->stream, src, dst, m.phi, m.invk, m.d, k);
+  else
+    hipLaunchKernelGGL((k_step<R, MAT, false>), grid, dim3(kBlock), 0, c->stream, src, dst, m.phi, m.invk, m.d, k);
+}
+
 template <typename R, int MAT>
 void launch_step_mat(lbm_ctx* c, int64_t n) {
   const MatPtrs<R> m = mat_ptrs<R>(c);
   const Consts<R> k = consts<R>(c);
-  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
   for (int64_t i = 0; i < n; ++i) {
-    const R* src = static_cast<const R*>(c->state(c->cur));
-    R* dst = static_cast<R*>(c->state(c->cur ^ 1));
-    hipLaunchKernelGGL((k_step<R, MAT>), grid, dim3(kBlock), 0, c->stream, src, dst, m.phi, m.invk, m.d, k);
+    launch_step_kernel<R, MAT>(c, static_cast<const R*>(c->state(c->cur)), static_cast<R*>(c->state(c->cur ^ 1)), m,
+                               k);
     c->cur ^= 1;
   }
 }
@@ -570,10 +581,7 @@ AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int32_t every) {
 
 template <typename R>
 void launch_one_step(lbm_ctx* c, const void* src, void* dst) {
-  const MatPtrs<R> m = mat_ptrs<R>(c);
-  const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
-  hipLaunchKernelGGL((k_step<R, MAT_FULL>), grid, dim3(kBlock), 0, c->stream, static_cast<const R*>(src),
-                     static_cast<R*>(dst), m.phi, m.invk, m.d, consts<R>(c));
+  launch_step_kernel<R, MAT_FULL>(c, static_cast<const R*>(src), static_cast<R*>(dst), mat_ptrs<R>(c), consts<R>(c));
 }
 
 template <typename R>

@@ -151,6 +151,16 @@ __device__ __forceinline__ R buffer_load(const R* base, uint32_t byte_off) {
   }
 }
 
+template <typename R>
+__device__ __forceinline__ void buffer_store(R* base, uint32_t byte_off, R v) {
+  if constexpr (sizeof(R) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), buffer_of(base), int(byte_off), 0, 0);
+  } else {
+    using U2 = uint32_t __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), buffer_of(base), int(byte_off), 0, 0);
+  }
+}
+
 //
 // UNIFORM: a wavefront whose nodes all lie one node or more inside the
 // lattice (no wall link, no periodic wrap) folds each population's plane and
@@ -326,7 +336,7 @@ struct React;
 template <typename R>
 __device__ __forceinline__ React<R> surface_reaction(R g_t, R g_c, const Mat<R>& m, const Consts<R>& k);
 
-template <typename R, int MAT, bool NT = true>
+template <typename R, int MAT, bool NT = true, bool UNIFORM = false>
 __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const Consts<R>& k,
                                                 const R* __restrict__ phi_f,
                                                 const R* __restrict__ invk_f,
@@ -336,7 +346,7 @@ __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const
   const bool inlet = open && x == 0 && y < k.ny_ch;
   const bool outlet = open && x == k.nx - 1;
   const int xp = inlet ? 1 : (outlet ? k.nx - 2 : x);
-  pull<R, NT>(src, k, xp, y, f);
+  pull<R, NT, UNIFORM>(src, k, xp, y, f);
   Mat<R> mp = material<R, MAT>(k, phi_f, invk_f, d_f, xp, y);
   if ((k.flags & F_THIN_CL) && !(k.flags & F_NO_REACTION) && y == k.ny - 1) {
     // thin-film CL: planes 13 and 18 hold the bounced-back populations that

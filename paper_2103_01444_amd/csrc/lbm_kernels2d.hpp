@@ -25,8 +25,12 @@ __device__ __forceinline__ void xcd_tile(int nbx, int nby, int& bx, int& by) {
 }
 
 // One time step: pull-stream, boundary columns, macros, flow collision,
-// reaction, scalar collisions, store.
-template <typename R, int MAT>
+// reaction, scalar collisions, store.  UNIFORM: wave-uniform buffer
+// addressing for the interior pull and for the stores (fewer vector
+// instructions per node).  Small lattices, whose launches are one round of
+// wavefronts bound by each wave's own chain, gain from it; the 4096x1024
+// lattice runs 0.5 % slower with it and keeps the per-lane form.
+template <typename R, int MAT, bool UNIFORM = false>
 __global__ __launch_bounds__(kBlock) void k_step(const R* __restrict__ src, R* __restrict__ dst,
                                                  const R* __restrict__ phi_f,
                                                  const R* __restrict__ invk_f,
@@ -37,12 +41,18 @@ __global__ __launch_bounds__(kBlock) void k_step(const R* __restrict__ src, R* _
   const int y = by;
   if (x >= k.nx) return;
   R f[19];
-  const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);
+  const Mat<R> mt = pre_collision<R, MAT, true, UNIFORM>(src, k, phi_f, invk_f, d_f, x, y, f);
   const bool cl = y >= k.y_cl0 && !(k.flags & F_NO_REACTION);
   collide(f, mt, k, cl);
   const int o = y * k.pitch + x;
+  if constexpr (UNIFORM) {
+    const uint32_t ob = uint32_t(o) * uint32_t(sizeof(R));
 #pragma unroll
-  for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
+    for (int q = 0; q < 19; ++q) buffer_store(dst + int64_t(q) * k.plane, ob, f[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
+  }
 }
 
 // Equilibrium initial state: rest fluid at zero pressure (shifted f = 0),
