@@ -24,25 +24,33 @@ struct Tile {
   int32_t c, x0, y0, pad;
 };
 
-// Advance cell i (row-major inside the tile) of a tile.
-template <typename R>
+// Advance cell i (row-major inside the tile) of a tile.  UNIFORM: wave-
+// uniform buffer addressing for the interior pull and the stores (batches
+// of few nodes, whose launches are one round of wavefronts).
+template <typename R, bool UNIFORM = false>
 __device__ __forceinline__ void batch_cell(const R* __restrict__ src, R* __restrict__ dst, const Consts<R>& k,
                                            const Tile& t, int i, int tx) {
   const int y = t.y0 + i / tx;
   const int x = t.x0 + i % tx;
   if (x >= k.nx || y >= k.ny) return;
   R f[19];
-  const Mat<R> mt = pre_collision<R, MAT_LAYERED, false>(src, k, nullptr, nullptr, nullptr, x, y, f);
+  const Mat<R> mt = pre_collision<R, MAT_LAYERED, false, UNIFORM>(src, k, nullptr, nullptr, nullptr, x, y, f);
   collide(f, mt, k, y >= k.y_cl0 && !(k.flags & F_NO_REACTION));
   const int o = y * k.pitch + x;
+  if constexpr (UNIFORM) {
+    const uint32_t ob = uint32_t(o) * uint32_t(sizeof(R));
 #pragma unroll
-  for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
+    for (int q = 0; q < 19; ++q) buffer_store(dst + int64_t(q) * k.plane, ob, f[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
+  }
 }
 
 // Advance the cells of one tile (tx x ty cells).  ONE: the tile has exactly
 // one cell per thread (tx ty = kBlock); without the cell loop the kernel
 // needs 59 instead of 76 VGPRs (8 instead of 6 waves per SIMD in FP32).
-template <typename R, bool ONE>
+template <typename R, bool ONE, bool UNIFORM = false>
 __device__ __forceinline__ void batch_tile(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
                                            const Tile& t, int parity, int tx, int ty) {
   const Consts<R> k = cases[t.c].k;
@@ -50,10 +58,10 @@ __device__ __forceinline__ void batch_tile(R* __restrict__ pool, const BatchCase
   const R* src = pool + o_src;
   R* dst = pool + o_dst;
   if constexpr (ONE) {
-    batch_cell(src, dst, k, t, threadIdx.x, tx);
+    batch_cell<R, UNIFORM>(src, dst, k, t, threadIdx.x, tx);
   } else {
     const int n = tx * ty;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) batch_cell(src, dst, k, t, i, tx);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) batch_cell<R, UNIFORM>(src, dst, k, t, i, tx);
   }
 }
 
@@ -65,13 +73,13 @@ __device__ __forceinline__ int xcd_logical(int flat, int total) {
   return xcd * full + (xcd < rem ? xcd : rem) + slot;
 }
 
-template <typename R, bool ONE>
+template <typename R, bool ONE, bool UNIFORM>
 __global__ __launch_bounds__(kBlock) void k_batch_step(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
                                                        const Tile* __restrict__ tiles, int ntiles, int parity,
                                                        int tx, int ty) {
   const int t = xcd_logical(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
-  batch_tile<R, ONE>(pool, cases, tiles[t], parity, tx, ty);
+  batch_tile<R, ONE, UNIFORM>(pool, cases, tiles[t], parity, tx, ty);
 }
 
 // The persistent form keeps the cell loop for every tile shape: its grid is

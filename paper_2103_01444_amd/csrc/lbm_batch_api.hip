@@ -91,6 +91,7 @@ struct lbm_batch {
   lbm_schedule sched{256, 1, 0, 0};
   int ntiles = 0;
   int persistent_grid = 0;
+  int64_t cells = 0;  // lattice nodes over all cases
   std::string err;
 
   template <typename R>
@@ -184,13 +185,23 @@ lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
     }
   } else {
     const bool one = tx * ty == kBlock;
+    // batches of few nodes (one round of wavefronts per launch) take the
+    // wave-uniform addressing form
+    const bool uniform = b->cells < (int64_t(1) << 20);
+    const dim3 grid(b->ntiles), block(kBlock);
     for (int64_t s = 0; s < nsteps; ++s) {
-      if (one)
-        hipLaunchKernelGGL((k_batch_step<R, true>), dim3(b->ntiles), dim3(kBlock), 0, b->stream, pool, cases, tiles,
-                           b->ntiles, b->parity, tx, ty);
+      if (one && uniform)
+        hipLaunchKernelGGL((k_batch_step<R, true, true>), grid, block, 0, b->stream, pool, cases, tiles, b->ntiles,
+                           b->parity, tx, ty);
+      else if (one)
+        hipLaunchKernelGGL((k_batch_step<R, true, false>), grid, block, 0, b->stream, pool, cases, tiles, b->ntiles,
+                           b->parity, tx, ty);
+      else if (uniform)
+        hipLaunchKernelGGL((k_batch_step<R, false, true>), grid, block, 0, b->stream, pool, cases, tiles, b->ntiles,
+                           b->parity, tx, ty);
       else
-        hipLaunchKernelGGL((k_batch_step<R, false>), dim3(b->ntiles), dim3(kBlock), 0, b->stream, pool, cases, tiles,
-                           b->ntiles, b->parity, tx, ty);
+        hipLaunchKernelGGL((k_batch_step<R, false, false>), grid, block, 0, b->stream, pool, cases, tiles, b->ntiles,
+                           b->parity, tx, ty);
       b->parity ^= 1;
     }
     const hipError_t e = hipGetLastError();
@@ -361,6 +372,7 @@ lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t 
   b->L = L;
   b->ws = static_cast<char*>(dev_ws);
   b->stream = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < ncases; ++i) b->cells += int64_t(g[i].nx) * g[i].ny;
   *out = b;
   for (int i = 0; i < ncases; ++i) {
     std::string msg;
