@@ -168,9 +168,7 @@ __device__ __forceinline__ void buffer_store(R* base, uint32_t byte_off, R v) {
 // register-bound collision adjoint leaves little issue slack, gains from it
 // (per reverse step of the 1024x256 adjoint 34.3 against 35.0 us, on another
 // box 33.4 against 34.9 us); the forward kernels run 0.5-1.5 % slower with
-// it (A/B on one box) and keep the per-lane form, and in the reverse step
-// the same form for the adjoint loads, the gradient update and the push
-// costs more in spilled registers than it saves (38.3 us).
+// it (A/B on one box) and keep the per-lane form.
 template <typename R, bool NT = true, bool UNIFORM = false>
 __device__ __forceinline__ void pull(const R* __restrict__ src, const Consts<R>& k, int x, int y,
                                      R (&f)[19]) {
