@@ -24,6 +24,21 @@ __device__ __forceinline__ void seed_mu(const R (&pre)[19], const Mat<R>& mt, co
   }
 }
 
+// a += (first ? b1 : b2), field by field (selecting values, not objects,
+// keeps both operands in registers).
+template <typename R>
+__device__ __forceinline__ void add_mat_adj(MatAdj<R>& a, bool first, const MatAdj<R>& b1, const MatAdj<R>& b2) {
+  a.phi += first ? b1.phi : b2.phi;
+  a.invk += first ? b1.invk : b2.invk;
+  a.sqk += first ? b1.sqk : b2.sqk;
+  a.fphi += first ? b1.fphi : b2.fphi;
+  a.l0 += first ? b1.l0 : b2.l0;
+  a.l1 += first ? b1.l1 : b2.l1;
+  a.bT += first ? b1.bT : b2.bT;
+  a.bC += first ? b1.bC : b2.bC;
+  a.rhocp += first ? b1.rhocp : b2.rhocp;
+}
+
 template <typename R>
 __device__ __forceinline__ void load_node(const R* __restrict__ a, const Consts<R>& k, int x, int y, R (&v)[19]) {
   const uint32_t ob = uint32_t(y * k.pitch + x) * uint32_t(sizeof(R));
@@ -48,15 +63,18 @@ __device__ __forceinline__ void node_mu(const R (&pre)[19], const Mat<R>& mt, co
 // One reverse step: lam_out = (dS'/dS)^T lam_in at the state S, gradients
 // accumulated into grad (planes phi, 1/K, D_eff).  SEED: lam_out = dJ/dS
 // (times w = dJ dx / nx * 4 F C_ref / dt), no lam_in.
-// The first and last wavefront of a row carry the boundary nodes, whose
-// chain is the longest, so the boundary block is shared (see below) and the
-// kernel runs at three waves per SIMD without spills (168 VGPRs): 31.1-31.6
-// us per reverse step of the 1024x256 adjoint, against 34.4 us when the
-// boundary node and its feeding column took separate passes (four waves,
-// 92 bytes spilled per lane) and 40.3 us for the shared block at four waves
-// (144 bytes spilled).
+// The first and last wavefront of a row carry the boundary nodes and the
+// columns feeding them, whose chain is the longest.  A boundary lane runs
+// its own collision adjoint in the common pass of the wavefront (on its
+// extrapolated populations) and the feeding lane reads it across lanes, so
+// that wavefront pays one collision adjoint plus the transposed
+// extrapolation.  Per reverse step of the 1024x256 adjoint: 28.5 us at four
+// waves per SIMD (128 VGPRs, 64 bytes spilled per lane), 29.7-30.1 us at
+// three; 29.3-29.9 us when the feeding lane recomputed the boundary node's
+// collision adjoint, 34.4 us when the boundary and feeding lanes took
+// separate divergent passes.
 template <typename R, bool SEED>
-__global__ __launch_bounds__(kBlock, 3) void k_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
+__global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
                                                      R* __restrict__ lam_out, R* __restrict__ grad,
                                                      const R* __restrict__ phi_f, const R* __restrict__ invk_f,
                                                      const R* __restrict__ d_f, Consts<R> k, R w) {
@@ -80,52 +98,85 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_step(const R* __restrict__ S,
   const int o = y * k.pitch + x;
   const bool bnode = inlet || outlet;
 
-  // Own collision adjoint of every node that is not an inlet / outlet node.
-  if (!bnode) {
-    node_mu<R, SEED>(p, mxp, k, cl, lam_in, x, y, w, mu, ma);
-  } else {
-#pragma unroll
-    for (int q = 0; q < 19; ++q) mu[q] = R(0);
-  }
-  // A boundary node's collision adjoint and the transpose of its
-  // extrapolation from the column next to it.  The boundary node needs them
-  // for its own material, the feeding column for its populations and
-  // material; both pulled that column, so they run this block together (one
-  // pass of the wavefront instead of one per lane kind).
-  if (open && y < k.ny_ch && x <= 1) {  // inlet node (x = 0) and column 1
-    const Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, 0, y);
-    R pre[19];
-#pragma unroll
-    for (int q = 0; q < 19; ++q) pre[q] = p[q];
-    boundary_column(pre, k, y, true, mxp, mb);
-    R mub[19];
-    MatAdj<R> mab{};
-    node_mu<R, SEED>(pre, mb, k, cl, lam_in, 0, y, w, mub, mab);
-    boundary_adj(p, mxp, mb, k, true, inlet_velocity(k, y), R(0), mub, mu, ma, mab);
-    if (x == 0) ma = mab;  // the boundary node keeps the terms of its own material
-  }
-  if (open && x >= k.nx - 2) {  // outlet node (x = nx - 1) and column nx - 2
-    Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, k.nx - 1, y);
-    R pre[19];
-#pragma unroll
-    for (int q = 0; q < 19; ++q) pre[q] = p[q];
-    boundary_column(pre, k, y, false, mxp, mb);
-    outlet_scalar_material(mb, mxp);
-    R mub[19];
-    MatAdj<R> mab{};
-    node_mu<R, SEED>(pre, mb, k, cl, lam_in, k.nx - 1, y, w, mub, mab);
-    if (!outlet) {  // the outlet node collides with column nx - 2's scalar material
-      ma.bT += mab.bT;
-      ma.bC += mab.bC;
-      ma.rhocp += mab.rhocp;
+  // One collision adjoint per lane: its own node's, for an inlet / outlet
+  // node on the populations extrapolated from the column next to it.
+  {
+    Mat<R> mc = mxp;
+    if (bnode) {
+      mc = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y);
+      boundary_column(p, k, y, inlet, mxp, mc);
+      if (outlet) outlet_scalar_material(mc, mxp);
     }
-    boundary_adj(p, mxp, mb, k, false, R(0), R(0), mub, mu, ma, mab);
-    if (outlet) {  // its scalar material terms belong to column nx - 2
-      ma = mab;
-      ma.bT = R(0);
-      ma.bC = R(0);
-      ma.rhocp = R(0);
+    node_mu<R, SEED>(p, mc, k, cl, lam_in, x, y, w, mu, ma);
+  }
+  if (bnode) pull<R, true, false>(S, k, xp, y, p);  // the column's own populations again
+
+  // Transpose of the extrapolation of a boundary node from the column next
+  // to it: the boundary node needs it for its own material, the feeding
+  // column for its populations and material.  Both lanes pulled that
+  // column; the feeding lane takes the boundary node's collision adjoint
+  // from its lane by a cross-lane read, and the two run the block together.
+  if (open && y < k.ny_ch && x < 64) {  // the wavefront holding x = 0 and 1
+    R mub[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) mub[q] = __shfl(mu[q], 0, 64);
+    if (x <= 1) {
+      const Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, 0, y);
+      MatAdj<R> axp{}, ab{};
+      boundary_adj(p, mxp, mb, k, true, inlet_velocity(k, y), R(0), mub, mu, axp, ab);
+      add_mat_adj(ma, x == 0, ab, axp);
     }
+  }
+  if (open) {
+    const int xo = k.nx - 1;
+    if ((xo & 63) != 0) {  // x = nx - 2 and nx - 1 in one wavefront
+      if ((x & ~63) == (xo & ~63)) {
+        const int src = xo & 63;
+        R mub[19];
+#pragma unroll
+        for (int q = 0; q < 19; ++q) mub[q] = __shfl(mu[q], src, 64);
+        const R sbT = __shfl(ma.bT, src, 64), sbC = __shfl(ma.bC, src, 64), src_p = __shfl(ma.rhocp, src, 64);
+        if (x >= xo - 1) {
+          Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xo, y);
+          outlet_scalar_material(mb, mxp);
+          if (!outlet) {  // the outlet node collides with column nx - 2's scalar material
+            ma.bT += sbT;
+            ma.bC += sbC;
+            ma.rhocp += src_p;
+          }
+          MatAdj<R> axp{}, ab{};
+          boundary_adj(p, mxp, mb, k, false, R(0), R(0), mub, mu, axp, ab);
+          add_mat_adj(ma, outlet, ab, axp);
+        }
+      }
+    } else if (x >= xo - 1) {  // the pair straddles two wavefronts: each lane on its own
+      Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xo, y);
+      R mub[19];
+      if (outlet) {
+#pragma unroll
+        for (int q = 0; q < 19; ++q) mub[q] = mu[q];
+        outlet_scalar_material(mb, mxp);
+      } else {
+        R pre[19];
+#pragma unroll
+        for (int q = 0; q < 19; ++q) pre[q] = p[q];
+        boundary_column(pre, k, y, false, mxp, mb);
+        outlet_scalar_material(mb, mxp);
+        MatAdj<R> mab{};
+        node_mu<R, SEED>(pre, mb, k, cl, lam_in, xo, y, w, mub, mab);
+        ma.bT += mab.bT;
+        ma.bC += mab.bC;
+        ma.rhocp += mab.rhocp;
+      }
+      MatAdj<R> axp{}, ab{};
+      boundary_adj(p, mxp, mb, k, false, R(0), R(0), mub, mu, axp, ab);
+      add_mat_adj(ma, outlet, ab, axp);
+    }
+  }
+  if (outlet) {  // its scalar material terms belong to column nx - 2
+    ma.bT = R(0);
+    ma.bC = R(0);
+    ma.rhocp = R(0);
   }
   if (bnode) {  // its pulled sources were never read: their adjoint is 0
 #pragma unroll
