@@ -36,7 +36,7 @@ __device__ __forceinline__ void node_mu(const R (&pre)[33], const Mat3<R>& mt, c
   } else {
     R la[33];
 #pragma unroll
-    for (int q = 0; q < 33; ++q) la[q] = lam_in[q * k.plane + o];
+    for (int q = 0; q < 33; ++q) la[q] = lbm::buffer_load<R, 0>(lam_in + int64_t(q) * k.plane, uint32_t(o) * uint32_t(sizeof(R)));
     collide_adj(pre, mt, k, cl, la, mu, ma);
   }
 }
@@ -46,9 +46,17 @@ __device__ __forceinline__ void node_mu(const R (&pre)[33], const Mat3<R>& mt, c
 template <typename R, bool ADD>
 __device__ __forceinline__ void push(R* __restrict__ lam_out, const Consts3<R>& k, int x, int y, int z,
                                      const R (&mu)[33]) {
-  const bool px = k.flags & F_PERIODIC_X, py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
   const int rowp = k.pitch * k.ny;
   const int o = z * rowp + y * k.pitch + x;
+  if (!ADD && __all(x >= 1 && x <= k.nx - 2 && y >= 1 && y <= k.ny - 2 && z >= 1 && z <= k.nz - 2)) {
+    const uint32_t ob = uint32_t(o) * uint32_t(sizeof(R));
+#pragma unroll
+    for (int q = 0; q < 33; ++q)
+      lbm::buffer_store(lam_out + (int64_t(q) * k.plane - int64_t(EZ[q]) * rowp - int64_t(EY[q]) * k.pitch - EX[q]),
+                        ob, mu[q]);
+    return;
+  }
+  const bool px = k.flags & F_PERIODIC_X, py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
 #pragma unroll
   for (int q = 0; q < 33; ++q) {
     int xs = x - EX[q], ys = y - EY[q], zs = z - EZ[q];
@@ -84,7 +92,7 @@ __global__ __launch_bounds__(kBlock3) void k3_adj_step(const R* __restrict__ S, 
   } else {
     const int o = (z * k.ny + y) * k.pitch + x;
     R p[33];
-    pull(S, k, x, y, z, p);
+    pull<R, true>(S, k, x, y, z, p);
     const Mat3<R> mt = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y, z);
     MatAdj3<R> ma{};
     node_mu<R, SEED>(p, mt, k, cl, lam_in, o, w, mu, ma);

@@ -98,11 +98,23 @@ __device__ __forceinline__ Mat3<R> material(const Consts3<R>& k, const R* __rest
   return m;
 }
 
-template <typename R>
+// UNIFORM: a wavefront whose nodes all lie one node or more inside the
+// lattice folds each population's plane and neighbour shift into a
+// wave-uniform buffer base (scalar registers) and adds one shared 32-bit
+// lane offset (used by the reverse step).
+template <typename R, bool UNIFORM = false>
 __device__ __forceinline__ void pull(const R* __restrict__ src, const Consts3<R>& k, int x, int y, int z,
                                      R (&f)[33]) {
-  const bool px = k.flags & F_PERIODIC_X, py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
   const int row = k.pitch * k.ny;
+  if (UNIFORM && __all(x >= 1 && x <= k.nx - 2 && y >= 1 && y <= k.ny - 2 && z >= 1 && z <= k.nz - 2)) {
+    const uint32_t ob = uint32_t(z * row + y * k.pitch + x) * uint32_t(sizeof(R));
+#pragma unroll
+    for (int q = 0; q < 33; ++q)
+      f[q] = lbm::buffer_load<R, 2>(
+          src + (int64_t(q) * k.plane - int64_t(EZ[q]) * row - int64_t(EY[q]) * k.pitch - EX[q]), ob);
+    return;
+  }
+  const bool px = k.flags & F_PERIODIC_X, py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
 #pragma unroll
   for (int q = 0; q < 33; ++q) {
     int xs = x - EX[q], ys = y - EY[q], zs = z - EZ[q];
