@@ -177,37 +177,54 @@ __global__ __launch_bounds__(64) void k3_adj_bnd(const R* __restrict__ S, const 
 }
 
 // One reverse step, apply pass (after both): one thread per (row,
-// population) adds the inlet and then the outlet slot to the element the
-// feeding column pushed (one after the other, so nx = 3, where both feed
-// column 1, is safe); population 0's thread also adds the gradient shares.
+// population) adds the inlet and the outlet slot to the elements the feeding
+// columns pushed, and one thread per (row, gradient component) adds the
+// gradient shares.  For nx > 3 the two targets of a thread differ (columns 1
+// and nx - 2), so both are loaded before either is stored; for nx = 3, where
+// both feed column 1, they are added one after the other.
+template <typename R>
+__device__ __forceinline__ int apply_target(const Consts3<R>& k, int q, int xp, int y, int z) {
+  const bool py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
+  const int rowp = k.pitch * k.ny;
+  const int xs = xp - EX[q];  // in [0, nx - 1]: x is open here
+  int ys = y - EY[q], zs = z - EZ[q];
+  if (py) ys = ys < 0 ? ys + k.ny : (ys >= k.ny ? ys - k.ny : ys);
+  if (pz) zs = zs < 0 ? zs + k.nz : (zs >= k.nz ? zs - k.nz : zs);
+  const bool in = (unsigned)ys < (unsigned)k.ny && (unsigned)zs < (unsigned)k.nz;
+  return in ? (q * k.plane + zs * rowp + ys * k.pitch + xs) : (OPP[q] * k.plane + z * rowp + y * k.pitch + xp);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock3) void k3_adj_apply(const R* __restrict__ side, R* __restrict__ lam_out,
                                                         R* __restrict__ grad, Consts3<R> k) {
   const int nrows = k.ny * k.nz;
   const int t = blockIdx.x * kBlock3 + threadIdx.x;
-  if (t >= 33 * nrows) return;
+  if (t >= 36 * nrows) return;
   const int q = t / nrows, r = t - q * nrows;
   const int z = r / k.ny, y = r - z * k.ny;
   const int slots = 2 * nrows;
-  const bool px = k.flags & F_PERIODIC_X, py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
-  const int rowp = k.pitch * k.ny;
-  for (int s = 0; s < 2; ++s) {
-    if (s == 0 && z >= k.nz_ch) continue;
-    const int slot = s * nrows + r;
-    const int xp = s == 0 ? 1 : k.nx - 2;
-    int xs = xp - EX[q], ys = y - EY[q], zs = z - EZ[q];
-    if (px) xs = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
-    if (py) ys = ys < 0 ? ys + k.ny : (ys >= k.ny ? ys - k.ny : ys);
-    if (pz) zs = zs < 0 ? zs + k.nz : (zs >= k.nz ? zs - k.nz : zs);
-    const bool in = (unsigned)xs < (unsigned)k.nx && (unsigned)ys < (unsigned)k.ny && (unsigned)zs < (unsigned)k.nz;
-    const int o = z * rowp + y * k.pitch + xp;
-    const int off = in ? (q * k.plane + zs * rowp + ys * k.pitch + xs) : (OPP[q] * k.plane + o);
-    lam_out[off] += side[q * slots + slot];
-    if (q == 0) {
-      grad[o] += side[33 * slots + slot];
-      grad[k.plane + o] += side[34 * slots + slot];
-      grad[2 * k.plane + o] += side[35 * slots + slot];
-    }
+  const bool in_row = z < k.nz_ch;  // the row has an inlet node
+  const R a_in = in_row ? side[q * slots + r] : R(0);
+  const R a_out = side[q * slots + nrows + r];
+  int o_in, o_out;
+  R* base;
+  if (q < 33) {
+    base = lam_out;
+    o_in = apply_target(k, q, 1, y, z);
+    o_out = apply_target(k, q, k.nx - 2, y, z);
+  } else {
+    base = grad + int64_t(q - 33) * k.plane;
+    const int rowp = k.pitch * k.ny;
+    o_in = z * rowp + y * k.pitch + 1;
+    o_out = z * rowp + y * k.pitch + k.nx - 2;
+  }
+  if (k.nx > 3 && in_row) {
+    const R v_in = base[o_in], v_out = base[o_out];
+    base[o_in] = v_in + a_in;
+    base[o_out] = v_out + a_out;
+  } else {
+    if (in_row) base[o_in] += a_in;
+    base[o_out] += a_out;
   }
 }
 

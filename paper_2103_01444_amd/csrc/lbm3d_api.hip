@@ -556,7 +556,7 @@ lbm_status reverse_step3(lbm3d_ctx* c, const R* S, const R* lam_in, R* lam_out, 
   if (open) {
     if (hipStreamWaitEvent(c->stream, c->ev_bnd, 0) != hipSuccess)
       return fail3(c, LBM_ERR_DEVICE, "boundary pass join failed");
-    hipLaunchKernelGGL(k3_adj_apply<R>, dim3(unsigned((33 * int64_t(nrows) + kBlock3 - 1) / kBlock3)), dim3(kBlock3), 0,
+    hipLaunchKernelGGL(k3_adj_apply<R>, dim3(unsigned((36 * int64_t(nrows) + kBlock3 - 1) / kBlock3)), dim3(kBlock3), 0,
                        c->stream, side, lam_out, grad, k);
   }
   return LBM_OK;
