@@ -266,8 +266,9 @@ const char* lbm_last_error(const lbm_ctx* ctx);
  * --------------------------------------------------------------------------- */
 
 /* Device workspace for a checkpointed run: ceil(nsteps/every) checkpoints,
- * a replay buffer of `every` states, two adjoint states, three gradient
- * planes.  0 if invalid. */
+ * two replay buffers of min(every, nsteps) states (the next segment is
+ * replayed on a second stream while one is swept), two adjoint states,
+ * three gradient planes.  0 if invalid. */
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int64_t nsteps, int32_t every);
 
 /* Initialise to equilibrium, run nsteps steps storing a checkpoint every
@@ -281,7 +282,9 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* ctx, int64_t nsteps, int32_t every,
 /* dJ times dJ/d(1/K), dJ/dphi, dJ/dD_eff of the preceding checkpointed run,
  * written (not accumulated) into caller device arrays [ny][nx] (context
  * precision; NULL skips one).  Replays each segment from its checkpoint and
- * sweeps it in reverse.  Synchronous.  LBM_ERR_STATE without a matching
+ * sweeps it in reverse; the replays run on a second HIP stream the library
+ * creates on first use (default priority, ordered by events, destroyed by
+ * lbm_destroy).  Synchronous.  LBM_ERR_STATE without a matching
  * lbm_forward_checkpointed (or after the state was changed since). */
 lbm_status lbm_backward(lbm_ctx* ctx, double dJ, void* grad_inv_k, void* grad_phi, void* grad_d_eff);
 

@@ -82,6 +82,10 @@ struct lbm_ctx {
   int32_t adj_every = 0;
   int64_t adj_step = -1;
   bool adj_ready = false;
+  // second stream and events of the reverse sweep: the replay of the next
+  // segment runs there while the current one is swept
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_in = nullptr, ev_rep[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
 
   void* state(int i) { return ws + L.off_state[i]; }
   void* mat_plane(int i) { return ws + L.off_mat + size_t(i) * L.plane * L.esize; }
@@ -153,12 +157,13 @@ MatPtrs<R> mat_ptrs(lbm_ctx* c) {
 constexpr int64_t kUniformMaxCells = int64_t(1) << 20;
 
 template <typename R, int MAT>
-void launch_step_kernel(lbm_ctx* c, const R* src, R* dst, const MatPtrs<R>& m, const Consts<R>& k) {
+void launch_step_kernel(lbm_ctx* c, const R* src, R* dst, const MatPtrs<R>& m, const Consts<R>& k,
+                        hipStream_t stream) {
   const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
   if (int64_t(c->g.nx) * c->g.ny < kUniformMaxCells)
-    hipLaunchKernelGGL((k_step<R, MAT, true>), grid, dim3(kBlock), 0, c->stream, src, dst, m.phi, m.invk, m.d, k);
+    hipLaunchKernelGGL((k_step<R, MAT, true>), grid, dim3(kBlock), 0, stream, src, dst, m.phi, m.invk, m.d, k);
   else
-    hipLaunchKernelGGL((k_step<R, MAT, false>), grid, dim3(kBlock), 0, c->stream, src, dst, m.phi, m.invk, m.d, k);
+    hipLaunchKernelGGL((k_step<R, MAT, false>), grid, dim3(kBlock), 0, stream, src, dst, m.phi, m.invk, m.d, k);
 }
 
 template <typename R, int MAT>
@@ -167,7 +172,7 @@ void launch_step_mat(lbm_ctx* c, int64_t n) {
   const Consts<R> k = consts<R>(c);
   for (int64_t i = 0; i < n; ++i) {
     launch_step_kernel<R, MAT>(c, static_cast<const R*>(c->state(c->cur)), static_cast<R*>(c->state(c->cur ^ 1)), m,
-                               k);
+                               k, c->stream);
     c->cur ^= 1;
   }
 }
@@ -530,7 +535,16 @@ lbm_status lbm_synchronize(lbm_ctx* c) {
   return LBM_OK;
 }
 
-void lbm_destroy(lbm_ctx* c) { delete c; }
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+  }
+  for (hipEvent_t e : {c->ev_in, c->ev_rep[0], c->ev_rep[1], c->ev_rev[0], c->ev_rev[1]})
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
 
 const char* lbm_status_string(lbm_status s) {
   switch (s) {
@@ -569,8 +583,8 @@ AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int32_t every) {
   size_t o = 0;
   A.off_ck = o;
   o += size_t(A.nck) * A.state;
-  A.off_replay = o;
-  o += size_t(every) * A.state;
+  A.off_replay = o;  // two replay buffers (the next segment is replayed while one is swept)
+  o += size_t(2) * size_t(std::min<int64_t>(every, nsteps)) * A.state;
   A.off_lam = o;
   o += 2 * A.state;
   A.off_grad = o;
@@ -580,8 +594,9 @@ AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int32_t every) {
 }
 
 template <typename R>
-void launch_one_step(lbm_ctx* c, const void* src, void* dst) {
-  launch_step_kernel<R, MAT_FULL>(c, static_cast<const R*>(src), static_cast<R*>(dst), mat_ptrs<R>(c), consts<R>(c));
+void launch_one_step(lbm_ctx* c, const void* src, void* dst, hipStream_t stream) {
+  launch_step_kernel<R, MAT_FULL>(c, static_cast<const R*>(src), static_cast<R*>(dst), mat_ptrs<R>(c), consts<R>(c),
+                                  stream);
 }
 
 template <typename R>
@@ -602,22 +617,57 @@ lbm_status backward_t(lbm_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_
   hipLaunchKernelGGL((k_adj_step<R, true>), grid, dim3(kBlock), 0, c->stream,
                      static_cast<const R*>(c->state(c->cur)), static_cast<const R*>(nullptr), lam[0], grad, m.phi,
                      m.invk, m.d, k, R(w));
+  // Segments are swept from the last to the first.  Segment s - 1 is
+  // replayed from its checkpoint into one replay buffer on the second
+  // stream while segment s is swept in reverse from the other on the
+  // context stream: a replay waits for the sweep that last used its buffer,
+  // a sweep waits for the replay of its segment.
+  if (!c->aux) {
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+      c->aux = nullptr;
+      return fail(c, LBM_ERR_DEVICE, "second stream creation failed");
+    }
+    for (hipEvent_t* e : {&c->ev_in, &c->ev_rep[0], &c->ev_rep[1], &c->ev_rev[0], &c->ev_rev[1]})
+      if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
+        return fail(c, LBM_ERR_DEVICE, "event creation failed");
+  }
+  const size_t rbuf = size_t(std::min<int64_t>(c->adj_every, c->adj_nsteps)) * A.state;
+  bool used[2] = {false, false};
+  if (hipEventRecord(c->ev_in, c->stream) != hipSuccess || hipStreamWaitEvent(c->aux, c->ev_in, 0) != hipSuccess)
+    return fail(c, LBM_ERR_DEVICE, "replay ordering failed");
+  auto seg_len = [&](int seg) {
+    return int(std::min<int64_t>(c->adj_every, c->adj_nsteps - int64_t(seg) * c->adj_every));
+  };
+  auto replay = [&](int seg, int b) -> lbm_status {
+    char* buf = ws + A.off_replay + size_t(b) * rbuf;
+    if (used[b] && hipStreamWaitEvent(c->aux, c->ev_rev[b], 0) != hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "replay ordering failed");
+    if (hipMemcpyAsync(buf, ws + A.off_ck + size_t(seg) * A.state, A.state, hipMemcpyDeviceToDevice, c->aux) !=
+        hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "replay restore failed");
+    const int len = seg_len(seg);
+    for (int j = 1; j < len; ++j)
+      launch_one_step<R>(c, buf + size_t(j - 1) * A.state, buf + size_t(j) * A.state, c->aux);
+    if (hipEventRecord(c->ev_rep[b], c->aux) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "replay event failed");
+    return LBM_OK;
+  };
+  if (lbm_status st = replay(A.nck - 1, 0); st != LBM_OK) return st;
   int cur = 0;
   for (int seg = A.nck - 1; seg >= 0; --seg) {
-    const int64_t start = int64_t(seg) * c->adj_every;
-    const int len = int(std::min<int64_t>(c->adj_every, c->adj_nsteps - start));
-    char* replay = ws + A.off_replay;
-    if (hipMemcpyAsync(replay, ws + A.off_ck + size_t(seg) * A.state, A.state, hipMemcpyDeviceToDevice,
-                       c->stream) != hipSuccess)
-      return fail(c, LBM_ERR_DEVICE, "replay restore failed");
-    for (int j = 1; j < len; ++j)
-      launch_one_step<R>(c, replay + size_t(j - 1) * A.state, replay + size_t(j) * A.state);
-    for (int j = len - 1; j >= 0; --j) {
+    const int b = (A.nck - 1 - seg) & 1;
+    if (seg > 0)
+      if (lbm_status st = replay(seg - 1, b ^ 1); st != LBM_OK) return st;
+    if (hipStreamWaitEvent(c->stream, c->ev_rep[b], 0) != hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "replay join failed");
+    const char* buf = ws + A.off_replay + size_t(b) * rbuf;
+    for (int j = seg_len(seg) - 1; j >= 0; --j) {
       hipLaunchKernelGGL((k_adj_step<R, false>), grid, dim3(kBlock), 0, c->stream,
-                         reinterpret_cast<const R*>(replay + size_t(j) * A.state), lam[cur], lam[cur ^ 1], grad,
-                         m.phi, m.invk, m.d, k, R(0));
+                         reinterpret_cast<const R*>(buf + size_t(j) * A.state), lam[cur], lam[cur ^ 1], grad, m.phi,
+                         m.invk, m.d, k, R(0));
       cur ^= 1;
     }
+    if (hipEventRecord(c->ev_rev[b], c->stream) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "sweep event failed");
+    used[b] = true;
   }
   hipLaunchKernelGGL(k_adj_init<R>, grid, dim3(kBlock), 0, c->stream, lam[cur], grad, k);
   void* outs[3] = {g_phi, g_invk, g_d};
