@@ -32,9 +32,14 @@ constexpr int OPP[19] = {0, 3, 4, 1, 2, 7, 8, 5, 6, 9, 12, 13, 10, 11, 14, 17, 1
 // Per-launch constants, in the kernel's arithmetic type R.
 template <typename R>
 struct Consts {
+  // Population q of node (x, y) is element q * plane + y * pitch + x: planar
+  // states have pitch = the padded row length and plane = pitch * ny (plus
+  // padding); the batched pool is row-interleaved, plane = the row length
+  // and pitch = 19 row lengths.  Per-cell fields use y * pitch + x and exist
+  // only in the planar (single-lattice) layout.
   int32_t nx, ny, pitch, ny_ch, y_cl0;
   uint32_t flags;
-  int32_t plane;        // elements per population plane (pitch * ny)
+  int32_t plane;        // stride between population q and q + 1
   int32_t bv;           // nonzero: Butler-Volmer kinetics (anodic branch), else the printed Tafel form
   // flow (Section 2.1)
   R s_e, s_q, nu;       // s_e: rate of rho, e, zeta, pxx, pxy; s_q: energy flux
