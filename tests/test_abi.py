@@ -142,3 +142,20 @@ def test_binding_constants_match_header_defines():
     assert len(defines) >= 12
     for name, val in defines.items():
         assert getattr(lbm, name) == val, name
+
+
+def test_null_handles_are_refused_without_touching_the_gpu(lib):
+    """Every entry point given a null context / batch returns
+    LBM_ERR_INVALID_ARG (or 0 / -1 / a message) and launches nothing;
+    destroying a null handle is a no-op."""
+    assert lib.lbm_step(None, 1) == 1 and lib.lbm3d_step(None, 1) == 1 and lib.lbm_batch_step(None, 1) == 1
+    assert lib.lbm_init_equilibrium(None) == 1 and lib.lbm_synchronize(None) == 1
+    assert lib.lbm_observables(None, None, None, None, None) == 1 and lib.lbm_batch_observables(None, None) == 1
+    assert lib.lbm_backward(None, 1.0, None, None, None) == 1 and lib.lbm3d_backward(None, 1.0, None, None, None) == 1
+    assert lib.lbm_adjoint_workspace_bytes(None, 10, 5) == 0 and lib.lbm3d_adjoint_workspace_bytes(None, 10, 5) == 0
+    assert lib.lbm_step_count(None) == -1 and lib.lbm3d_step_count(None) == -1 and lib.lbm_batch_step_count(None) == -1
+    assert lib.lbm_last_error(None) == b"null context" and lib.lbm3d_last_error(None) == b"null context"
+    assert lib.lbm_batch_last_error(None) == b"null batch"
+    lib.lbm_destroy(None)
+    lib.lbm3d_destroy(None)
+    lib.lbm_batch_destroy(None)
