@@ -39,12 +39,12 @@ def _compare(fg, fo, vel, others, label):
     for key in vel:
         err = float((fg[key].cpu() - fo[key]).abs().max()) / u_scale
         print(f"{label} {key}: rel {err:.1e}", flush=True)
-        assert err < 1e-11, key
+        assert err < 1e-12, key
     for key in others:
         scale = float(fo[key].abs().max())
         err = float((fg[key].cpu() - fo[key]).abs().max()) / max(scale, 1e-300)
         print(f"{label} {key}: rel {err:.1e}", flush=True)
-        assert err < 1e-11 or scale == 0.0, key
+        assert err < 1e-12 or scale == 0.0, key
 
 
 def _max_rel(a, b):

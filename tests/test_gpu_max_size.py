@@ -3,7 +3,14 @@ within 32-bit element offsets): 8192 x 13790 in FP64, periodic in x with a
 body force along x, so that every column carries the same solution.  The
 GPU run is compared column by column with the FP64 oracle on a 3-column
 periodic lattice of the same rows; the offsets of the last rows of the
-last planes sit just below 2^31."""
+last planes sit just below 2^31.
+
+Every field and observable is held to 1e-12 of its largest value.  The body
+force is chosen so that the flow reaches about 1e-3 in lattice units, the
+order of the workloads' velocities, within the run: the velocity is a
+difference of populations of order 0.1, whose FP64 round-off (about 1e-16
+absolute per step) would dominate a relative comparison of a velocity
+orders of magnitude smaller."""
 import pytest
 import torch
 
@@ -25,7 +32,7 @@ def test_largest_accepted_lattice_matches_the_oracle():
     w = dict(W.cathode2d_200x40(), nx=nx, ny=ny, ny_channel=layers[0], ny_gdl=layers[1], ny_cl=layers[2],
              precision=64, Re=0.0, V_op=0.45)
     flags = lbm.LBM_PERIODIC_X | lbm.LBM_BODY_FORCE
-    bf = 1e-6
+    bf = 2e-5
     gpu = lbm.Cathode.from_workload(w, flags=flags, body_force_x=bf, dx_cm=1e-3)
     steps = 60
     gpu.step(steps)
@@ -42,18 +49,21 @@ def test_largest_accepted_lattice_matches_the_oracle():
     m = L.Model(L.Geometry(3, ny, *layers, periodic_x=True), p)
     s = m.run(m.initial_state(), steps)
     fo = m.fields(s)
-    # u is a difference of O(1) populations: its round-off is ~1e-16 absolute
-    for key, tol in (("ux", 1e-10), ("theta", 1e-11), ("c", 1e-11)):
+    for key, tol in (("ux", 1e-12), ("theta", 1e-12), ("c", 1e-12)):
         ref = fo[key][:, :1].expand(ny, len(cols))
         scale = float(ref.abs().max())
         err = float((fg[key] - ref).abs().max()) / scale
         print(f"max lattice {key}: rel err {err:.1e} (scale {scale:.2e})", flush=True)
         assert err < tol, key
     uy_ref = fo["uy"][:, :1].expand(ny, len(cols))  # small but not zero at the layer interfaces
-    assert float((fg["uy"] - uy_ref).abs().max()) < 1e-10 * float(fo["ux"].abs().max())
+    e = float((fg["uy"] - uy_ref).abs().max()) / float(fo["ux"].abs().max())
+    print(f"max lattice uy: err {e:.1e} of max |ux|", flush=True)
+    assert e < 1e-12
     oo = m.observables(s)
     for key in ("current_density", "heat_rate", "T_max"):
-        assert abs(o_gpu[key] / float(oo[key]) - 1) < 1e-11, key
+        e = abs(o_gpu[key] / float(oo[key]) - 1)
+        print(f"max lattice {key}: rel err {e:.1e}", flush=True)
+        assert e < 1e-12, key
 
 
 def test_largest_accepted_3d_lattice_matches_the_oracle():
@@ -72,7 +82,7 @@ def test_largest_accepted_3d_lattice_matches_the_oracle():
     w = W.cathode3d_scaled(nx, ny, nz, precision=64, nz_channel=layers[0], nz_gdl=layers[1], nz_cl=layers[2],
                            Re=0.0, V_op=0.45, dp_lat=0.0, Da_gdl=1e-3)
     flags = lbm.LBM_PERIODIC_X | lbm.LBM_PERIODIC_Y | lbm.LBM_BODY_FORCE
-    bf = 1e-6
+    bf = 2e-5
     gpu = lbm.Cathode3D.from_workload(w, flags=flags, body_force_x=bf, dx_cm=1e-3)
     steps = 40
     gpu.step(steps)
@@ -86,11 +96,13 @@ def test_largest_accepted_3d_lattice_matches_the_oracle():
     p.dx_cm = 1e-3
     m = L3.Model3D(L3.Geometry3D(3, 3, nz, *layers, periodic_x=True, periodic_y=True), p)
     fo = m.fields(m.run(m.initial_state(), steps))
-    for key, tol in (("ux", 1e-10), ("theta", 1e-11), ("c", 1e-11)):
+    for key, tol in (("ux", 1e-12), ("theta", 1e-12), ("c", 1e-12)):
         ref = fo[key][:, :1, 0].expand(nz, len(pts))
         scale = float(ref.abs().max())
         err = float((fg[key] - ref).abs().max()) / scale
         print(f"max 3D lattice {key}: rel err {err:.1e} (scale {scale:.2e})", flush=True)
         assert err < tol, key
     uz_ref = fo["uz"][:, :1, 0].expand(nz, len(pts))
-    assert float((fg["uz"] - uz_ref).abs().max()) < 1e-10 * float(fo["ux"].abs().max())
+    e = float((fg["uz"] - uz_ref).abs().max()) / float(fo["ux"].abs().max())
+    print(f"max 3D lattice uz: err {e:.1e} of max |ux|", flush=True)
+    assert e < 1e-12

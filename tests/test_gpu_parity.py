@@ -72,7 +72,9 @@ def test_fp64_cathode_200x40_full_run():
         fg = gpu.fields()
         fo = m.fields(s)
         compare_fields(fg, fo, 1e-12, f"200x40 fp64 step {gpu.step_count}")
-        assert rel(fg["p"], fo["p"]) < 1e-11
+        ep = rel(fg["p"], fo["p"])
+        print(f"200x40 fp64 step {gpu.step_count} p rel err {ep:.2e}", flush=True)
+        assert ep < 1e-12
     og, oo = gpu.observables(), m.observables(s)
     for key in ("current_density", "power_density", "heat_rate", "o2_utilisation", "T_max", "sum_f", "sum_theta",
                 "sum_c", "consumed_c", "heat_added"):
@@ -150,19 +152,31 @@ def test_one_step_periodic_and_body_force_modes(flags):
 
 
 def test_poiseuille_on_gpu_matches_closed_form():
-    """Independent of the oracle: the FP64 kernel reproduces the exact
-    half-way bounce-back Poiseuille profile (Section 2.1 rates)."""
+    """Independent of the oracle: the FP64 kernel reproduces the half-way
+    bounce-back Poiseuille profile (Section 2.1 rates).  The closed form is
+    that of incompressible flow; the scheme departs from it by a relative
+    amount proportional to the speed (3.1e-8 at a peak speed of 8e-4,
+    3.1e-12 at 8e-6, the same in the oracle), so the closed form is met to
+    that departure and the oracle's run of the same case to 1e-12."""
     lbm = _gpu_mod()
-    H, a = 8, 1e-7
-    p = lbm.default_params()
-    p.tau_f, p.body_force_x, p.dx_cm, p.Re = 0.8, a, 1e-3, 0.0
-    gpu = lbm.Cathode(4, H, H, 0, 0, p, precision=64, flags=_flags(px=True, body=True, noreact=True))
-    gpu.step(2500)
-    u = gpu.fields()["ux"][:, 0].double().cpu()
+    H = 8
     nu = (0.8 - 0.5) / 3
     y = torch.arange(H, dtype=DT)
-    exact = a / (2 * nu) * (y + 0.5) * (H - 0.5 - y)
-    assert rel(u, exact) < 1e-11
+    for a, tol_exact in ((1e-5, 4e-8), (1e-7, 4e-12)):
+        p = lbm.default_params()
+        p.tau_f, p.body_force_x, p.dx_cm, p.Re = 0.8, a, 1e-3, 0.0
+        gpu = lbm.Cathode(4, H, H, 0, 0, p, precision=64, flags=_flags(px=True, body=True, noreact=True))
+        gpu.step(2500)
+        u = gpu.fields()["ux"][:, 0].double().cpu()
+        exact = a / (2 * nu) * (y + 0.5) * (H - 0.5 - y)
+        e = rel(u, exact)
+        m = L.Model(L.Geometry(4, H, H, 0, 0, periodic_x=True),
+                    L.Params(tau_f=0.8, body_force=(a, 0.0), dx_cm=1e-3, Re=0.0, reaction=False))
+        eo = rel(u, m.fields(m.run(m.initial_state(), 2500))["ux"][:, 0])
+        print(f"GPU Poiseuille a={a:.0e}: rel err {e:.2e} (closed form), {eo:.2e} (oracle)", flush=True)
+        assert e < tol_exact
+        if a >= 1e-5:  # at 8e-6 the speed is 1e-4 of the populations: their round-off is 1e-12 of it
+            assert eo < 1e-12
 
 
 # ---------------------------------------------------------------- FP32 parity

@@ -40,7 +40,7 @@ def test_pressure_driven_channel_is_exact_poiseuille_on_gpu(p_in, p_out):
     x = torch.arange(nx, dtype=DT)
     perr = float((f["p"].cpu() - (p_in + (p_out - p_in) * x / (nx - 1))).abs().max())
     print(f"pressure-driven Poiseuille on GPU: rel err {err:.1e}, pressure err {perr:.1e}", flush=True)
-    assert err < 1e-11 and perr < 1e-13
+    assert err < 1e-12 and perr < 1e-13
 
 
 @pytest.mark.parametrize("mode", ["layered", "phi", "full"])
@@ -90,7 +90,9 @@ def test_fp64_pressure_driven_cathode_run_and_observables():
     for key in ("ux", "uy"):
         assert float((fg[key].cpu() - fo[key]).abs().max()) / us < 1e-12, key
     for key in ("p", "theta", "c"):
-        assert float((fg[key].cpu() - fo[key]).abs().max() / fo[key].abs().max()) < 1e-11, key
+        e = float((fg[key].cpu() - fo[key]).abs().max() / fo[key].abs().max())
+        print(f"pressure {key}: rel err {e:.2e}", flush=True)
+        assert e < 1e-12, key
     og, oo = gpu.observables(), m.observables(s)
     for key in ("current_density", "heat_rate", "o2_utilisation", "inlet_flux", "T_max", "sum_c", "consumed_c"):
         ref = float(oo[key])
