@@ -324,9 +324,20 @@ lbm_status lbm_batch_init_equilibrium(lbm_batch* b);
 lbm_status lbm_batch_set_schedule(lbm_batch* b, const lbm_schedule* s);
 lbm_status lbm_batch_get_schedule(const lbm_batch* b, lbm_schedule* s);
 /* Time every candidate schedule for trial_steps steps from the current
- * state; keep the fastest, restore the state.  Synchronous. */
+ * state; keep the fastest, restore the state.  Synchronous.  The library
+ * keeps no cache of its own: a caller that wants to skip the trials next
+ * time stores *best (the Python binding keeps a JSON file keyed by GPU
+ * architecture, precision and the case lattice sizes) and sets it with
+ * lbm_batch_set_schedule.  A persistent candidate whose grid barrier times
+ * out (lbm_batch_step) is skipped. */
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_schedule* best, double* best_ms_per_step);
-/* Advance every case nsteps steps.  Async. */
+/* Advance every case nsteps steps.  Async.  With a persistent schedule the
+ * grid is sized so that every workgroup is resident (the smaller of the
+ * runtime's occupancy figure and the kernel's register budget); its
+ * barrier waits at most 4 s, so a grid that is not co-resident ends the
+ * launch instead of hanging it, and the next synchronising call returns
+ * LBM_ERR_DEVICE (the state is then invalid until
+ * lbm_batch_init_equilibrium). */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
 /* out[ncases]: observables of every case (as lbm_observables).  Synchronous. */
 lbm_status lbm_batch_observables(lbm_batch* b, lbm_obs* out);

@@ -5,10 +5,10 @@
 //   k_batch_step        one workgroup per tile, one launch per time step;
 //   k_batch_persistent  one cooperative launch for many steps: each
 //                       workgroup owns a contiguous chunk of tiles and the
-//                       grid synchronizes between steps.
+//                       grid synchronizes between steps (a barrier whose
+//                       wait is bounded: a grid that is not co-resident
+//                       fails the launch instead of hanging it).
 #pragma once
-
-#include <hip/hip_cooperative_groups.h>
 
 #include "lbm_kernels2d.hpp"
 
@@ -82,25 +82,78 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(R* __restrict__ pool, con
   batch_tile<R, ONE, UNIFORM>(pool, cases, tiles[t], parity, tx, ty);
 }
 
-// The persistent form keeps the cell loop for every tile shape: its grid is
-// sized from the occupancy query, and the one-cell instance sits at the
-// 64-VGPR boundary where the compiler reports 7 waves per SIMD; a grid
-// sized for 8 would leave workgroups that never start and a grid barrier
-// that never completes.
+// Waves per SIMD the persistent kernel is compiled for (at least): the
+// compiler keeps both its vector and its scalar registers within what that
+// many waves can hold, so a grid of that many 256-lane workgroups per CU
+// (four waves, one per SIMD) is co-resident.  The scalar registers matter:
+// at 106 of them (112 allocated of 800 per SIMD) only 7 waves fit, however
+// few vector registers the kernel uses.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_batch_persistent(R* __restrict__ pool,
-                                                             const BatchCase<R>* __restrict__ cases,
-                                                             const Tile* __restrict__ tiles, int ntiles,
-                                                             int nsteps, int parity0, int tx, int ty) {
-  namespace cg = cooperative_groups;
-  cg::grid_group grid = cg::this_grid();
+struct PersistentWaves;
+template <>
+struct PersistentWaves<float> {
+  static constexpr int value = 6;
+};
+template <>
+struct PersistentWaves<double> {
+  static constexpr int value = 2;
+};
+
+// Grid-wide barrier of the persistent kernel.  `count` counts arrivals since
+// the launch (cleared before it); step s waits for (s + 1) gridDim.x of
+// them.  A wait longer than `limit` wall-clock ticks (seconds, where a step
+// takes micro- to milliseconds) means workgroups that never started: the
+// waiter sets `failed`, and every workgroup that sees it leaves the kernel.
+struct GridBarrier {
+  unsigned int* count;
+  int* failed;
+  long long limit;
+};
+
+__device__ __forceinline__ bool grid_barrier(const GridBarrier& gb, unsigned int target) {
+  __shared__ int ok;
+  __threadfence();  // this thread's stores of the step, visible at device scope
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(gb.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    int good = 1;
+    while (__hip_atomic_load(gb.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(gb.failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          wall_clock64() - t0 > gb.limit) {
+        __hip_atomic_store(gb.failed, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+    }
+    ok = good;
+  }
+  __syncthreads();
+  __threadfence();  // the other workgroups' stores, seen by this one's loads
+  return ok != 0;
+}
+
+__global__ void k_clear_barrier(unsigned int* count, int* failed, int clear_failed) {
+  if (threadIdx.x == 0) {
+    *count = 0u;
+    if (clear_failed) *failed = 0;
+  }
+}
+
+// The persistent form keeps the cell loop for every tile shape.
+template <typename R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PersistentWaves<R>::value)))
+void k_batch_persistent(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
+                        const Tile* __restrict__ tiles, int ntiles, int nsteps, int parity0, int tx, int ty,
+                        GridBarrier gb) {
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int t0 = int((int64_t(lb) * ntiles) / gridDim.x);
   const int t1 = int((int64_t(lb + 1) * ntiles) / gridDim.x);
   for (int s = 0; s < nsteps; ++s) {
     const int parity = (parity0 + s) & 1;
     for (int t = t0; t < t1; ++t) batch_tile<R, false>(pool, cases, tiles[t], parity, tx, ty);
-    grid.sync();
+    if (!grid_barrier(gb, unsigned(s + 1) * unsigned(gridDim.x))) return;
   }
 }
 

@@ -1,6 +1,8 @@
 // Host side of the batched sweep (lbm_batch_* in include/lbm_pem.h).
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -22,6 +24,7 @@ struct BatchLayout {
   std::vector<int64_t> state_off[2];  // element offsets per case
   int64_t pool_elems = 0;
   size_t off_pool = 0, off_backup = 0, off_cases = 0, off_tiles = 0, off_partial = 0, off_prof = 0, off_out = 0;
+  size_t off_sync = 0;  // the persistent kernel's barrier: arrival count and failure flag
   size_t total = 0;
   int max_tiles = 0;
   int max_obs_blocks = 0;
@@ -70,6 +73,8 @@ BatchLayout make_batch_layout(const lbm_geometry* g, int n) {
   o += align_up(size_t(3) * L.max_nx * sizeof(double));
   L.off_out = o;
   o += align_up(16 * sizeof(double));
+  L.off_sync = o;
+  o += align_up(2 * sizeof(int));
   L.total = o;
   return L;
 }
@@ -91,6 +96,7 @@ struct lbm_batch {
   lbm_schedule sched{256, 1, 0, 0};
   int ntiles = 0;
   int persistent_grid = 0;
+  long long barrier_limit = 0;  // wall-clock ticks a persistent barrier waits at most
   int64_t cells = 0;  // lattice nodes over all cases
   std::string err;
 
@@ -102,6 +108,8 @@ struct lbm_batch {
   double* partial() { return reinterpret_cast<double*>(ws + L.off_partial); }
   double* prof() { return reinterpret_cast<double*>(ws + L.off_prof); }
   double* out() { return reinterpret_cast<double*>(ws + L.off_out); }
+  unsigned int* barrier_count() { return reinterpret_cast<unsigned int*>(ws + L.off_sync); }
+  int* barrier_failed() { return reinterpret_cast<int*>(ws + L.off_sync + sizeof(int)); }
 };
 
 namespace {
@@ -148,20 +156,51 @@ lbm_status build_tiles(lbm_batch* b, int tx, int ty) {
 }
 
 // Workgroups of the persistent kernel's grid: every one must be resident at
-// once for its grid barrier.  One workgroup per CU below the occupancy
-// query's figure, so that a query that misses a limit (the compiler's
-// SGPR-bound occupancy can sit one below the VGPR-bound one) still leaves
-// the whole grid resident; the kernel's loop spreads the tiles over it.
+// once for its grid barrier.  Per CU that is the smaller of the runtime's
+// occupancy query and the derivation from the kernel's resources: a
+// 256-lane workgroup is four waves, one per SIMD, so workgroups per CU =
+// waves per SIMD; the vector registers (hipFuncGetAttributes, allocated in
+// groups of 8 from 512 per SIMD) allow 512 / alloc waves, the scalar ones
+// are within what the PersistentWaves the kernel is compiled for allow
+// (the compiler's guarantee), and the kernel uses no LDS beyond a word.
+// With LBM_LOG set, both figures go to stderr.
 template <typename R>
-int cooperative_grid(lbm_batch* b) {
-  int dev = 0, ncu = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_batch_persistent<R>),
-                                                   kBlock, 0) != hipSuccess)
-    return 0;
-  const int co = ncu * std::max(1, per_cu - 1);
-  return std::min(co, b->ntiles);
+lbm_status persistent_grid(lbm_batch* b, int* grid_out) {
+  const void* fn = reinterpret_cast<const void*>(&k_batch_persistent<R>);
+  int dev = 0, ncu = 0, query = 0;
+  hipFuncAttributes a{};
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&query, fn, kBlock, 0) != hipSuccess ||
+      hipFuncGetAttributes(&a, fn) != hipSuccess)
+    return bfail(b, LBM_ERR_DEVICE, "occupancy of the persistent kernel unavailable");
+  const int vgpr_alloc = std::max(8, (a.numRegs + 7) / 8 * 8);
+  const int by_vgpr = std::min(8, 512 / vgpr_alloc);
+  const int derived = std::min(by_vgpr, PersistentWaves<R>::value);
+  const int per_cu = std::min(query, derived);
+  if (std::getenv("LBM_LOG"))
+    std::fprintf(stderr,
+                 "lbm: persistent kernel (%s): occupancy query %d workgroups/CU; derived %d (VGPRs %d -> %d waves, "
+                 "compiled for >= %d); grid %d CUs x %d\n",
+                 sizeof(R) == 8 ? "fp64" : "fp32", query, derived, a.numRegs, by_vgpr, PersistentWaves<R>::value,
+                 ncu, per_cu);
+  if (per_cu < 1) return bfail(b, LBM_ERR_DEVICE, "no co-resident grid for the persistent kernel");
+  *grid_out = std::min(ncu * per_cu, b->ntiles);
+  return LBM_OK;
+}
+
+// The persistent kernel's barrier gave up (workgroups that never started):
+// sticky until lbm_batch_init_equilibrium, reported by every synchronising
+// call.
+lbm_status barrier_status(lbm_batch* b) {
+  int failed = 0;
+  if (hipMemcpyAsync(&failed, b->barrier_failed(), sizeof(int), hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return bfail(b, LBM_ERR_DEVICE, "reading the persistent barrier flag failed");
+  if (failed)
+    return bfail(b, LBM_ERR_DEVICE,
+                 "persistent launch: the grid barrier timed out (workgroups not co-resident); the state is invalid");
+  return LBM_OK;
 }
 
 template <typename R>
@@ -173,10 +212,13 @@ lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
   if (b->sched.persistent) {
     int grid = b->persistent_grid;
     int64_t left = nsteps;
+    GridBarrier gb{b->barrier_count(), b->barrier_failed(), b->barrier_limit};
     while (left > 0) {
-      int chunk = int(std::min<int64_t>(left, 1 << 20));
+      int chunk = int(std::min<int64_t>(left, 1 << 20));  // (chunk) x (grid) arrivals fit the 32-bit count
       int ntiles = b->ntiles, par = b->parity;
-      void* args[] = {&pool, &cases, &tiles, &ntiles, &chunk, &par, const_cast<int*>(&tx), const_cast<int*>(&ty)};
+      hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(64), 0, b->stream, gb.count, gb.failed, 0);
+      void* args[] = {&pool, &cases, &tiles, &ntiles, &chunk, &par, const_cast<int*>(&tx), const_cast<int*>(&ty),
+                      &gb};
       const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch_persistent<R>),
                                                       dim3(grid), dim3(kBlock), args, 0, b->stream);
       if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
@@ -217,10 +259,7 @@ lbm_status set_schedule_t(lbm_batch* b, const lbm_schedule& s) {
     return bfail(b, LBM_ERR_INVALID_ARG, "tile shape out of range");
   b->sched = s;
   if (lbm_status st = build_tiles(b, s.tile_x, s.tile_y); st != LBM_OK) return st;
-  if (s.persistent) {
-    b->persistent_grid = cooperative_grid<R>(b);
-    if (b->persistent_grid < 1) return bfail(b, LBM_ERR_DEVICE, "no co-resident grid for the persistent kernel");
-  }
+  if (s.persistent) return persistent_grid<R>(b, &b->persistent_grid);
   return LBM_OK;
 }
 
@@ -231,6 +270,7 @@ lbm_status init_t(lbm_batch* b) {
     hipLaunchKernelGGL((k_init<R, MAT_LAYERED>), grid, dim3(kBlock), 0, b->stream,
                        b->pool<R>() + b->L.state_off[0][i], nullptr, nullptr, nullptr, bconsts<R>(b, i));
   }
+  hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(64), 0, b->stream, b->barrier_count(), b->barrier_failed(), 1);
   b->parity = 0;
   b->step = 0;
   const hipError_t e = hipGetLastError();
@@ -239,6 +279,7 @@ lbm_status init_t(lbm_batch* b) {
 
 template <typename R>
 lbm_status observables_t(lbm_batch* b, lbm_obs* out) {
+  if (lbm_status st = barrier_status(b); st != LBM_OK) return st;
   for (int i = 0; i < b->n; ++i) {
     const lbm_geometry& g = b->g[i];
     const lbm_params& p = b->p[i];
@@ -318,6 +359,12 @@ lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double*
         st = bfail(b, LBM_ERR_DEVICE, "autotune trial failed");
         break;
       }
+      if (persistent && barrier_status(b) != LBM_OK) {  // not co-resident: the schedule is unusable
+        hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(64), 0, b->stream, b->barrier_count(),
+                           b->barrier_failed(), 1);
+        b->err.clear();
+        continue;
+      }
       float ms = 0;
       (void)hipEventElapsedTime(&ms, e0, e1);
       const double per = double(ms) / trial_steps;
@@ -374,6 +421,11 @@ lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t 
   b->stream = static_cast<hipStream_t>(hip_stream);
   for (int i = 0; i < ncases; ++i) b->cells += int64_t(g[i].nx) * g[i].ny;
   *out = b;
+  int dev = 0, wall_khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+    return bfail(b, LBM_ERR_DEVICE, "device wall-clock rate unavailable");
+  b->barrier_limit = 4000LL * wall_khz;  // 4 s
   for (int i = 0; i < ncases; ++i) {
     std::string msg;
     if (lbm_status st = derive(g[i], p[i], b->d[i], msg); st != LBM_OK)
@@ -391,6 +443,7 @@ lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t 
   }
   const bool dbl = g[0].precision == 64;
   if (lbm_status st = dbl ? upload_cases<double>(b) : upload_cases<float>(b); st != LBM_OK) return st;
+  hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(64), 0, b->stream, b->barrier_count(), b->barrier_failed(), 1);
   lbm_schedule s{256, 1, 0, 0};
   return dbl ? set_schedule_t<double>(b, s) : set_schedule_t<float>(b, s);
 }
@@ -445,7 +498,8 @@ int64_t lbm_batch_step_count(const lbm_batch* b) { return b ? b->step : -1; }
 lbm_status lbm_batch_synchronize(lbm_batch* b) {
   if (!b) return LBM_ERR_INVALID_ARG;
   const hipError_t e = hipStreamSynchronize(b->stream);
-  return e == hipSuccess ? LBM_OK : bfail(b, LBM_ERR_DEVICE, std::string("synchronize: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("synchronize: ") + hipGetErrorString(e));
+  return barrier_status(b);
 }
 
 void lbm_batch_destroy(lbm_batch* b) { delete b; }
