@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 import numpy as np
 import torch
@@ -346,20 +347,39 @@ class Cathode:
         return J.value
 
     def backward(self, dJ: float = 1.0) -> dict:
-        """dJ times the gradient of J with respect to the per-cell 1/K,
-        porosity and D_eff (and K: -(1/K)^2 dJ/d(1/K)), as [ny, nx] tensors."""
+        """dJ times the gradient of J with respect to the per-cell 1/K
+        (``inv_k``), porosity (``phi``) and D_eff (``d_eff``), and with
+        respect to the permeability K itself (``K``: -(1/K)^2 dJ/d(1/K), zero
+        in the clear channel where 1/K = 0), as [ny, nx] tensors."""
         out = {k: torch.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
                for k in ("inv_k", "phi", "d_eff")}
         self._check(self.lib.lbm_backward(self.ctx, float(dJ), _ptr(out["inv_k"]), _ptr(out["phi"]),
                                           _ptr(out["d_eff"])))
+        out["K"] = grad_wrt_permeability(self.material()["inv_k"], out["inv_k"])
         return out
 
+    def close(self):
+        """Wait for the stream and destroy the library context (idempotent).
+        Call it, or use the object as a context manager, before the process
+        ends: at interpreter shutdown the HIP runtime may already be gone, so
+        the destructor then leaves the context alone."""
+        h = getattr(self, "ctx", None)
+        if h:
+            self.ctx = None
+            self.lib.lbm_synchronize(h)
+            self.lib.lbm_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
-            if getattr(self, "ctx", None):
-                self.lib.lbm_synchronize(self.ctx)
-                self.lib.lbm_destroy(self.ctx)
-                self.ctx = None
+            self.close()
         except Exception:
             pass
 
@@ -471,18 +491,36 @@ class Cathode3D:
 
     def backward(self, dJ: float = 1.0) -> dict:
         """dJ times the gradient of J with respect to the per-cell 1/K,
-        porosity and D_eff, as [nz, ny, nx] tensors."""
+        porosity and D_eff, and K (-(1/K)^2 dJ/d(1/K)), as [nz, ny, nx]
+        tensors."""
         out = {k: torch.empty(self.shape, dtype=self.dtype, device=self.device) for k in ("inv_k", "phi", "d_eff")}
         self._check(self.lib.lbm3d_backward(self.ctx, float(dJ), _ptr(out["inv_k"]), _ptr(out["phi"]),
                                             _ptr(out["d_eff"])))
+        out["K"] = grad_wrt_permeability(self.material()["inv_k"], out["inv_k"])
         return out
 
+    def close(self):
+        """Wait for the stream and destroy the library context (idempotent).
+        Call it, or use the object as a context manager, before the process
+        ends: at interpreter shutdown the HIP runtime may already be gone, so
+        the destructor then leaves the context alone."""
+        h = getattr(self, "ctx", None)
+        if h:
+            self.ctx = None
+            self.lib.lbm3d_synchronize(h)
+            self.lib.lbm3d_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
-            if getattr(self, "ctx", None):
-                self.lib.lbm3d_synchronize(self.ctx)
-                self.lib.lbm3d_destroy(self.ctx)
-                self.ctx = None
+            self.close()
         except Exception:
             pass
 
@@ -591,14 +629,37 @@ class BatchedSweep:
         self._check(self.lib.lbm_batch_get_populations(self.h, int(i), _ptr(t)))
         return t
 
+    def close(self):
+        """Wait for the stream and destroy the library context (idempotent).
+        Call it, or use the object as a context manager, before the process
+        ends: at interpreter shutdown the HIP runtime may already be gone, so
+        the destructor then leaves the context alone."""
+        h = getattr(self, "h", None)
+        if h:
+            self.h = None
+            self.lib.lbm_batch_synchronize(h)
+            self.lib.lbm_batch_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
-            if getattr(self, "h", None):
-                self.lib.lbm_batch_synchronize(self.h)
-                self.lib.lbm_batch_destroy(self.h)
-                self.h = None
+            self.close()
         except Exception:
             pass
+
+
+def grad_wrt_permeability(inv_k: torch.Tensor, grad_inv_k: torch.Tensor) -> torch.Tensor:
+    """dJ/dK from dJ/d(1/K): the chain rule through K = 1/(1/K),
+    dJ/dK = -(1/K)^2 dJ/d(1/K); zero where 1/K = 0 (the clear channel,
+    K infinite)."""
+    return -(inv_k * inv_k) * grad_inv_k
 
 
 class CurrentDensity(torch.autograd.Function):
@@ -610,6 +671,11 @@ class CurrentDensity(torch.autograd.Function):
     (checkpointed recomputation every ``every`` steps).
 
         J = CurrentDensity.apply(inv_k, phi, d_eff, workload, nsteps, every)
+
+    The gradients are those of 1/K, porosity and D_eff.  For the gradient
+    with respect to the permeability K, pass ``inv_k = 1.0 / K`` computed in
+    torch (autograd applies dJ/dK = -(1/K)^2 dJ/d(1/K)), or convert with
+    ``grad_wrt_permeability``.
     """
 
     @staticmethod
