@@ -219,6 +219,20 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 lbm_status lbm_observables(lbm_ctx* ctx, lbm_obs* out, double* prof_i, double* prof_c,
                            double* prof_T);
 
+/* For callers that cannot allocate device memory or have it allocated for
+ * them (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): lbm_observables with the reduction's intermediate
+ * results (per-workgroup partial sums, reduced values, CL profiles) in a
+ * static device array of the library, 4 MiB per GPU, held until the process
+ * ends, instead of the context's workspace.  Same kernels, same results (bit
+ * for bit).  Allocates nothing.  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (other threads, other contexts) race.
+ * Synchronous.  LBM_ERR_INVALID_ARG if the lattice needs more than 4 MiB of
+ * it: (ceil(nx/256) ny + 1) 9 + 3 nx doubles, i.e. up to about 3600 rows
+ * at nx = 4096. */
+lbm_status lbm_observables_noalloc(lbm_ctx* ctx, lbm_obs* out, double* prof_i, double* prof_c,
+                                   double* prof_T);
+
 /* Macroscopic fields of the current state into caller device arrays
  * [ny][nx] (context precision): u_x, u_y (lattice), p (lattice, Section 2.1
  * pressure relation), T (K), theta = T - T_in (K, the stored variable, at

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -203,25 +204,35 @@ void launch_init(lbm_ctx* c) {
   }
 }
 
+// Where the observable reduction keeps its intermediate results: the
+// per-workgroup partial sums (nblocks_obs x kObsQ), the reduced values
+// (kObsQ) and the three CL profiles (3 nx).  Every element is written
+// before it is read, so the buffers need no clearing.
+struct ObsBuffers {
+  double* partial;
+  double* out;
+  double* prof;
+};
+
 template <typename R, int MAT>
-void launch_obs_mat(lbm_ctx* c, double i_scale) {
+void launch_obs_mat(lbm_ctx* c, double i_scale, const ObsBuffers& b) {
   const MatPtrs<R> m = mat_ptrs<R>(c);
   const R* src = static_cast<const R*>(c->state(c->cur));
   const dim3 grid((c->g.nx + kBlock - 1) / kBlock, c->g.ny);
   hipLaunchKernelGGL((k_obs_cells<R, MAT>), grid, dim3(kBlock), 0, c->stream, src, m.phi, m.invk, m.d,
-                     consts<R>(c), c->partial());
-  hipLaunchKernelGGL(k_obs_final<kObsQ>, dim3(kObsQ), dim3(kBlock), 0, c->stream, c->partial(), c->L.nblocks_obs, c->out());
+                     consts<R>(c), b.partial);
+  hipLaunchKernelGGL(k_obs_final<kObsQ>, dim3(kObsQ), dim3(kBlock), 0, c->stream, b.partial, c->L.nblocks_obs, b.out);
   const dim3 pgrid((c->g.nx + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_obs_profiles<R, MAT>), pgrid, dim3(kBlock), 0, c->stream, src, m.phi, m.invk, m.d,
-                     consts<R>(c), i_scale, c->prof());
+                     consts<R>(c), i_scale, b.prof);
 }
 
 template <typename R>
-void launch_obs(lbm_ctx* c, double i_scale) {
+void launch_obs(lbm_ctx* c, double i_scale, const ObsBuffers& b) {
   switch (c->mat) {
-    case MAT_LAYERED: launch_obs_mat<R, MAT_LAYERED>(c, i_scale); break;
-    case MAT_PHI: launch_obs_mat<R, MAT_PHI>(c, i_scale); break;
-    default: launch_obs_mat<R, MAT_FULL>(c, i_scale); break;
+    case MAT_LAYERED: launch_obs_mat<R, MAT_LAYERED>(c, i_scale, b); break;
+    case MAT_PHI: launch_obs_mat<R, MAT_PHI>(c, i_scale, b); break;
+    default: launch_obs_mat<R, MAT_FULL>(c, i_scale, b); break;
   }
 }
 
@@ -308,19 +319,21 @@ lbm_status set_params_t(lbm_ctx* c, const lbm_params* p, const void* phi, const 
 }
 
 template <typename R>
-lbm_status observables_t(lbm_ctx* c, lbm_obs* o, double* pi, double* pc, double* pT) {
+lbm_status observables_t(lbm_ctx* c, lbm_obs* o, double* pi, double* pc, double* pT, const ObsBuffers& b) {
   const lbm_params& p = c->p;
   const double four_fc = 4.0 * p.faraday * p.C_ref;
   const double i_scale = four_fc / c->d.dt * c->d.dx;  // i(x) = sum_CL (4 F C_ref s_c / dt) dx
-  launch_obs<R>(c, i_scale);
+  launch_obs<R>(c, i_scale, b);
   if (lbm_status s = check_launch(c, "observables"); s != LBM_OK) return s;
   double h[kObsQ];
-  if (hipMemcpyAsync(h, c->out(), sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+  if (hipMemcpyAsync(h, b.out, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
     return fail(c, LBM_ERR_DEVICE, "observable copy failed");
   const size_t nx = size_t(c->g.nx);
-  std::vector<double> prof(3 * nx);
-  if (hipMemcpyAsync(prof.data(), c->prof(), 3 * nx * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
-    return fail(c, LBM_ERR_DEVICE, "profile copy failed");
+  double* const dst[3] = {pi, pc, pT};
+  for (int i = 0; i < 3; ++i)
+    if (dst[i] && hipMemcpyAsync(dst[i], b.prof + i * nx, nx * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream) != hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "profile copy failed");
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "observables sync failed");
   const double ncell = double(c->g.nx) * c->g.ny;
   lbm_obs r{};
@@ -339,13 +352,53 @@ lbm_status observables_t(lbm_ctx* c, lbm_obs* o, double* pi, double* pc, double*
   r.consumed_c = sum_sc;
   r.heat_added = h[4];
   if (o) *o = r;
-  if (pi) std::memcpy(pi, prof.data(), nx * sizeof(double));
-  if (pc) std::memcpy(pc, prof.data() + nx, nx * sizeof(double));
-  if (pT) std::memcpy(pT, prof.data() + 2 * nx, nx * sizeof(double));
   const double vals[] = {r.current_density, r.heat_rate, r.T_max, r.sum_f, r.sum_theta, r.sum_c, r.heat_added};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(c, LBM_ERR_NONFINITE, "non-finite observable");
   if (h[7] > 0) return fail(c, LBM_ERR_NONFINITE, "non-finite populations");
+  return LBM_OK;
+}
+
+// The observable reduction's scratch for lbm_observables_noalloc, for callers
+// that cannot allocate device memory: the per-workgroup partial sums, the
+// reduced values and the CL profiles (ObsBuffers) of one call.  Each GPU
+// holds its own copy until the process ends; every call on a GPU reuses it,
+// so calls that overlap on one GPU race.
+constexpr size_t kNoAllocScratchDoubles = size_t(1) << 19;  // 4 MiB
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_addr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+
+// Scratch doubles one lbm_observables_noalloc call needs (ObsBuffers).
+size_t noalloc_scratch_doubles(const lbm_ctx* c) {
+  return size_t(c->L.nblocks_obs) * kObsQ + kObsQ + 3 * size_t(c->g.nx);
+}
+
+// Device address of `scratch` on the context's GPU, resolved once per device
+// with that device current (in host code the array's name is not a device
+// address).
+lbm_status scratch_for_device(lbm_ctx* c, double** out) {
+  if (c->device < 0 || c->device >= kMaxDevices) return fail(c, LBM_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[c->device]) {
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "hipGetDevice failed");
+    if (prev != c->device && hipSetDevice(c->device) != hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "hipSetDevice failed");
+    void* addr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (prev != c->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !addr)
+      return fail(c, LBM_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    g_scratch_addr[c->device] = static_cast<double*>(addr);
+  }
+  *out = g_scratch_addr[c->device];
   return LBM_OK;
 }
 
@@ -437,7 +490,25 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
 lbm_status lbm_observables(lbm_ctx* c, lbm_obs* out, double* pi, double* pc, double* pT) {
   if (!c) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
-  return c->g.precision == 64 ? observables_t<double>(c, out, pi, pc, pT) : observables_t<float>(c, out, pi, pc, pT);
+  const ObsBuffers b{c->partial(), c->out(), c->prof()};
+  return c->g.precision == 64 ? observables_t<double>(c, out, pi, pc, pT, b)
+                              : observables_t<float>(c, out, pi, pc, pT, b);
+}
+
+lbm_status lbm_observables_noalloc(lbm_ctx* c, lbm_obs* out, double* pi, double* pc, double* pT) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
+  const size_t need = noalloc_scratch_doubles(c);
+  if (need > kNoAllocScratchDoubles)
+    return fail(c, LBM_ERR_INVALID_ARG,
+                "lattice too large for the static observable scratch: needs " + std::to_string(need * 8) +
+                    " bytes, the maximum is " + std::to_string(kNoAllocScratchDoubles * 8));
+  double* base = nullptr;
+  if (lbm_status s = scratch_for_device(c, &base); s != LBM_OK) return s;
+  const size_t n_part = size_t(c->L.nblocks_obs) * kObsQ;
+  const ObsBuffers b{base, base + n_part, base + n_part + kObsQ};
+  return c->g.precision == 64 ? observables_t<double>(c, out, pi, pc, pT, b)
+                              : observables_t<float>(c, out, pi, pc, pT, b);
 }
 
 lbm_status lbm_get_fields(lbm_ctx* c, void* ux, void* uy, void* p, void* T, void* th, void* cc) {

@@ -74,7 +74,7 @@ class Schedule(ctypes.Structure):
 _lib = None
 
 EXPORTED = ["lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_set_params", "lbm_init_equilibrium",
-            "lbm_step", "lbm_observables", "lbm_get_fields", "lbm_get_material", "lbm_get_populations",
+            "lbm_step", "lbm_observables", "lbm_observables_noalloc", "lbm_get_fields", "lbm_get_material", "lbm_get_populations",
             "lbm_set_populations",
             "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count", "lbm_synchronize",
             "lbm_destroy", "lbm_status_string", "lbm_last_error",
@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_init_equilibrium": (ctypes.c_int, [vp]),
         "lbm_step": (ctypes.c_int, [vp, i64]),
         "lbm_observables": (ctypes.c_int, [vp, P(Obs), vp, vp, vp]),
+        "lbm_observables_noalloc": (ctypes.c_int, [vp, P(Obs), vp, vp, vp]),
         "lbm_get_fields": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
         "lbm_get_material": (ctypes.c_int, [vp, vp, vp, vp]),
@@ -287,13 +288,16 @@ class Cathode:
     def synchronize(self):
         self._check(self.lib.lbm_synchronize(self.ctx))
 
-    def observables(self) -> dict:
+    def observables(self, noalloc: bool = False) -> dict:
+        """Observables of the current state (lbm_observables, or with
+        ``noalloc`` lbm_observables_noalloc)."""
         o = Obs()
         pi = np.zeros(self.nx)
         pc = np.zeros(self.nx)
         pT = np.zeros(self.nx)
-        st = self.lib.lbm_observables(self.ctx, ctypes.byref(o), pi.ctypes.data_as(ctypes.c_void_p),
-                                      pc.ctypes.data_as(ctypes.c_void_p), pT.ctypes.data_as(ctypes.c_void_p))
+        fn = self.lib.lbm_observables_noalloc if noalloc else self.lib.lbm_observables
+        st = fn(self.ctx, ctypes.byref(o), pi.ctypes.data_as(ctypes.c_void_p), pc.ctypes.data_as(ctypes.c_void_p),
+                pT.ctypes.data_as(ctypes.c_void_p))
         self._check(st)
         d = {name: getattr(o, name) for name, _ in Obs._fields_}
         d.update(i_profile=pi, c_profile=pc, T_profile=pT)
