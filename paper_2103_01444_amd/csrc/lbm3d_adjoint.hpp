@@ -30,28 +30,32 @@ template <typename R>
 __device__ __forceinline__ void material_adj(const Consts3<R>& k, const Mat3<R>& m, const MatAdj3<R>& a, R& g_phi,
                                              R& g_invk, R& g_d) {
   const R phi = m.phi;
+  const R iphi = R(1) / phi, irc = R(1) / m.rhocp;
   R lphi = a.phi, linvk = a.invk, lsqk = a.sqk, lfphi = a.fphi;
   lphi += a.l1 * m.fphi * m.sqk * R(0.5);  // l1 = phi fphi sqk / 2
   lfphi += a.l1 * phi * m.sqk * R(0.5);
   lsqk += a.l1 * phi * m.fphi * R(0.5);
   lphi += a.l0 * k.nu * m.invk * R(0.25);  // l0 = 1/2 + phi nu invk / 4
   linvk += a.l0 * phi * k.nu * R(0.25);
-  lphi += lfphi * R(-1.5) * m.fphi / phi;  // fphi = 0.143 phi^-1.5
+  lphi += lfphi * R(-1.5) * m.fphi * iphi;  // fphi = 0.143 phi^-1.5
   if (m.sqk > R(0)) linvk += lsqk * R(0.5) / m.sqk;  // 0 at invk = 0
   // aT = sqrt3 alpha, alpha = (k_f phi + k_s (1 - phi)) scale / rhocp (Eq. 19)
-  const R alpha = (k.k_f * phi + k.k_s * (R(1) - phi)) * k.alpha_scale / m.rhocp;
+  const R alpha = (k.k_f * phi + k.k_s * (R(1) - phi)) * k.alpha_scale * irc;
   const R drc = k.rhocp_f - k.rhocp_s;
   const R lalpha = a.aT * R(kSqrt3);
-  lphi += lalpha * ((k.k_f - k.k_s) * k.alpha_scale / m.rhocp - alpha * drc / m.rhocp);
+  lphi += lalpha * ((k.k_f - k.k_s) * k.alpha_scale - alpha * drc) * irc;
   lphi += a.rhocp * drc;
   g_phi += lphi;
   g_invk += linvk;
   g_d += a.aC * R(kSqrt3);  // aC = sqrt3 D
 }
 
+// Forward intermediates of the flow macros, with the reciprocals the
+// adjoint divides by (each taken once per node).
 template <typename R>
 struct MacroTape3 {
   R vx, vy, vz, vm, r, den, ux, uy, uz, um, drag, s, p, Fx, Fy, Fz;
+  R iphi, iden, ir;  // 1 / phi, 1 / den, 1 / r
 };
 
 template <typename R>
@@ -72,9 +76,11 @@ __device__ __forceinline__ MacroTape3<R> flow_macros_tape(const R (&f)[33], cons
   t.vm = sqrt(t.vx * t.vx + t.vy * t.vy + t.vz * t.vz);
   t.r = sqrt(m.l0 * m.l0 + m.l1 * t.vm);
   t.den = m.l0 + t.r;
-  t.ux = t.vx / t.den;
-  t.uy = t.vy / t.den;
-  t.uz = t.vz / t.den;
+  t.iden = R(1) / t.den;
+  t.ir = R(1) / t.r;
+  t.ux = t.vx * t.iden;
+  t.uy = t.vy * t.iden;
+  t.uz = t.vz * t.iden;
   const R u2 = t.ux * t.ux + t.uy * t.uy + t.uz * t.uz;
   t.um = sqrt(u2);
   t.drag = m.phi * (k.nu * m.invk + m.fphi * m.sqk * t.um);
@@ -85,8 +91,8 @@ __device__ __forceinline__ MacroTape3<R> flow_macros_tape(const R (&f)[33], cons
     t.Fx += m.phi * k.ax;
     t.Fy += m.phi * k.ay;
   }
-  const R iphi = R(1) / m.phi;
-  t.p = (t.s - R(0.5) * u2 * iphi) * R(0.5) * iphi;
+  t.iphi = R(1) / m.phi;
+  t.p = (t.s - R(0.5) * u2 * t.iphi) * R(0.5) * t.iphi;
   return t;
 }
 
@@ -95,7 +101,7 @@ __device__ __forceinline__ MacroTape3<R> flow_macros_tape(const R (&f)[33], cons
 template <typename R>
 __device__ __forceinline__ void flow_macros_adj(const MacroTape3<R>& t, const Mat3<R>& m, const Consts3<R>& k, R lux,
                                                 R luy, R luz, R lp, R lFx, R lFy, R lFz, R* lf, MatAdj3<R>& ma) {
-  const R iphi = R(1) / m.phi;
+  const R iphi = t.iphi;
   const R u2 = t.ux * t.ux + t.uy * t.uy + t.uz * t.uz;
   // p = 0.5 s iphi - 0.25 u2 iphi^2
   const R ls = R(0.5) * iphi * lp;
@@ -116,15 +122,17 @@ __device__ __forceinline__ void flow_macros_adj(const MacroTape3<R>& t, const Ma
   luy += R(2) * t.uy * lu2;
   luz += R(2) * t.uz * lu2;
   ma.phi += -iphi * iphi * liphi;
-  R lvx = lux / t.den, lvy = luy / t.den, lvz = luz / t.den;
-  const R lden = -(t.ux * lux + t.uy * luy + t.uz * luz) / t.den;
-  ma.l0 += lden + lden * m.l0 / t.r;
-  ma.l1 += lden * t.vm * R(0.5) / t.r;
-  const R lvm = lden * m.l1 * R(0.5) / t.r;
+  R lvx = lux * t.iden, lvy = luy * t.iden, lvz = luz * t.iden;
+  const R lden = -(t.ux * lux + t.uy * luy + t.uz * luz) * t.iden;
+  const R ldr = lden * t.ir;
+  ma.l0 += lden + ldr * m.l0;
+  ma.l1 += ldr * t.vm * R(0.5);
+  const R lvm = ldr * m.l1 * R(0.5);
   if (t.vm > R(0)) {
-    lvx += lvm * t.vx / t.vm;
-    lvy += lvm * t.vy / t.vm;
-    lvz += lvm * t.vz / t.vm;
+    const R q = lvm / t.vm;
+    lvx += q * t.vx;
+    lvy += q * t.vy;
+    lvz += q * t.vz;
   }
   if (k.flags & F_BODY_FORCE) ma.phi += R(0.5) * (k.ax * lvx + k.ay * lvy);
 #pragma unroll
@@ -241,8 +249,9 @@ __device__ __forceinline__ void collide_adj(const R (&f)[33], const Mat3<R>& mt,
     if (s == 0) ma.aT += law; else ma.aC += law;
   }
   if (cl) {  // src_T = S_T(theta, c, rhocp), src_C = -s_c(theta, c)
-    const R lsc = -lsrc[1] + k.four_f_cref * rx.ehs / mt.rhocp * lsrc[0];
-    ma.rhocp += -rx.S_T / mt.rhocp * lsrc[0];
+    const R irc = R(1) / mt.rhocp;
+    const R lsc = -lsrc[1] + k.four_f_cref * rx.ehs * irc * lsrc[0];
+    ma.rhocp += -rx.S_T * irc * lsrc[0];
     lX[1] += rx.dsc_dc * lsc;
     lX[0] += rx.dsc_dth * lsc;
   }
@@ -255,7 +264,7 @@ __device__ __forceinline__ void collide_adj(const R (&f)[33], const Mat3<R>& mt,
   // ---- flow: two-rate D3Q19 collision with porous forcing ----
   const R sp = k.s_plus, sm = k.s_minus;
   const R hp = R(1) - R(0.5) * sp, hm = R(1) - R(0.5) * sm;
-  const R phi = mt.phi, iphi = R(1) / phi;
+  const R phi = mt.phi, iphi = t.iphi;
   const R u2 = t.ux * t.ux + t.uy * t.uy + t.uz * t.uz;
   const R uF = t.ux * t.Fx + t.uy * t.Fy + t.uz * t.Fz;
   R lp = R(0), lu2 = R(0), luF = R(0), liphi = R(0);

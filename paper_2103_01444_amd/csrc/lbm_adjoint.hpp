@@ -27,6 +27,7 @@ template <typename R>
 __device__ __forceinline__ void material_adj(const Consts<R>& k, const Mat<R>& m, const MatAdj<R>& a, R& g_phi,
                                              R& g_invk, R& g_d) {
   const R phi = m.phi;
+  const R iphi = R(1) / phi, irc = R(1) / m.rhocp;
   R lphi = a.phi, linvk = a.invk, lsqk = a.sqk, lfphi = a.fphi;
   // l1 = phi fphi sqk / 2
   lphi += a.l1 * m.fphi * m.sqk * R(0.5);
@@ -36,25 +37,26 @@ __device__ __forceinline__ void material_adj(const Consts<R>& k, const Mat<R>& m
   lphi += a.l0 * k.nu * m.invk * R(0.25);
   linvk += a.l0 * phi * k.nu * R(0.25);
   // fphi = 0.143 phi^-1.5
-  lphi += lfphi * R(-1.5) * m.fphi / phi;
+  lphi += lfphi * R(-1.5) * m.fphi * iphi;
   // sqk = sqrt(invk); derivative taken as 0 at invk = 0 (clear fluid)
   if (m.sqk > R(0)) linvk += lsqk * R(0.5) / m.sqk;
   // rhocp = phi rhocp_f + (1 - phi) rhocp_s; alpha (Eq. 19) -> bT = 20 sqrt3 alpha - 4
   const R c20s3 = R(34.64101615137754587);
-  const R alpha = (m.bT + R(4)) / c20s3;
+  const R alpha = (m.bT + R(4)) * R(0.028867513459481288225);  // 1 / (20 sqrt 3)
   const R drc = k.rhocp_f - k.rhocp_s;
   const R lalpha = a.bT * c20s3;
-  lphi += lalpha * ((k.k_f - k.k_s) * k.alpha_scale / m.rhocp - alpha * drc / m.rhocp);
+  lphi += lalpha * ((k.k_f - k.k_s) * k.alpha_scale - alpha * drc) * irc;
   lphi += a.rhocp * drc;
   g_phi += lphi;
   g_invk += linvk;
   g_d += a.bC * c20s3;
 }
 
-// Adjoint of meq_shifted(p, ux, uy, phi) given the adjoint lm[1..8] of the moments.
+// Adjoint of meq_shifted(p, ux, uy, phi) given the adjoint lm[1..8] of the
+// moments; iphi = 1 / phi.
 template <typename R>
-__device__ __forceinline__ void meq_adj(R p, R ux, R uy, R phi, const R (&lm)[9], R& lp, R& lux, R& luy, R& lphi) {
-  const R iphi = R(1) / phi;
+__device__ __forceinline__ void meq_adj(R p, R ux, R uy, R phi, R iphi, const R (&lm)[9], R& lp, R& lux, R& luy,
+                                        R& lphi) {
   const R u2 = ux * ux + uy * uy;
   lp += R(6) * phi * lm[1] - R(9) * phi * lm[2];
   lphi += R(6) * p * lm[1] - R(9) * p * lm[2] + (lm[2] - lm[1]) * R(3) * u2 * iphi * iphi -
@@ -64,10 +66,12 @@ __device__ __forceinline__ void meq_adj(R p, R ux, R uy, R phi, const R (&lm)[9]
   luy += a12 * uy + lm[5] - lm[6] - R(2) * uy * iphi * lm[7] + ux * iphi * lm[8];
 }
 
-// Forward intermediates of flow_macros kept for its adjoint.
+// Forward intermediates of flow_macros kept for its adjoint, with the
+// reciprocals the adjoint divides by (each taken once per node).
 template <typename R>
 struct MacroTape {
   R vx, vy, vm, r, den, ux, uy, um, drag, s18, p, Fx, Fy;
+  R iphi, iden, ir;  // 1 / phi, 1 / den, 1 / r
 };
 
 template <typename R>
@@ -82,8 +86,10 @@ __device__ __forceinline__ MacroTape<R> flow_macros_tape(const R (&f)[19], const
   t.vm = dsqrt(t.vx * t.vx + t.vy * t.vy);
   t.r = dsqrt(m.l0 * m.l0 + m.l1 * t.vm);
   t.den = m.l0 + t.r;
-  t.ux = t.vx / t.den;
-  t.uy = t.vy / t.den;
+  t.iden = R(1) / t.den;
+  t.ir = R(1) / t.r;
+  t.ux = t.vx * t.iden;
+  t.uy = t.vy * t.iden;
   const R u2 = t.ux * t.ux + t.uy * t.uy;
   t.um = dsqrt(u2);
   t.drag = m.phi * (k.nu * m.invk + m.fphi * m.sqk * t.um);
@@ -94,8 +100,8 @@ __device__ __forceinline__ MacroTape<R> flow_macros_tape(const R (&f)[19], const
     t.Fy += m.phi * k.ay;
   }
   t.s18 = f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-  const R iphi = R(1) / m.phi;
-  t.p = R(0.6) * iphi * t.s18 - R(0.4) * u2 * iphi * iphi;
+  t.iphi = R(1) / m.phi;
+  t.p = R(0.6) * t.iphi * t.s18 - R(0.4) * u2 * t.iphi * t.iphi;
   return t;
 }
 
@@ -104,7 +110,7 @@ __device__ __forceinline__ MacroTape<R> flow_macros_tape(const R (&f)[19], const
 template <typename R>
 __device__ __forceinline__ void flow_macros_adj(const MacroTape<R>& t, const Mat<R>& m, const Consts<R>& k, R lux,
                                                 R luy, R lp, R lFx, R lFy, R* lf, MatAdj<R>& ma) {
-  const R iphi = R(1) / m.phi;
+  const R iphi = t.iphi;
   const R u2 = t.ux * t.ux + t.uy * t.uy;
   // p = 0.6 iphi s18 - 0.4 u2 iphi^2
   const R ls18 = R(0.6) * iphi * lp;
@@ -121,19 +127,21 @@ __device__ __forceinline__ void flow_macros_adj(const MacroTape<R>& t, const Mat
   ma.fphi += m.phi * m.sqk * t.um * ldrag;
   ma.sqk += m.phi * m.fphi * t.um * ldrag;
   const R lum = m.phi * m.fphi * m.sqk * ldrag;
-  if (t.um > R(0)) lu2 += lum * R(0.5) / t.um;
+  if (t.um > R(0)) lu2 += lum * R(0.5) / t.um;  // one division (vm, um > 0 only in moving cells)
   lux += R(2) * t.ux * lu2;
   luy += R(2) * t.uy * lu2;
   ma.phi += -iphi * iphi * liphi;
   // u = v / den, den = l0 + r, r = sqrt(l0^2 + l1 vm)
-  R lvx = lux / t.den, lvy = luy / t.den;
-  const R lden = -(t.ux * lux + t.uy * luy) / t.den;
-  ma.l0 += lden + lden * m.l0 / t.r;
-  ma.l1 += lden * t.vm * R(0.5) / t.r;
-  const R lvm = lden * m.l1 * R(0.5) / t.r;
+  R lvx = lux * t.iden, lvy = luy * t.iden;
+  const R lden = -(t.ux * lux + t.uy * luy) * t.iden;
+  const R ldr = lden * t.ir;
+  ma.l0 += lden + ldr * m.l0;
+  ma.l1 += ldr * t.vm * R(0.5);
+  const R lvm = ldr * m.l1 * R(0.5);
   if (t.vm > R(0)) {
-    lvx += lvm * t.vx / t.vm;
-    lvy += lvm * t.vy / t.vm;
+    const R q = lvm / t.vm;
+    lvx += q * t.vx;
+    lvy += q * t.vy;
   }
   if (k.flags & F_BODY_FORCE) ma.phi += R(0.5) * (k.ax * lvx + k.ay * lvy);
   // v = sum e f, s18 = sum_{1..8} f
@@ -147,26 +155,36 @@ __device__ __forceinline__ void flow_macros_adj(const MacroTape<R>& t, const Mat
   lf[8] += lvx - lvy + ls18;
 }
 
-// (M^T x)_i = sum_k M[k][i] x_k  (inv_moments9 applied to x scaled by diag(M M^T)).
+// (M^T y)_i = sum_k M[k][i] y_k: the columns of the Eq. 3 matrix (integer
+// coefficients, additions only).
 template <typename R>
-__device__ __forceinline__ void mt_times(const R (&x)[9], R* out) {
-  R s[9];
-  const R d[9] = {R(9), R(36), R(36), R(6), R(12), R(6), R(12), R(4), R(4)};
-#pragma unroll
-  for (int i = 0; i < 9; ++i) s[i] = x[i] * d[i];
-  inv_moments9(s, out);
+__device__ __forceinline__ void mt_times(const R (&y)[9], R* out) {
+  const R b14 = y[0] - y[1] - R(2) * y[2];
+  const R b58 = y[0] + R(2) * y[1] + y[2];
+  out[0] = y[0] - R(4) * y[1] + R(4) * y[2];
+  out[1] = b14 + y[3] - R(2) * y[4] + y[7];
+  out[2] = b14 + y[5] - R(2) * y[6] - y[7];
+  out[3] = b14 - y[3] + R(2) * y[4] + y[7];
+  out[4] = b14 - y[5] + R(2) * y[6] - y[7];
+  out[5] = b58 + y[3] + y[4] + y[5] + y[6] + y[8];
+  out[6] = b58 - y[3] - y[4] + y[5] + y[6] - y[8];
+  out[7] = b58 - y[3] - y[4] - y[5] - y[6] + y[8];
+  out[8] = b58 + y[3] + y[4] - y[5] - y[6] - y[8];
 }
 
-// M^{-T} a = (M a) / diag(M M^T).
+// 1 / diag(M M^T): M^{-T} a = (M a) / diag(M M^T).
 template <typename R>
-__device__ __forceinline__ void minvt_times(const R* a, R (&out)[9]) {
+__device__ __forceinline__ R inv_mmt(int i) {
+  constexpr double d[9] = {1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 6, 1.0 / 12, 1.0 / 6, 1.0 / 12, 0.25, 0.25};
+  return R(d[i]);
+}
+
+template <typename R>
+__device__ __forceinline__ void m_times(const R* a, R (&out)[9]) {
   R f[19];
 #pragma unroll
   for (int i = 0; i < 9; ++i) f[i] = a[i];
   moments9(f, out);
-  const R d[9] = {R(9), R(36), R(36), R(6), R(12), R(6), R(12), R(4), R(4)};
-#pragma unroll
-  for (int i = 0; i < 9; ++i) out[i] /= d[i];
 }
 
 // Adjoint of add_geq(X, ux, uy, b, sgn, g): given lg (adjoint of g) add the
@@ -261,8 +279,9 @@ __device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, 
   if (cl) {
     // src_T = S_T(theta, c, rhocp), src_C = -s_c(theta, c)
     const R lST = lsrc[0], lSC = lsrc[1];
-    const R lsc = -lSC + k.four_f_cref * rx.ehs / mt.rhocp * lST;
-    ma.rhocp += -rx.S_T / mt.rhocp * lST;
+    const R irc = R(1) / mt.rhocp;
+    const R lsc = -lSC + k.four_f_cref * rx.ehs * irc * lST;
+    ma.rhocp += -rx.S_T * irc * lST;
     lX[1] += rx.dsc_dc * lsc;
     lX[0] += rx.dsc_dth * lsc;
   }
@@ -273,19 +292,24 @@ __device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, 
   }
 
   // ---- flow (reverse of the MRT collision with porous forcing) ----
+  // f* = M^-1 m*, m* = (1 - S) M f + S m_eq + (1 - S/2) G, M^-1 = M^T
+  // diag(M M^T)^-1: the adjoint of m* is M la times the constants
+  // 1 / diag(M M^T), and the part that goes back through M f is M^T of
+  // (1 - S) times it (integer coefficients, no division).
   R lms[9];
-  minvt_times(la, lms);  // adjoint of m*
+  m_times(la, lms);
   const R se = k.s_e, sq = k.s_q;
   const R s[9] = {se, se, se, R(0), sq, R(0), sq, se, se};
   R lm[9], lme[9], lG[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
+    lms[i] *= inv_mmt<R>(i);
     lm[i] = (R(1) - s[i]) * lms[i];
     lme[i] = s[i] * lms[i];
     lG[i] = (R(1) - R(0.5) * s[i]) * lms[i];
   }
   lme[0] = R(0);  // the density-moment equilibrium is a constant
-  const R iphi = R(1) / mt.phi;
+  const R iphi = t.iphi;
   const R uF = t.ux * t.Fx + t.uy * t.Fy;
   // G(u, F, phi)
   const R luF = R(6) * iphi * (lG[1] - lG[2]);
@@ -298,7 +322,7 @@ __device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, 
   ma.phi += -iphi * iphi * liphi_G;
   // meq(p, u, phi)
   R lp = R(0);
-  meq_adj(t.p, t.ux, t.uy, mt.phi, lme, lp, lux, luy, ma.phi);
+  meq_adj(t.p, t.ux, t.uy, mt.phi, iphi, lme, lp, lux, luy, ma.phi);
   // m = M f
   R lfm[9];
   mt_times(lm, lfm);
@@ -319,22 +343,25 @@ __device__ __forceinline__ void boundary_adj(const R (&pre_xp)[19], const Mat<R>
 #pragma unroll
   for (int i = 0; i < 19; ++i) mu_xp[i] += mu_b[i];  // identity part (scalars at the outlet: a copy)
   R ldm[9];
-  minvt_times(mu_b, ldm);
+  m_times(mu_b, ldm);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) ldm[i] *= inv_mmt<R>(i);
   ldm[0] = R(0);
+  const R iphi_b = R(1) / mb.phi;
   R lp1 = R(0), lux1 = R(0), luy1 = R(0);
   // + meq(pb, ub; phi_b): inlet pb = p1 (ub fixed); outlet pb = p_out, ub = u1.
   R dumx = R(0), dumy = R(0);
   if (inlet) {
-    meq_adj(t.p, ubx, uby, mb.phi, ldm, lp1, dumx, dumy, mab.phi);
+    meq_adj(t.p, ubx, uby, mb.phi, iphi_b, ldm, lp1, dumx, dumy, mab.phi);
   } else {
     R dp = R(0);
-    meq_adj(k.p_out, t.ux, t.uy, mb.phi, ldm, dp, lux1, luy1, mab.phi);
+    meq_adj(k.p_out, t.ux, t.uy, mb.phi, iphi_b, ldm, dp, lux1, luy1, mab.phi);
   }
   // - meq(p1, u1; phi_xp)
   R nldm[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) nldm[i] = -ldm[i];
-  meq_adj(t.p, t.ux, t.uy, mxp.phi, nldm, lp1, lux1, luy1, maxp.phi);
+  meq_adj(t.p, t.ux, t.uy, mxp.phi, t.iphi, nldm, lp1, lux1, luy1, maxp.phi);
   if (inlet) {
     const R th1 = pre_xp[9] + pre_xp[10] + pre_xp[11] + pre_xp[12] + pre_xp[13];
     const R c1 = pre_xp[14] + pre_xp[15] + pre_xp[16] + pre_xp[17] + pre_xp[18];
