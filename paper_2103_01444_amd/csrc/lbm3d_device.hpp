@@ -127,14 +127,44 @@ __device__ __forceinline__ void pull(const R* __restrict__ src, const Consts3<R>
   }
 }
 
+// Pull of the planes [Q0, Q1) only, into f[0 .. Q1 - Q0) (as pull).  A
+// wavefront whose nodes all lie inside the lattice by one node or more
+// loads through wave-uniform buffer bases (one 32-bit lane offset for all
+// planes: no per-load 64-bit address registers).
+template <typename R, int Q0, int Q1>
+__device__ __forceinline__ void pull_range(const R* __restrict__ src, const Consts3<R>& k, int x, int y, int z,
+                                           R* f) {
+  const int row = k.pitch * k.ny;
+  if (__all(x >= 1 && x <= k.nx - 2 && y >= 1 && y <= k.ny - 2 && z >= 1 && z <= k.nz - 2)) {
+    const uint32_t ob = uint32_t(z * row + y * k.pitch + x) * uint32_t(sizeof(R));
+#pragma unroll
+    for (int q = Q0; q < Q1; ++q)
+      f[q - Q0] = lbm::buffer_load<R, 2>(
+          src + (int64_t(q) * k.plane - int64_t(EZ[q]) * row - int64_t(EY[q]) * k.pitch - EX[q]), ob);
+    return;
+  }
+  const bool px = k.flags & F_PERIODIC_X, py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
+#pragma unroll
+  for (int q = Q0; q < Q1; ++q) {
+    int xs = x - EX[q], ys = y - EY[q], zs = z - EZ[q];
+    if (px) xs = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
+    if (py) ys = ys < 0 ? ys + k.ny : (ys >= k.ny ? ys - k.ny : ys);
+    if (pz) zs = zs < 0 ? zs + k.nz : (zs >= k.nz ? zs - k.nz : zs);
+    const bool in = (unsigned)xs < (unsigned)k.nx && (unsigned)ys < (unsigned)k.ny && (unsigned)zs < (unsigned)k.nz;
+    const int off = in ? (q * k.plane + zs * row + ys * k.pitch + xs) : (OPP[q] * k.plane + z * row + y * k.pitch + x);
+    f[q - Q0] = __builtin_nontemporal_load(src + off);
+  }
+}
+
 template <typename R>
 struct Macro3 {
   R ux, uy, uz, p, Fx, Fy, Fz;
 };
 
 // Eq. 8 velocity, Eq. 7 drag, 3D pressure relation of the porous equilibrium.
-template <typename R>
-__device__ __forceinline__ Macro3<R> flow_macros(const R (&f)[33], const Mat3<R>& m, const Consts3<R>& k) {
+template <typename R, int N>
+__device__ __forceinline__ Macro3<R> flow_macros(const R (&f)[N], const Mat3<R>& m, const Consts3<R>& k) {
+  static_assert(N >= 19, "the 19 flow populations come first");
   R vx = R(0), vy = R(0), vz = R(0), s = R(0);
 #pragma unroll
   for (int q = 1; q < 19; ++q) {
@@ -204,29 +234,49 @@ __device__ __forceinline__ R inlet_velocity(const Consts3<R>& k, int y, int z) {
   return k.u_in_coef * yc * (R(k.ny) - yc) * zc * (R(k.nz_ch) - zc);
 }
 
-// Boundary columns (non-equilibrium extrapolation, as in 2D).
-template <typename R>
-__device__ __forceinline__ void boundary_column(R (&f)[33], const Consts3<R>& k, int y, int z, bool inlet,
-                                                const Mat3<R>& mp, const Mat3<R>& mb) {
+// Boundary columns (non-equilibrium extrapolation, as in 2D), flow part: the
+// 19 flow populations f[0..18] of the column next to the boundary become
+// the boundary node's; returns that column's macroscopic fields (the scalar
+// part of the inlet needs them).
+template <typename R, int N>
+__device__ __forceinline__ Macro3<R> boundary_flow(R (&f)[N], const Consts3<R>& k, int y, int z, bool inlet,
+                                                   const Mat3<R>& mp, const Mat3<R>& mb) {
   const Macro3<R> a = flow_macros(f, mp, k);
   if (inlet) {
     const R ub = inlet_velocity(k, y, z);
     add_feq(a.p, ub, R(0), R(0), mb.phi, R(1), f);
     add_feq(a.p, a.ux, a.uy, a.uz, mp.phi, R(-1), f);
-    R th = R(0), c = R(0);
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      th += f[19 + q];
-      c += f[26 + q];
-    }
-    add_geq(R(0), ub, R(0), R(0), mb.aT, R(1), f + 19);
-    add_geq(th, a.ux, a.uy, a.uz, mp.aT, R(-1), f + 19);
-    add_geq(k.c_in, ub, R(0), R(0), mb.aC, R(1), f + 26);
-    add_geq(c, a.ux, a.uy, a.uz, mp.aC, R(-1), f + 26);
   } else {
     add_feq(R(0), a.ux, a.uy, a.uz, mb.phi, R(1), f);
     add_feq(a.p, a.ux, a.uy, a.uz, mp.phi, R(-1), f);
   }
+  return a;
+}
+
+// Scalar part of the inlet column: g[0..6] temperature rise, g[7..13] O2 of
+// the column next to the inlet; a: that column's macroscopic fields.  (At
+// the outlet the scalars are copies of that column.)
+template <typename R>
+__device__ __forceinline__ void boundary_scalars_inlet(R* g, const Consts3<R>& k, int y, int z, const Macro3<R>& a,
+                                                       const Mat3<R>& mp, const Mat3<R>& mb) {
+  const R ub = inlet_velocity(k, y, z);
+  R th = R(0), c = R(0);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    th += g[q];
+    c += g[7 + q];
+  }
+  add_geq(R(0), ub, R(0), R(0), mb.aT, R(1), g);
+  add_geq(th, a.ux, a.uy, a.uz, mp.aT, R(-1), g);
+  add_geq(k.c_in, ub, R(0), R(0), mb.aC, R(1), g + 7);
+  add_geq(c, a.ux, a.uy, a.uz, mp.aC, R(-1), g + 7);
+}
+
+template <typename R>
+__device__ __forceinline__ void boundary_column(R (&f)[33], const Consts3<R>& k, int y, int z, bool inlet,
+                                                const Mat3<R>& mp, const Mat3<R>& mb) {
+  const Macro3<R> a = boundary_flow(f, k, y, z, inlet, mp, mb);
+  if (inlet) boundary_scalars_inlet(f + 19, k, y, z, a, mp, mb);
 }
 
 template <typename R, int MAT>
@@ -252,11 +302,10 @@ __device__ __forceinline__ Mat3<R> pre_collision(const R* __restrict__ src, cons
 
 using lbm::reaction;  // the CL reaction of Eqs. 12-17 (shared with 2D)
 
-// Two-rate collision of every population of a node (flow with Guo's porous
-// forcing; scalars with the CL source injected with the rest weights).
+// Two-rate collision of the 19 flow populations with Guo's porous forcing;
+// a: the node's macroscopic fields.
 template <typename R>
-__device__ __forceinline__ void collide(R (&f)[33], const Mat3<R>& mt, const Consts3<R>& k, bool cl) {
-  const Macro3<R> a = flow_macros(f, mt, k);
+__device__ __forceinline__ void collide_flow(R* f, const Macro3<R>& a, const Mat3<R>& mt, const Consts3<R>& k) {
   const R iphi = R(1) / mt.phi;
   const R u2 = a.ux * a.ux + a.uy * a.uy + a.uz * a.uz;
   const R uF = a.ux * a.Fx + a.uy * a.Fy + a.uz * a.Fz;
@@ -283,12 +332,20 @@ __device__ __forceinline__ void collide(R (&f)[33], const Mat3<R>& mt, const Con
     f[i] = np + nm;
     f[o] = np - nm;
   }
+}
+
+// Two-rate collisions of the scalar lattices g[0..6] (temperature rise) and
+// g[7..13] (O2) advected by (ux, uy, uz), with the CL source injected with
+// the rest weights.
+template <typename R>
+__device__ __forceinline__ void collide_scalars(R* gs, R ux, R uy, R uz, const Mat3<R>& mt, const Consts3<R>& k,
+                                                bool cl) {
   R srcT = R(0), srcC = R(0);
   R th = R(0), c = R(0);
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
-    th += f[19 + q];
-    c += f[26 + q];
+    th += gs[q];
+    c += gs[7 + q];
   }
   if (cl) {
     const lbm::React<R> r = reaction(th, c, mt.rhocp, k);
@@ -299,7 +356,7 @@ __device__ __forceinline__ void collide(R (&f)[33], const Mat3<R>& mt, const Con
   const R qm = R(1.2679491924311228);  // odd rate 6 / (3 + sqrt 3)
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    R* g = f + 19 + 7 * s;
+    R* g = gs + 7 * s;
     const R X = s == 0 ? th : c;
     const R aw = s == 0 ? mt.aT : mt.aC;
     const R src = s == 0 ? srcT : srcC;
@@ -307,7 +364,7 @@ __device__ __forceinline__ void collide(R (&f)[33], const Mat3<R>& mt, const Con
 #pragma unroll
     for (int pr = 0; pr < 3; ++pr) {
       const int i = 2 * pr + 1, o = i + 1;
-      const R eu = R(EX[19 + i]) * a.ux + R(EY[19 + i]) * a.uy + R(EZ[19 + i]) * a.uz;
+      const R eu = R(EX[19 + i]) * ux + R(EY[19 + i]) * uy + R(EZ[19 + i]) * uz;
       const R gp = R(0.5) * (g[i] + g[o]), gm = R(0.5) * (g[i] - g[o]);
       const R np = gp - qp * (gp - X * aw) + src * aw;
       const R nm = gm - qm * (gm - R(0.5) * X * eu);
@@ -322,6 +379,60 @@ __device__ __forceinline__ void collide(R (&f)[33], const Mat3<R>& mt, const Con
     // a fixed relative ~1e-7 of the scalar per step; this form conserves it.
     g[0] = (X + src) - moving;
   }
+}
+
+// Two-rate collision of every population of a node (flow with Guo's porous
+// forcing; scalars with the CL source injected with the rest weights).
+template <typename R>
+__device__ __forceinline__ void collide(R (&f)[33], const Mat3<R>& mt, const Consts3<R>& k, bool cl) {
+  const Macro3<R> a = flow_macros(f, mt, k);
+  collide_flow(f, a, mt, k);
+  collide_scalars(f + 19, a.ux, a.uy, a.uz, mt, k, cl);
+}
+
+// Store f[0 .. Q1 - Q0) into the planes [Q0, Q1) at element offset o, through
+// wave-uniform buffer bases (the 33 planes hold fewer than 2^31 elements).
+template <typename R, int Q0, int Q1>
+__device__ __forceinline__ void store_range(R* __restrict__ dst, const Consts3<R>& k, int o, const R* f) {
+  const uint32_t ob = uint32_t(o) * uint32_t(sizeof(R));
+#pragma unroll
+  for (int q = Q0; q < Q1; ++q) lbm::buffer_store(dst + int64_t(q) * k.plane, ob, f[q - Q0]);
+}
+
+// One time step of node (x, y, z) in two passes: the 19 flow populations
+// (pull, boundary extrapolation, collision, store), then the 14 scalar ones
+// with the node's velocity, so that at most 19 populations are held at once.
+template <typename R, int MAT>
+__device__ __forceinline__ void step_node(const R* __restrict__ src, R* __restrict__ dst, const R* __restrict__ phi_f,
+                                          const R* __restrict__ invk_f, const R* __restrict__ d_f,
+                                          const Consts3<R>& k, int x, int y, int z) {
+  const bool open = !(k.flags & F_PERIODIC_X);
+  const bool inlet = open && x == 0 && z < k.nz_ch;
+  const bool outlet = open && x == k.nx - 1;
+  const int xp = inlet ? 1 : (outlet ? k.nx - 2 : x);
+  const Mat3<R> mp = material<R, MAT>(k, phi_f, invk_f, d_f, xp, y, z);
+  Mat3<R> mt = mp;
+  if (inlet || outlet) mt = material<R, MAT>(k, phi_f, invk_f, d_f, x, y, z);
+  const int o = (z * k.ny + y) * k.pitch + x;
+  Macro3<R> a, nb{};
+  {
+    R f[19];
+    pull_range<R, 0, 19>(src, k, xp, y, z, f);
+    if (inlet || outlet) nb = boundary_flow(f, k, y, z, inlet, mp, mt);
+    a = flow_macros(f, mt, k);
+    collide_flow(f, a, mt, k);
+    store_range<R, 0, 19>(dst, k, o, f);
+  }
+  if (outlet) {  // scalar material of column nx-2 at the outlet
+    mt.aT = mp.aT;
+    mt.aC = mp.aC;
+    mt.rhocp = mp.rhocp;
+  }
+  R g[14];
+  pull_range<R, 19, 33>(src, k, xp, y, z, g);
+  if (inlet) boundary_scalars_inlet(g, k, y, z, nb, mp, mt);
+  collide_scalars(g, a.ux, a.uy, a.uz, mt, k, z >= k.z_cl0 && !(k.flags & F_NO_REACTION));
+  store_range<R, 19, 33>(dst, k, o, g);
 }
 
 }  // namespace lbm3

@@ -40,20 +40,23 @@ __device__ __forceinline__ void node_of(const Consts3<R>& k, int& x, int& y, int
   x = bx * kBlock3 + threadIdx.x;
 }
 
+// Waves per SIMD the FP32 step is compiled for: the flow and scalar passes
+// of step_node and the wave-uniform loads and stores keep it at 63 VGPRs (8
+// waves) with no spill, where the single-pass form needed 89 (5 waves).
+// The FP64 instance is left unconstrained.
+template <typename R>
+struct StepWaves3 {
+  static constexpr int value = sizeof(R) == 4 ? 8 : 1;
+};
+
 template <typename R, int MAT>
-__global__ __launch_bounds__(kBlock3) void k3_step(const R* __restrict__ src, R* __restrict__ dst,
-                                                   const R* __restrict__ phi_f, const R* __restrict__ invk_f,
-                                                   const R* __restrict__ d_f, Consts3<R> k) {
+__global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(StepWaves3<R>::value)))
+void k3_step(const R* __restrict__ src, R* __restrict__ dst, const R* __restrict__ phi_f,
+             const R* __restrict__ invk_f, const R* __restrict__ d_f, Consts3<R> k) {
   int x, y, z;
   node_of(k, x, y, z);
   if (x >= k.nx) return;
-  R f[33];
-  const Mat3<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, z, f);
-  const bool cl = z >= k.z_cl0 && !(k.flags & F_NO_REACTION);
-  collide(f, mt, k, cl);
-  const int o = (z * k.ny + y) * k.pitch + x;
-#pragma unroll
-  for (int q = 0; q < 33; ++q) dst[q * k.plane + o] = f[q];
+  step_node<R, MAT>(src, dst, phi_f, invk_f, d_f, k, x, y, z);
 }
 
 // Rest fluid at zero pressure (shifted f = 0), theta = 0, O2 at c_in.
