@@ -58,27 +58,51 @@ def measured_traffic(per_launch_cells: int, which: str = "step2d"):
     return c.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, phi, target_s: float = 15.0):
-    """The FP64 oracle on the host cores, timed on a bounded sample: whole
-    4096x1024 lattice, as many steps as fit in about target_s seconds."""
+def _oracle_sample(w, phi, target_s: float):
+    """Steps per second of the FP64 oracle on lattice w: one untimed step,
+    then as many as fit in about target_s seconds (at least one)."""
     import torch
 
     from oracle import lbm2d as L
-    m = L.Model(L.geometry_from_workload(w), L.Params.from_workload(w), phi=torch.as_tensor(phi))
+    m = L.Model(L.geometry_from_workload(w), L.Params.from_workload(w),
+                phi=None if phi is None else torch.as_tensor(phi))
     s = m.initial_state()
     t0 = time.perf_counter()
     s = m.step(s)
     first = time.perf_counter() - t0
-    n = max(1, min(20, int(target_s / max(first, 1e-3)) - 1))
+    n = max(1, min(2000, int(target_s / max(first, 1e-4)) - 1))
     t0 = time.perf_counter()
     for _ in range(n):
         s = m.step(s)
-    dt = time.perf_counter() - t0
+    return n, time.perf_counter() - t0
+
+
+def cpu_baseline(w, phi, target_s: float = 10.0):
+    """The FP64 oracle on the host cores, timed on bounded samples: the
+    whole 4096x1024 lattice with all the threads torch uses and with one,
+    and the 200x40 FP64 cathode (all threads) for up to its 2000 steps."""
+    import torch
+
+    import workloads as W
     cells = w["nx"] * w["ny"]
-    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle, full {w['nx']}x{w['ny']} lattice, {n} steps after 1 untimed "
-                      f"({dt:.1f} s)"}
+    threads = torch.get_num_threads()
+    n, dt = _oracle_sample(w, phi, target_s)
+    out = {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 oracle, full {w['nx']}x{w['ny']} lattice, {n} steps after 1 untimed ({dt:.1f} s), "
+                     f"{threads} threads (os.cpu_count() {os.cpu_count()})"}
+    torch.set_num_threads(1)
+    try:
+        n1, dt1 = _oracle_sample(w, phi, target_s)
+    finally:
+        torch.set_num_threads(threads)
+    out["single_thread"] = {"value": round(cells * n1 / dt1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                            "sample": f"same lattice, {n1} steps after 1 untimed ({dt1:.1f} s)"}
+    w1 = W.cathode2d_200x40()
+    n2, dt2 = _oracle_sample(w1, None, target_s)
+    out["cathode2d_200x40"] = {"value": round(w1["nx"] * w1["ny"] * n2 / dt2 / 1e6, 3), "unit": "MLUPS",
+                               "cores": threads, "sample": f"FP64 oracle, {n2} of its {w1['steps']} steps "
+                                                           f"after 1 untimed ({dt2:.1f} s)"}
+    return out
 
 
 def _timed(stream, fn):
@@ -111,6 +135,7 @@ def bench_batched(steps: int, seq_steps: int) -> dict:
     b.step(20)
     wall, ev = _timed(b.stream, lambda: b.step(steps))
     obs = b.observables()
+    b.close()
     del b
     sims = [Cathode.from_workload(w) for w in cases]
     for s in sims:
@@ -121,18 +146,55 @@ def bench_batched(steps: int, seq_steps: int) -> dict:
             s.step(seq_steps)
 
     wall_seq, _ = _timed(sims[0].stream, seq)
+    for s in sims:
+        s.close()
     del sims
     mlups = cells * steps / wall / 1e6
     mlups_seq = cells * seq_steps / wall_seq / 1e6
     achieved = cells * BYTES_PER_LU_POPS * steps / ev / 1e9
     return {"workload": "batched_sweep_64", "cases": len(cases), "cells": cells, "steps": steps,
             "value": round(mlups, 1), "unit": "MLUPS", "ms_per_step": round(wall * 1e3 / steps, 4),
-            "schedule": {k: tune[k] for k in ("tile_x", "tile_y", "persistent")},
+            "schedule": {k: tune.get(k, 0) for k in ("tile_x", "tile_y", "persistent", "block")},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_lattice_update": BYTES_PER_LU_POPS},
             "plain_sequential": {"value": round(mlups_seq, 1), "unit": "MLUPS", "steps_per_case": seq_steps},
             "speedup_vs_plain_sequential": round(mlups / mlups_seq, 3),
             "mean_current_density_A_cm2": float(np.mean([o["current_density"] for o in obs]))}
+
+
+BYTES_PER_LU_FP64 = 19 * 8 * 2  # 19 FP64 populations read and written per lattice update
+
+
+def bench_fp64(steps_large: int) -> dict:
+    """FP64 mode: the 200x40 cathode over its 2000 steps (8000 nodes: the
+    launch latency bounds it), and the 4096x1024 recipe in FP64 against the
+    304 B/LU (+8 for the porosity) roofline."""
+    import workloads as W
+    from paper_2103_01444_amd import Cathode
+
+    w1 = W.cathode2d_200x40()
+    with Cathode.from_workload(w1) as sim:
+        sim.step(20)
+        wall1, ev1 = _timed(sim.stream, lambda: sim.step(w1["steps"]))
+    c1 = w1["nx"] * w1["ny"]
+    out = {"cathode2d_200x40": {"cells": c1, "steps": w1["steps"], "value": round(c1 * w1["steps"] / wall1 / 1e6, 1),
+                                "unit": "MLUPS", "avg_launch_us": round(ev1 / w1["steps"] * 1e6, 3)}}
+    w = W.cathode2d_4096x1024()
+    w = dict(w, precision=64)
+    with Cathode.from_workload(w, phi=W.porosity_field(w)) as sim:
+        sim.step(20)
+        wall, ev = _timed(sim.stream, lambda: sim.step(steps_large))
+    cells = w["nx"] * w["ny"]
+    launch_s = ev / steps_large
+    bpl = BYTES_PER_LU_FP64 + 8
+    achieved = cells * bpl / launch_s / 1e9
+    out["cathode2d_4096x1024"] = {
+        "cells": cells, "steps": steps_large, "value": round(cells * steps_large / wall / 1e6, 1), "unit": "MLUPS",
+        "kernel": {"name": "k_step<double, MAT_PHI>", "avg_launch_us": round(launch_s * 1e6, 3),
+                   "bytes_per_lattice_update": bpl},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+    return out
 
 
 ADJ_BYTES_PER_LU = 19 * 4 * 3 + 3 * 4 + 3 * 4 * 2  # reverse step: pull S, read lambda, push lambda', 3 fields, gradient RMW
@@ -153,12 +215,13 @@ def bench_adjoint(nsteps: int = 4000, every: int = 200) -> dict:
     wall_f, _ = _timed(sim.stream, lambda: sim.step(nsteps))
     res = {}
     wall_cf, _ = _timed(sim.stream, lambda: res.update(J=sim.forward_checkpointed(nsteps, every)))
-    wall_b, _ = _timed(sim.stream, lambda: res.update(g=sim.backward(1.0)))
+    wall_b, _ = _timed(sim.stream, lambda: res.update(g=sim.backward(1.0, permeability=False)))
     g = res["g"]
     mlups_f = cells * nsteps / wall_f / 1e6
     mlups_b = cells * nsteps / wall_b / 1e6
     # backward = replay (one forward per step) + reverse step
     achieved = cells * nsteps * (ADJ_BYTES_PER_LU + FWD_FULL_BYTES_PER_LU) / wall_b / 1e9
+    sim.close()
     return {"workload": w["name"], "cells": cells, "steps": nsteps, "checkpoint_every": every,
             "forward": {"value": round(mlups_f, 1), "unit": "MLUPS"},
             "forward_checkpointed": {"value": round(cells * nsteps / wall_cf / 1e6, 1), "unit": "MLUPS"},
@@ -185,6 +248,7 @@ def bench_3d(steps: int, warmup: int = 50) -> dict:
     sim.step(warmup)
     wall, ev = _timed(sim.stream, lambda: sim.step(steps))
     obs = sim.observables()
+    sim.close()
     del sim
     cells = w["nx"] * w["ny"] * w["nz"]
     launch_s = ev / steps
@@ -200,9 +264,17 @@ def bench_3d(steps: int, warmup: int = 50) -> dict:
                             "o2_utilisation": obs["o2_utilisation"]}}
 
 
-def bench_polarisation(steps: int) -> dict:
+def bench_polarisation(steps: int, block: int = 500000, tol: float = 1e-4) -> dict:
     """Polarisation / power / heat curves of the pressure-driven 200x40
-    cathode (3 outlet pressures x 13 voltages = 39 cases in one batch)."""
+    cathode (3 outlet pressures x 13 voltages = 39 cases in one batch), run
+    to steady state: blocks of ``block`` steps until the current density of
+    every case changes by less than ``tol`` (relative) over a block, or
+    ``steps`` steps.  The slowest mode is heat conduction along the channel
+    in the solid of the GDL (a few 10^6 steps at this lattice's time step,
+    which the gas thermal diffusivity bounds).  The throughput is timed over
+    the first block."""
+    import numpy as np
+
     import workloads as W
     from paper_2103_01444_amd import BatchedSweep
 
@@ -211,30 +283,48 @@ def bench_polarisation(steps: int) -> dict:
     b = BatchedSweep(cases)
     tune = b.autotune(trial_steps=10, cache_path=os.environ.get(
         "LBMPEM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lbmpem_tune.json")))
-    head = steps - steps // 10
-    wall, ev = _timed(b.stream, lambda: b.step(head))
+    first = min(block, steps)
+    wall, ev = _timed(b.stream, lambda: b.step(first))
+    done, drift = first, float("inf")
     prev = [o["current_density"] for o in b.observables()]
-    wall2, ev2 = _timed(b.stream, lambda: b.step(steps - head))
-    wall, ev = wall + wall2, ev + ev2
+    while done < steps and drift >= tol:
+        n = min(block, steps - done)
+        b.step(n)
+        done += n
+        obs = b.observables()
+        drift = max(abs(o["current_density"] - p) / abs(o["current_density"]) for o, p in zip(obs, prev))
+        prev = [o["current_density"] for o in obs]
     obs = b.observables()
+    b.close()
     del b
-    drift = max(abs(o["current_density"] - p) / abs(o["current_density"]) for o, p in zip(obs, prev))
     nu = (cases[0]["tau_f"] - 0.5) / 3.0
     nv = len(W.POLARISATION_V)
+    v = np.array(W.POLARISATION_V)
+    I = np.array([o["current_density"] for o in obs]).reshape(-1, nv)
     curves = []
     for j, p_out in enumerate(W.POLARISATION_P_OUT):
         o = obs[j * nv:(j + 1) * nv]
-        curves.append({"p_in": W.POLARISATION_P_IN, "p_out": p_out, "Re": round(o[-1]["inlet_flux"] / nu, 3), "V": list(W.POLARISATION_V),
+        curves.append({"p_in": W.POLARISATION_P_IN, "p_out": p_out, "Re": round(o[-1]["inlet_flux"] / nu, 3),
+                       "V": list(W.POLARISATION_V),
                        "I_A_cm2": [round(x["current_density"], 4) for x in o],
                        "P_W_cm2": [round(x["power_density"], 4) for x in o],
-                       "heat_W_cm2": [round(x["heat_rate"], 4) for x in o]})
-    achieved = cells * BYTES_PER_LU_POPS * steps / ev / 1e9
-    return {"workload": "polarisation_sweep_39", "cases": len(cases), "cells": cells, "steps": steps,
-            "value": round(cells * steps / wall / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(wall * 1e3 / steps, 4),
-            "schedule": {k: tune[k] for k in ("tile_x", "tile_y", "persistent")},
+                       "heat_W_cm2": [round(x["heat_rate"], 4) for x in o],
+                       "T_max_K": [round(x["T_max"], 3) for x in o]})
+    kinetic, plateau = v >= 0.599, v <= 0.551
+    trends = {  # Section 5 (Figs. 9, 12): on the steady curves
+        "I_falls_with_V_above_0.6V": bool(np.all(np.diff(I[:, kinetic], axis=1) < 0)),
+        "I_rises_with_flow_rate_up_to_0.55V": bool(np.all(np.diff(I[:, plateau], axis=0) > 0)),
+        "power_peaks_inside_the_range": bool(all(0 < int(np.argmax(c["P_W_cm2"])) < nv - 1 for c in curves)),
+    }
+    achieved = cells * BYTES_PER_LU_POPS * first / ev / 1e9
+    return {"workload": "polarisation_sweep_39", "cases": len(cases), "cells": cells, "steps_timed": first,
+            "value": round(cells * first / wall / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(wall * 1e3 / first, 4),
+            "schedule": {k: tune.get(k, 0) for k in ("tile_x", "tile_y", "persistent", "block")},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_lattice_update": BYTES_PER_LU_POPS},
-            "curves_after_steps": steps, "max_rel_change_I_last_tenth": round(drift, 6), "curves": curves}
+            "curves_after_steps": done, "steady_block_steps": block,
+            "max_rel_change_I_last_block": round(drift, 8), "steady": bool(drift < tol), "trends": trends,
+            "curves": curves}
 
 
 def bench_variants(steps: int) -> dict:
@@ -260,6 +350,7 @@ def bench_variants(steps: int) -> dict:
         sim.step(50)
         wall, ev = _timed(sim.stream, lambda: sim.step(steps))
         o = sim.observables()
+        sim.close()
         del sim
         achieved = cells * (BYTES_PER_LU_POPS + BYTES_PER_LU_PHI) * steps / ev / 1e9
         out[name] = {"value": round(cells * steps / wall / 1e6, 1), "unit": "MLUPS", "steps": steps,
@@ -285,7 +376,7 @@ def bench_adjoint3d(nsteps: int = 5000, every: int = 70) -> dict:
     wall_f, _ = _timed(sim.stream, lambda: sim.step(nsteps))
     res = {}
     wall_cf, _ = _timed(sim.stream, lambda: res.update(J=sim.forward_checkpointed(nsteps, every)))
-    wall_b, _ = _timed(sim.stream, lambda: res.update(g=sim.backward(1.0)))
+    wall_b, _ = _timed(sim.stream, lambda: res.update(g=sim.backward(1.0, permeability=False)))
     g = res["g"]
     achieved = cells * nsteps * (ADJ3_BYTES_PER_LU + FWD3_FULL_BYTES_PER_LU) / wall_b / 1e9
     out = {"workload": w["name"], "cells": cells, "steps": nsteps, "checkpoint_every": every,
@@ -299,6 +390,7 @@ def bench_adjoint3d(nsteps: int = 5000, every: int = 70) -> dict:
                         "bytes_per_lattice_update": ADJ3_BYTES_PER_LU + FWD3_FULL_BYTES_PER_LU},
            "J_A_cm2": res["J"],
            "max_abs_grad_inv_k": float(g["inv_k"].abs().max())}
+    sim.close()
     del sim, g, res
     return out
 
@@ -313,8 +405,12 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint")
     ap.add_argument("--steps3d", type=int, default=5000, help="0 skips the 3D cathode")
     ap.add_argument("--adjoint3d-steps", type=int, default=5000, help="0 skips the 3D adjoint")
-    ap.add_argument("--polarisation-steps", type=int, default=300000, help="0 skips the polarisation sweep")
+    ap.add_argument("--polarisation-steps", type=int, default=8000000,
+                    help="most steps of the polarisation sweep (it stops at steady state); 0 skips it")
     ap.add_argument("--variant-steps", type=int, default=2000, help="0 skips the model-option variants")
+    ap.add_argument("--fp64-steps", type=int, default=1000, help="0 skips the FP64 rows")
+    ap.add_argument("--sustained-s", type=float, default=8.0,
+                    help="seconds of continued stepping before the sustained k_step figure (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write copy kernel 5 times (counter calibration)")
     args = ap.parse_args()
@@ -392,7 +488,25 @@ def main():
         "observables": {"current_density_A_cm2": obs["current_density"], "T_max_K": obs["T_max"],
                         "o2_utilisation": obs["o2_utilisation"]},
     }
+    if args.sustained_s > 0:
+        # the same kernel after args.sustained_s seconds of continuous load
+        # (the first seconds of a process run faster than the steady state)
+        n_load = max(1, int(args.sustained_s / launch_s))
+        sim.step(n_load)
+        n_meas = 2000
+        _, ev_s = _timed(stream, lambda: sim.step(n_meas))
+        ls = ev_s / n_meas
+        line["sustained"] = {"after_steps": n_load + args.steps + args.warmup, "steps": n_meas,
+                             "avg_launch_us": round(ls * 1e6, 3),
+                             "frac": round(bytes_per_launch / ls / 1e9 / HBM_PEAK_GBS, 4)}
+        print(f"bench: sustained kernel avg {ls * 1e6:.2f} us after {n_load} more steps", file=sys.stderr, flush=True)
+    sim.close()
     del sim
+    if args.fp64_steps > 0:
+        print("bench: FP64 rows", file=sys.stderr, flush=True)
+        line["fp64"] = bench_fp64(args.fp64_steps)
+        print(f"bench: fp64 4096x1024 {line['fp64']['cathode2d_4096x1024']['value']} MLUPS, "
+              f"200x40 {line['fp64']['cathode2d_200x40']['value']} MLUPS", file=sys.stderr, flush=True)
     if args.variant_steps > 0:
         print("bench: model-option variants", file=sys.stderr, flush=True)
         line["variants"] = bench_variants(args.variant_steps)

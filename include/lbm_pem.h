@@ -322,7 +322,9 @@ typedef struct lbm_batch lbm_batch;
 typedef struct lbm_schedule {
   int32_t tile_x, tile_y;  /* tile_x * tile_y in [64, 65536] */
   int32_t persistent;      /* 0: one launch per step; 1: one cooperative launch */
-  int32_t reserved;
+  int32_t block;           /* threads per workgroup of the per-step form: 0 or 256 (cells of a tile in a
+                            * loop, or one per thread when the tile has 256), or 64 / 128 when the tile has
+                            * exactly that many cells (one per thread); the persistent form uses 256 */
 } lbm_schedule;
 
 /* Device workspace for ncases lattices (state pool, autotuning backup,

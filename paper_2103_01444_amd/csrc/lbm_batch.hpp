@@ -73,10 +73,12 @@ __device__ __forceinline__ int xcd_logical(int flat, int total) {
   return xcd * full + (xcd < rem ? xcd : rem) + slot;
 }
 
-template <typename R, bool ONE, bool UNIFORM>
-__global__ __launch_bounds__(kBlock) void k_batch_step(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
-                                                       const Tile* __restrict__ tiles, int ntiles, int parity,
-                                                       int tx, int ty) {
+// BS: workgroup size.  Tiles of exactly BS cells (64, 128 or 256) run one
+// cell per thread; other tiles loop over their cells with 256 threads.
+template <typename R, bool ONE, bool UNIFORM, int BS = kBlock>
+__global__ __launch_bounds__(BS) void k_batch_step(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
+                                                   const Tile* __restrict__ tiles, int ntiles, int parity, int tx,
+                                                   int ty) {
   const int t = xcd_logical(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
   batch_tile<R, ONE, UNIFORM>(pool, cases, tiles[t], parity, tx, ty);

@@ -226,24 +226,43 @@ lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
       left -= chunk;
     }
   } else {
-    const bool one = tx * ty == kBlock;
-    // batches of few nodes (one round of wavefronts per launch) take the
-    // wave-uniform addressing form
+    // workgroups of 64 or 128 threads: one cell of the tile (of that many
+    // cells) per thread; of 256: one cell per thread for tiles of 256 cells,
+    // a cell loop otherwise.  Batches of few nodes (one round of wavefronts
+    // per launch) take the wave-uniform addressing form.
+    const int cells = tx * ty;
+    const int bs = b->sched.block == 64 || b->sched.block == 128 ? b->sched.block : kBlock;
     const bool uniform = b->cells < (int64_t(1) << 20);
-    const dim3 grid(b->ntiles), block(kBlock);
+    const dim3 grid(b->ntiles);
     for (int64_t s = 0; s < nsteps; ++s) {
-      if (one && uniform)
-        hipLaunchKernelGGL((k_batch_step<R, true, true>), grid, block, 0, b->stream, pool, cases, tiles, b->ntiles,
-                           b->parity, tx, ty);
-      else if (one)
-        hipLaunchKernelGGL((k_batch_step<R, true, false>), grid, block, 0, b->stream, pool, cases, tiles, b->ntiles,
-                           b->parity, tx, ty);
-      else if (uniform)
-        hipLaunchKernelGGL((k_batch_step<R, false, true>), grid, block, 0, b->stream, pool, cases, tiles, b->ntiles,
-                           b->parity, tx, ty);
-      else
-        hipLaunchKernelGGL((k_batch_step<R, false, false>), grid, block, 0, b->stream, pool, cases, tiles, b->ntiles,
-                           b->parity, tx, ty);
+      if (bs == 64) {
+        if (uniform)
+          hipLaunchKernelGGL((k_batch_step<R, true, true, 64>), grid, dim3(64), 0, b->stream, pool, cases, tiles,
+                             b->ntiles, b->parity, tx, ty);
+        else
+          hipLaunchKernelGGL((k_batch_step<R, true, false, 64>), grid, dim3(64), 0, b->stream, pool, cases, tiles,
+                             b->ntiles, b->parity, tx, ty);
+      } else if (bs == 128) {
+        if (uniform)
+          hipLaunchKernelGGL((k_batch_step<R, true, true, 128>), grid, dim3(128), 0, b->stream, pool, cases, tiles,
+                             b->ntiles, b->parity, tx, ty);
+        else
+          hipLaunchKernelGGL((k_batch_step<R, true, false, 128>), grid, dim3(128), 0, b->stream, pool, cases, tiles,
+                             b->ntiles, b->parity, tx, ty);
+      } else if (cells == kBlock) {
+        if (uniform)
+          hipLaunchKernelGGL((k_batch_step<R, true, true>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
+                             b->ntiles, b->parity, tx, ty);
+        else
+          hipLaunchKernelGGL((k_batch_step<R, true, false>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
+                             b->ntiles, b->parity, tx, ty);
+      } else if (uniform) {
+        hipLaunchKernelGGL((k_batch_step<R, false, true>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
+                           b->ntiles, b->parity, tx, ty);
+      } else {
+        hipLaunchKernelGGL((k_batch_step<R, false, false>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
+                           b->ntiles, b->parity, tx, ty);
+      }
       b->parity ^= 1;
     }
     const hipError_t e = hipGetLastError();
@@ -257,6 +276,9 @@ template <typename R>
 lbm_status set_schedule_t(lbm_batch* b, const lbm_schedule& s) {
   if (s.tile_x < 1 || s.tile_y < 1 || s.tile_x * s.tile_y < kMinTileCells || s.tile_x * s.tile_y > 1 << 16)
     return bfail(b, LBM_ERR_INVALID_ARG, "tile shape out of range");
+  if (!(s.block == 0 || s.block == kBlock ||
+        ((s.block == 64 || s.block == 128) && s.tile_x * s.tile_y == s.block && !s.persistent)))
+    return bfail(b, LBM_ERR_INVALID_ARG, "workgroup size: 0 or 256, or 64 / 128 for a per-step tile of as many cells");
   b->sched = s;
   if (lbm_status st = build_tiles(b, s.tile_x, s.tile_y); st != LBM_OK) return st;
   if (s.persistent) return persistent_grid<R>(b, &b->persistent_grid);
@@ -337,7 +359,7 @@ lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double*
   const int parity0 = b->parity;
   const int64_t step0 = b->step;
   const lbm_schedule keep = b->sched;
-  static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {1024, 1}, {64, 4},
+  static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {1024, 1}, {64, 2}, {64, 4}, {32, 4},
                                   {128, 2}, {256, 2}, {256, 4}, {512, 2}, {128, 8}, {64, 16}};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -345,33 +367,38 @@ lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double*
   double best_t = 1e300;
   lbm_schedule best_s = keep;
   lbm_status st = LBM_OK;
-  for (int persistent = 0; persistent < 2 && st == LBM_OK; ++persistent) {
+  std::vector<lbm_schedule> cand;
+  for (int persistent = 0; persistent < 2; ++persistent)
     for (const auto& sh : shapes) {
-      lbm_schedule s{sh[0], sh[1], persistent, 0};
-      if (set_schedule_t<R>(b, s) != LBM_OK) continue;  // shape not usable here
-      st = launch_steps<R>(b, 2);                        // warm up
-      if (st != LBM_OK) break;
-      (void)hipEventRecord(e0, b->stream);
-      st = launch_steps<R>(b, trial_steps);
-      if (st != LBM_OK) break;
-      (void)hipEventRecord(e1, b->stream);
-      if (hipEventSynchronize(e1) != hipSuccess) {
-        st = bfail(b, LBM_ERR_DEVICE, "autotune trial failed");
-        break;
-      }
-      if (persistent && barrier_status(b) != LBM_OK) {  // not co-resident: the schedule is unusable
-        hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(64), 0, b->stream, b->barrier_count(),
-                           b->barrier_failed(), 1);
-        b->err.clear();
-        continue;
-      }
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      const double per = double(ms) / trial_steps;
-      if (per < best_t) {
-        best_t = per;
-        best_s = s;
-      }
+      cand.push_back({sh[0], sh[1], persistent, 0});
+      const int cells = sh[0] * sh[1];
+      if (!persistent && (cells == 64 || cells == 128)) cand.push_back({sh[0], sh[1], 0, cells});
+    }
+  for (const lbm_schedule& s : cand) {
+    const int persistent = s.persistent;
+    if (set_schedule_t<R>(b, s) != LBM_OK) continue;  // shape not usable here
+    st = launch_steps<R>(b, 2);                        // warm up
+    if (st != LBM_OK) break;
+    (void)hipEventRecord(e0, b->stream);
+    st = launch_steps<R>(b, trial_steps);
+    if (st != LBM_OK) break;
+    (void)hipEventRecord(e1, b->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      st = bfail(b, LBM_ERR_DEVICE, "autotune trial failed");
+      break;
+    }
+    if (persistent && barrier_status(b) != LBM_OK) {  // not co-resident: the schedule is unusable
+      hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(64), 0, b->stream, b->barrier_count(),
+                         b->barrier_failed(), 1);
+      b->err.clear();
+      continue;
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double per = double(ms) / trial_steps;
+    if (per < best_t) {
+      best_t = per;
+      best_s = s;
     }
   }
   (void)hipEventDestroy(e0);

@@ -68,7 +68,7 @@ class Obs(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("block", ctypes.c_int32)]
 
 
 _lib = None
@@ -350,16 +350,18 @@ class Cathode:
                                                       ctypes.byref(J)))
         return J.value
 
-    def backward(self, dJ: float = 1.0) -> dict:
+    def backward(self, dJ: float = 1.0, permeability: bool = True) -> dict:
         """dJ times the gradient of J with respect to the per-cell 1/K
         (``inv_k``), porosity (``phi``) and D_eff (``d_eff``), and with
-        respect to the permeability K itself (``K``: -(1/K)^2 dJ/d(1/K), zero
-        in the clear channel where 1/K = 0), as [ny, nx] tensors."""
+        ``permeability`` with respect to the permeability K itself (``K``:
+        -(1/K)^2 dJ/d(1/K), zero in the clear channel where 1/K = 0), as
+        [ny, nx] tensors."""
         out = {k: torch.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
                for k in ("inv_k", "phi", "d_eff")}
         self._check(self.lib.lbm_backward(self.ctx, float(dJ), _ptr(out["inv_k"]), _ptr(out["phi"]),
                                           _ptr(out["d_eff"])))
-        out["K"] = grad_wrt_permeability(self.material()["inv_k"], out["inv_k"])
+        if permeability:
+            out["K"] = grad_wrt_permeability(self.material()["inv_k"], out["inv_k"])
         return out
 
     def close(self):
@@ -493,14 +495,15 @@ class Cathode3D:
                                                         ctypes.byref(J)))
         return J.value
 
-    def backward(self, dJ: float = 1.0) -> dict:
+    def backward(self, dJ: float = 1.0, permeability: bool = True) -> dict:
         """dJ times the gradient of J with respect to the per-cell 1/K,
-        porosity and D_eff, and K (-(1/K)^2 dJ/d(1/K)), as [nz, ny, nx]
-        tensors."""
+        porosity and D_eff, and with ``permeability`` K (-(1/K)^2
+        dJ/d(1/K)), as [nz, ny, nx] tensors."""
         out = {k: torch.empty(self.shape, dtype=self.dtype, device=self.device) for k in ("inv_k", "phi", "d_eff")}
         self._check(self.lib.lbm3d_backward(self.ctx, float(dJ), _ptr(out["inv_k"]), _ptr(out["phi"]),
                                             _ptr(out["d_eff"])))
-        out["K"] = grad_wrt_permeability(self.material()["inv_k"], out["inv_k"])
+        if permeability:
+            out["K"] = grad_wrt_permeability(self.material()["inv_k"], out["inv_k"])
         return out
 
     def close(self):
@@ -583,10 +586,10 @@ class BatchedSweep:
     def schedule(self) -> dict:
         s = Schedule()
         self._check(self.lib.lbm_batch_get_schedule(self.h, ctypes.byref(s)))
-        return dict(tile_x=s.tile_x, tile_y=s.tile_y, persistent=s.persistent)
+        return dict(tile_x=s.tile_x, tile_y=s.tile_y, persistent=s.persistent, block=s.block)
 
-    def set_schedule(self, tile_x: int, tile_y: int, persistent: int):
-        s = Schedule(tile_x, tile_y, persistent, 0)
+    def set_schedule(self, tile_x: int, tile_y: int, persistent: int, block: int = 0):
+        s = Schedule(tile_x, tile_y, persistent, block)
         self._check(self.lib.lbm_batch_set_schedule(self.h, ctypes.byref(s)))
 
     def autotune(self, trial_steps: int = 20, cache_path: str | None = None) -> dict:
@@ -599,12 +602,13 @@ class BatchedSweep:
                 cache = json.load(f)
         if key in cache:
             c = cache[key]
-            self.set_schedule(c["tile_x"], c["tile_y"], c["persistent"])
+            self.set_schedule(c["tile_x"], c["tile_y"], c["persistent"], c.get("block", 0))
             return dict(c, cached=True)
         best = Schedule()
         ms = ctypes.c_double()
         self._check(self.lib.lbm_batch_autotune(self.h, int(trial_steps), ctypes.byref(best), ctypes.byref(ms)))
-        res = dict(tile_x=best.tile_x, tile_y=best.tile_y, persistent=best.persistent, ms_per_step=ms.value)
+        res = dict(tile_x=best.tile_x, tile_y=best.tile_y, persistent=best.persistent, block=best.block,
+                   ms_per_step=ms.value)
         if cache_path:
             cache[key] = res
             os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)

@@ -35,7 +35,8 @@ def test_batch_cases_equal_single_contexts_bitwise():
         assert obs[i]["sum_c"] == o["sum_c"]
 
 
-@pytest.mark.parametrize("sched", [(64, 4, 0), (512, 2, 0), (128, 2, 1), (256, 1, 1), (64, 16, 1)])
+@pytest.mark.parametrize("sched", [(64, 4, 0), (512, 2, 0), (128, 2, 1), (256, 1, 1), (64, 16, 1), (128, 1, 0, 128),
+                                   (32, 2, 0, 64), (128, 1, 0, 0)])
 def test_every_schedule_gives_identical_results(sched):
     lbm = _lbm()
     cases = _cases()
@@ -61,7 +62,7 @@ def test_autotune_keeps_state_and_is_cached(tmp_path):
     assert b.step_count == 40
     for i in range(len(cases)):
         assert torch.equal(b.populations(i), before[i])
-    assert b.schedule == {k: res[k] for k in ("tile_x", "tile_y", "persistent")}
+    assert b.schedule == {k: res[k] for k in ("tile_x", "tile_y", "persistent", "block")}
     b2 = lbm.BatchedSweep(cases)
     res2 = b2.autotune(trial_steps=3, cache_path=str(tmp_path / "tune.json"))
     assert res2["cached"] and b2.schedule == b.schedule
