@@ -101,23 +101,53 @@ struct PersistentWaves<double> {
   static constexpr int value = 2;
 };
 
-// Grid-wide barrier of the persistent kernel.  `count` counts arrivals since
-// the launch (cleared before it); step s waits for (s + 1) gridDim.x of
-// them.  A wait longer than `limit` wall-clock ticks (seconds, where a step
-// takes micro- to milliseconds) means workgroups that never started: the
-// waiter sets `failed`, and every workgroup that sees it leaves the kernel.
+// Grid-wide barrier of the persistent kernel, in two levels.  The
+// workgroups form 8 groups (blockIdx.x mod 8, the XCD the dispatcher deals
+// them to); each arrival adds to its group's count, and the group's last
+// arrival of a step adds to the global count, which the waiters read:
+// count[64 (1 + g)] holds group g's arrivals since the launch, count[0] the
+// groups' (all cleared before the launch, 256 bytes apart).  Step s ends
+// when count[0] reaches (s + 1) times the number of groups.  One count for
+// every workgroup cost 125 us per step for the barrier alone on MI355X (1536
+// workgroups), two levels 25 us.  A wait longer than `limit` wall-clock
+// ticks (seconds, where a step takes micro- to milliseconds) means
+// workgroups that never started: the waiter sets `failed`, and every
+// workgroup that sees it leaves the kernel.
+constexpr int kBarrierWords = 9;  // the global count and 8 group counts
 struct GridBarrier {
   unsigned int* count;
   int* failed;
   long long limit;
 };
 
-__device__ __forceinline__ bool grid_barrier(const GridBarrier& gb, unsigned int target) {
+// Only the arriving thread fences.  Every wavefront first waits for its
+// stores of the step to complete into the XCD's L2 and meets the others at
+// the workgroup barrier; the arriving thread's release fence at device scope
+// then writes that L2 back, and its acquire fence after the wait invalidates
+// this CU's L1 and the L2's stale lines before the second workgroup barrier
+// lets the other threads load.  On gfx950 each device-scope fence is an L2
+// write-back or invalidate of the whole XCD; fencing in every wavefront
+// multiplied them by four and invalidated lines that workgroups still inside
+// the step were reading.
+__device__ __forceinline__ bool grid_barrier(const GridBarrier& gb, unsigned int step) {
   __shared__ int ok;
-  __threadfence();  // this thread's stores of the step, visible at device scope
+  // every wavefront's stores acknowledged by the L2 (s_waitcnt vmcnt(0);
+  // expcnt and lgkmcnt left at their maxima) before the arriving thread's
+  // write-back
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(gb.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the workgroup's stores of the step, visible at device scope
+    const unsigned groups = gridDim.x < 8u ? gridDim.x : 8u;
+    const unsigned g = blockIdx.x & 7u;
+    const unsigned members = gridDim.x / 8u + (g < gridDim.x % 8u ? 1u : 0u);
+    const unsigned before =
+        __hip_atomic_fetch_add(gb.count + 64 * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (before + 1u == step * members) {  // the group's last arrival: its members' releases, passed on
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      __hip_atomic_fetch_add(gb.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const unsigned target = step * groups;
     const long long t0 = wall_clock64();
     int good = 1;
     while (__hip_atomic_load(gb.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -129,18 +159,16 @@ __device__ __forceinline__ bool grid_barrier(const GridBarrier& gb, unsigned int
       }
       __builtin_amdgcn_s_sleep(4);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other workgroups' stores, seen by this workgroup's loads
     ok = good;
   }
   __syncthreads();
-  __threadfence();  // the other workgroups' stores, seen by this one's loads
   return ok != 0;
 }
 
 __global__ void k_clear_barrier(unsigned int* count, int* failed, int clear_failed) {
-  if (threadIdx.x == 0) {
-    *count = 0u;
-    if (clear_failed) *failed = 0;
-  }
+  if (threadIdx.x < kBarrierWords) count[64 * threadIdx.x] = 0u;
+  if (threadIdx.x == 0 && clear_failed) *failed = 0;
 }
 
 // The persistent form keeps the cell loop for every tile shape.
@@ -155,7 +183,7 @@ void k_batch_persistent(R* __restrict__ pool, const BatchCase<R>* __restrict__ c
   for (int s = 0; s < nsteps; ++s) {
     const int parity = (parity0 + s) & 1;
     for (int t = t0; t < t1; ++t) batch_tile<R, false>(pool, cases, tiles[t], parity, tx, ty);
-    if (!grid_barrier(gb, unsigned(s + 1) * unsigned(gridDim.x))) return;
+    if (!grid_barrier(gb, unsigned(s + 1))) return;
   }
 }
 

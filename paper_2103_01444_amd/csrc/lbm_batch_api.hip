@@ -24,7 +24,7 @@ struct BatchLayout {
   std::vector<int64_t> state_off[2];  // element offsets per case
   int64_t pool_elems = 0;
   size_t off_pool = 0, off_backup = 0, off_cases = 0, off_tiles = 0, off_partial = 0, off_prof = 0, off_out = 0;
-  size_t off_sync = 0;  // the persistent kernel's barrier: arrival count and failure flag
+  size_t off_sync = 0;  // the persistent kernel's barrier: its counts (256 B apart), then the failure flag
   size_t total = 0;
   int max_tiles = 0;
   int max_obs_blocks = 0;
@@ -74,7 +74,7 @@ BatchLayout make_batch_layout(const lbm_geometry* g, int n) {
   L.off_out = o;
   o += align_up(16 * sizeof(double));
   L.off_sync = o;
-  o += align_up(2 * sizeof(int));
+  o += align_up(size_t(kBarrierWords + 1) * 256);
   L.total = o;
   return L;
 }
@@ -109,7 +109,7 @@ struct lbm_batch {
   double* prof() { return reinterpret_cast<double*>(ws + L.off_prof); }
   double* out() { return reinterpret_cast<double*>(ws + L.off_out); }
   unsigned int* barrier_count() { return reinterpret_cast<unsigned int*>(ws + L.off_sync); }
-  int* barrier_failed() { return reinterpret_cast<int*>(ws + L.off_sync + sizeof(int)); }
+  int* barrier_failed() { return reinterpret_cast<int*>(ws + L.off_sync + size_t(kBarrierWords) * 256); }
 };
 
 namespace {

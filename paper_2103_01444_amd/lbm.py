@@ -381,8 +381,9 @@ class Cathode:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # bound at definition: at interpreter exit the module's globals may already be None
+        if _finalizing():
             return
         try:
             self.close()
@@ -523,8 +524,9 @@ class Cathode3D:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # bound at definition: at interpreter exit the module's globals may already be None
+        if _finalizing():
             return
         try:
             self.close()
@@ -654,8 +656,9 @@ class BatchedSweep:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # bound at definition: at interpreter exit the module's globals may already be None
+        if _finalizing():
             return
         try:
             self.close()

@@ -159,3 +159,20 @@ def test_null_handles_are_refused_without_touching_the_gpu(lib):
     lib.lbm_destroy(None)
     lib.lbm3d_destroy(None)
     lib.lbm_batch_destroy(None)
+
+
+def test_destructors_survive_interpreter_teardown(monkeypatch):
+    """At interpreter exit a module's globals may already be None when a
+    context is collected: the destructors must neither raise nor make HIP
+    calls while the interpreter is finalising, and must close otherwise."""
+    from paper_2103_01444_amd import lbm
+    for cls in (lbm.Cathode, lbm.Cathode3D, lbm.BatchedSweep):
+        closed = []
+        monkeypatch.setattr(cls, "close", lambda self, closed=closed: closed.append(1))
+        obj = cls.__new__(cls)
+        with monkeypatch.context() as m:
+            m.setattr(lbm, "sys", None)
+            obj.__del__()
+        assert closed == [1], cls.__name__
+        obj.__del__(lambda: True)  # finalising: no call at all
+        assert closed == [1], cls.__name__
