@@ -355,6 +355,12 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_schedule* b
  * LBM_ERR_DEVICE (the state is then invalid until
  * lbm_batch_init_equilibrium). */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
+/* The longest a persistent launch's grid barrier waits (seconds, 0 to 3600;
+ * 4 by default) before it gives up as described under lbm_batch_step.  0
+ * gives up after one tick of the device wall clock.  For callers that bound
+ * the latency of a failed launch, and for tests of that error path.
+ * LBM_ERR_INVALID_ARG outside [0, 3600].  Applies to later launches. */
+lbm_status lbm_batch_set_barrier_timeout(lbm_batch* b, double seconds);
 /* out[ncases]: observables of every case (as lbm_observables).  Synchronous. */
 lbm_status lbm_batch_observables(lbm_batch* b, lbm_obs* out);
 /* Canonical populations of case i (layout of lbm_get_populations).  Async. */

@@ -97,6 +97,7 @@ struct lbm_batch {
   int ntiles = 0;
   int persistent_grid = 0;
   long long barrier_limit = 0;  // wall-clock ticks a persistent barrier waits at most
+  int wall_khz = 0;             // the device wall clock's rate
   int64_t cells = 0;  // lattice nodes over all cases
   std::string err;
 
@@ -452,6 +453,7 @@ lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t 
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
     return bfail(b, LBM_ERR_DEVICE, "device wall-clock rate unavailable");
+  b->wall_khz = wall_khz;
   b->barrier_limit = 4000LL * wall_khz;  // 4 s
   for (int i = 0; i < ncases; ++i) {
     std::string msg;
@@ -495,6 +497,12 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_schedule* b
   if (!b || trial_steps < 1) return LBM_ERR_INVALID_ARG;
   return b->g[0].precision == 64 ? autotune_t<double>(b, trial_steps, best, best_ms_per_step)
                                  : autotune_t<float>(b, trial_steps, best, best_ms_per_step);
+}
+
+lbm_status lbm_batch_set_barrier_timeout(lbm_batch* b, double seconds) {
+  if (!b || !(seconds >= 0.0) || seconds > 3600.0) return LBM_ERR_INVALID_ARG;
+  b->barrier_limit = static_cast<long long>(seconds * 1000.0 * double(b->wall_khz));
+  return LBM_OK;
 }
 
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {

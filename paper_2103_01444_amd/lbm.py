@@ -79,7 +79,8 @@ EXPORTED = ["lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_set_
             "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count", "lbm_synchronize",
             "lbm_destroy", "lbm_status_string", "lbm_last_error",
             "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_init_equilibrium", "lbm_batch_set_schedule",
-            "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_observables",
+            "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_set_barrier_timeout", "lbm_batch_step",
+            "lbm_batch_observables",
             "lbm_batch_get_populations", "lbm_batch_step_count", "lbm_batch_synchronize", "lbm_batch_destroy",
             "lbm_batch_last_error", "lbm_adjoint_workspace_bytes", "lbm_forward_checkpointed", "lbm_backward",
             "lbm3d_workspace_bytes", "lbm3d_create", "lbm3d_set_params", "lbm3d_init_equilibrium", "lbm3d_step",
@@ -125,6 +126,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_batch_set_schedule": (ctypes.c_int, [vp, P(Schedule)]),
         "lbm_batch_get_schedule": (ctypes.c_int, [vp, P(Schedule)]),
         "lbm_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int32, P(Schedule), P(ctypes.c_double)]),
+        "lbm_batch_set_barrier_timeout": (ctypes.c_int, [vp, ctypes.c_double]),
         "lbm_batch_step": (ctypes.c_int, [vp, i64]),
         "lbm_batch_observables": (ctypes.c_int, [vp, P(Obs)]),
         "lbm_batch_get_populations": (ctypes.c_int, [vp, ctypes.c_int32, vp]),
@@ -620,6 +622,14 @@ class BatchedSweep:
 
     def step(self, n: int = 1):
         self._check(self.lib.lbm_batch_step(self.h, int(n)))
+
+    def init_equilibrium(self):
+        """Every case back to its initial state (step 0)."""
+        self._check(self.lib.lbm_batch_init_equilibrium(self.h))
+
+    def set_barrier_timeout(self, seconds: float):
+        """Bound on each grid-barrier wait of a persistent launch (4 s by default)."""
+        self._check(self.lib.lbm_batch_set_barrier_timeout(self.h, float(seconds)))
 
     @property
     def step_count(self) -> int:

@@ -35,6 +35,34 @@ def test_batch_cases_equal_single_contexts_bitwise():
         assert obs[i]["sum_c"] == o["sum_c"]
 
 
+
+def test_persistent_barrier_timeout_is_an_error_then_recovers():
+    """A persistent launch whose grid-barrier waits are bounded at zero (the
+    condition forced from the host: one tick of the device clock) gives up
+    at a barrier: every workgroup leaves the kernel, the next synchronising
+    call raises the device error, and after re-initialisation with the
+    default bound the batch steps bit-identically to an untouched one."""
+    lbm = _lbm()
+    cases = _cases(3)
+    b = lbm.BatchedSweep(cases)
+    ref = lbm.BatchedSweep(cases)
+    b.set_schedule(256, 1, 1)
+    b.set_barrier_timeout(0.0)
+    b.step(8)
+    with pytest.raises(lbm.LbmError, match="timed out"):
+        b.synchronize()
+    with pytest.raises(lbm.LbmError, match="invalid argument"):
+        b.set_barrier_timeout(-1.0)
+    b.set_barrier_timeout(4.0)
+    b.init_equilibrium()
+    b.step(30)
+    ref.step(30)
+    b.synchronize()
+    for i in range(len(cases)):
+        assert torch.equal(b.populations(i), ref.populations(i)), i
+    b.close()
+    ref.close()
+
 @pytest.mark.parametrize("sched", [(64, 4, 0), (512, 2, 0), (128, 2, 1), (256, 1, 1), (64, 16, 1), (128, 1, 0, 128),
                                    (32, 2, 0, 64), (128, 1, 0, 0)])
 def test_every_schedule_gives_identical_results(sched):
