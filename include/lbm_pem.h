@@ -94,6 +94,11 @@ typedef enum lbm_status {
                               * is stored in the solid; the reaction heat is unchanged in kelvin per step */
 #define LBM_PHYSICAL_HEAT 512u /* 2D and 3D: the reaction heat with the irreversible part counted positive,
                                 * Q = -j (T dU0/dT - eta), instead of Eq. 15's printed -j (eta + T dU0/dT) */
+#define LBM_CELL_FIELDS 1024u /* batch case (2D): porosity, 1/K and D_eff are per-cell fields
+                               * (lbm_batch_set_fields; until set, each is derived from the case's layers
+                               * as lbm_set_params does with no array), and the case steps as a single
+                               * context with lbm_params.independent_fields = 1.  Every case of a batch sets
+                               * it or none (it sizes the workspace).  A single context ignores it. */
 
 typedef struct lbm_geometry {
   int32_t nx, ny;                      /* nx >= 3, ny >= 1 */
@@ -306,10 +311,11 @@ lbm_status lbm_backward(lbm_ctx* ctx, double dJ, void* grad_inv_k, void* grad_ph
  * Batched parameter sweep.  The paper's results are sweeps over operating
  * voltage, temperature, flow rate, permeability, porosity and effective
  * diffusivity (Section 5); a batch advances many such independent cases,
- * each a layered cathode (lbm_params' layered inputs, no per-cell arrays)
- * with its own lattice size, all in one precision, together.  Each case
- * computes exactly what a single context with the same geometry and
- * parameters computes (bit for bit).
+ * each with its own lattice size, all in one precision, together: layered
+ * cathodes (lbm_params' layered inputs), or, when the cases carry
+ * LBM_CELL_FIELDS, cathodes with per-cell porosity, 1/K and D_eff
+ * (lbm_batch_set_fields).  Each case computes exactly what a single context
+ * with the same geometry, parameters and fields computes (bit for bit).
  *
  * Work is cut into equal tiles of tile_x x tile_y nodes; the schedule runs
  * either one launch per step (persistent = 0) or one cooperative
@@ -331,12 +337,26 @@ typedef struct lbm_schedule {
  * tables, reduction scratch); 0 if a geometry is invalid or precisions differ. */
 size_t lbm_batch_workspace_bytes(const lbm_geometry* g, int32_t ncases);
 
-/* g[ncases], p[ncases]: per-case geometry and layered inputs, validated as
- * by lbm_set_params.  On error *out may still hold a batch so that
+/* g[ncases], p[ncases]: per-case geometry and inputs, validated as by
+ * lbm_set_params (with LBM_CELL_FIELDS the fields start derived from the
+ * layers; lbm_params.independent_fields is then implied).  On error *out may still hold a batch so that
  * lbm_batch_last_error() can explain; destroy it.  Synchronous. */
 lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t ncases, void* dev_ws,
                             size_t ws_bytes, void* hip_stream, lbm_batch** out);
 lbm_status lbm_batch_init_equilibrium(lbm_batch* b);
+/* Per-cell porosity, 1/K and D_eff of case i (Eqs. 7-8, 18-19, Section 2.2;
+ * the paper varies each of them independently in Section 5): dense
+ * [ny][nx] device arrays in the batch precision, read during the call;
+ * NULL keeps the field derived from the case's layers (1/K by
+ * Kozeny-Carman from the porosity when the case's dp_lat > 0, D_eff by
+ * Eq. 18 or deff_ratio_gdl), as lbm_set_params does for a context with
+ * independent_fields = 1, to which the case is then bit-identical.  The
+ * arrays are checked as lbm_set_params checks them (LBM_ERR_UNSTABLE_PARAMS,
+ * nothing stored).  The fields apply from the next step; the equilibrium
+ * that lbm_batch_init_equilibrium sets depends on them, so set them first.
+ * LBM_ERR_STATE unless the cases carry LBM_CELL_FIELDS.  Synchronous. */
+lbm_status lbm_batch_set_fields(lbm_batch* b, int32_t i, const void* phi, const void* inv_k,
+                                const void* d_eff);
 lbm_status lbm_batch_set_schedule(lbm_batch* b, const lbm_schedule* s);
 lbm_status lbm_batch_get_schedule(const lbm_batch* b, lbm_schedule* s);
 /* Time every candidate schedule for trial_steps steps from the current

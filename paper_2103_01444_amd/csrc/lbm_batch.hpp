@@ -24,17 +24,26 @@ struct Tile {
   int32_t c, x0, y0, pad;
 };
 
+// Per-cell fields of a batch whose cases carry them (MAT_FULL): rows 19, 20
+// and 21 of every lattice row of the case's first state buffer hold
+// porosity, 1/K and D_eff, so that they share the populations' row
+// interleave (element y * pitch + x of the planes at 19, 20, 21 rows).
+constexpr int kFieldRow = 19;
+
 // Advance cell i (row-major inside the tile) of a tile.  UNIFORM: wave-
 // uniform buffer addressing for the interior pull and the stores (batches
-// of few nodes, whose launches are one round of wavefronts).
-template <typename R, bool UNIFORM = false>
+// of few nodes, whose launches are one round of wavefronts).  MAT: the
+// material of every case, MAT_LAYERED or MAT_FULL (fields at `fields`).
+template <typename R, int MAT, bool UNIFORM = false>
 __device__ __forceinline__ void batch_cell(const R* __restrict__ src, R* __restrict__ dst, const Consts<R>& k,
-                                           const Tile& t, int i, int tx) {
+                                           const R* __restrict__ fields, const Tile& t, int i, int tx) {
   const int y = t.y0 + i / tx;
   const int x = t.x0 + i % tx;
   if (x >= k.nx || y >= k.ny) return;
   R f[19];
-  const Mat<R> mt = pre_collision<R, MAT_LAYERED, false, UNIFORM>(src, k, nullptr, nullptr, nullptr, x, y, f);
+  const R* invk_f = MAT == MAT_LAYERED ? nullptr : fields + k.plane;
+  const R* d_f = MAT == MAT_LAYERED ? nullptr : fields + 2 * k.plane;
+  const Mat<R> mt = pre_collision<R, MAT, false, UNIFORM>(src, k, fields, invk_f, d_f, x, y, f);
   collide(f, mt, k, y >= k.y_cl0 && !(k.flags & F_NO_REACTION));
   const int o = y * k.pitch + x;
   if constexpr (UNIFORM) {
@@ -50,18 +59,19 @@ __device__ __forceinline__ void batch_cell(const R* __restrict__ src, R* __restr
 // Advance the cells of one tile (tx x ty cells).  ONE: the tile has exactly
 // one cell per thread (tx ty = kBlock); without the cell loop the kernel
 // needs 59 instead of 76 VGPRs (8 instead of 6 waves per SIMD in FP32).
-template <typename R, bool ONE, bool UNIFORM = false>
+template <typename R, int MAT, bool ONE, bool UNIFORM = false>
 __device__ __forceinline__ void batch_tile(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
                                            const Tile& t, int parity, int tx, int ty) {
   const Consts<R> k = cases[t.c].k;
   const int64_t o_src = cases[t.c].off[parity], o_dst = cases[t.c].off[parity ^ 1];
   const R* src = pool + o_src;
   R* dst = pool + o_dst;
+  const R* fields = MAT == MAT_LAYERED ? nullptr : pool + cases[t.c].off[0] + int64_t(kFieldRow) * k.plane;
   if constexpr (ONE) {
-    batch_cell<R, UNIFORM>(src, dst, k, t, threadIdx.x, tx);
+    batch_cell<R, MAT, UNIFORM>(src, dst, k, fields, t, threadIdx.x, tx);
   } else {
     const int n = tx * ty;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) batch_cell<R, UNIFORM>(src, dst, k, t, i, tx);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) batch_cell<R, MAT, UNIFORM>(src, dst, k, fields, t, i, tx);
   }
 }
 
@@ -75,13 +85,13 @@ __device__ __forceinline__ int xcd_logical(int flat, int total) {
 
 // BS: workgroup size.  Tiles of exactly BS cells (64, 128 or 256) run one
 // cell per thread; other tiles loop over their cells with 256 threads.
-template <typename R, bool ONE, bool UNIFORM, int BS = kBlock>
+template <typename R, int MAT, bool ONE, bool UNIFORM, int BS = kBlock>
 __global__ __launch_bounds__(BS) void k_batch_step(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
                                                    const Tile* __restrict__ tiles, int ntiles, int parity, int tx,
                                                    int ty) {
   const int t = xcd_logical(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
-  batch_tile<R, ONE, UNIFORM>(pool, cases, tiles[t], parity, tx, ty);
+  batch_tile<R, MAT, ONE, UNIFORM>(pool, cases, tiles[t], parity, tx, ty);
 }
 
 // Waves per SIMD the persistent kernel is compiled for (at least): the
@@ -172,7 +182,7 @@ __global__ void k_clear_barrier(unsigned int* count, int* failed, int clear_fail
 }
 
 // The persistent form keeps the cell loop for every tile shape.
-template <typename R>
+template <typename R, int MAT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PersistentWaves<R>::value)))
 void k_batch_persistent(R* __restrict__ pool, const BatchCase<R>* __restrict__ cases,
                         const Tile* __restrict__ tiles, int ntiles, int nsteps, int parity0, int tx, int ty,
@@ -182,7 +192,7 @@ void k_batch_persistent(R* __restrict__ pool, const BatchCase<R>* __restrict__ c
   const int t1 = int((int64_t(lb + 1) * ntiles) / gridDim.x);
   for (int s = 0; s < nsteps; ++s) {
     const int parity = (parity0 + s) & 1;
-    for (int t = t0; t < t1; ++t) batch_tile<R, false>(pool, cases, tiles[t], parity, tx, ty);
+    for (int t = t0; t < t1; ++t) batch_tile<R, MAT, false>(pool, cases, tiles[t], parity, tx, ty);
     if (!grid_barrier(gb, unsigned(s + 1))) return;
   }
 }

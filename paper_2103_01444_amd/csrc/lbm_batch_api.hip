@@ -30,6 +30,8 @@ struct BatchLayout {
   int max_obs_blocks = 0;
   int max_nx = 0;
   size_t esize = 4;
+  int rows = 19;        // rows per lattice row of a state buffer: 19 populations (+ 3 field rows)
+  bool fields = false;  // the cases carry per-cell fields (LBM_CELL_FIELDS)
 };
 
 bool batch_geometry_ok(const lbm_geometry* g, int n) {
@@ -37,6 +39,9 @@ bool batch_geometry_ok(const lbm_geometry* g, int n) {
   for (int i = 0; i < n; ++i) {
     if (!geometry_ok(&g[i])) return false;
     if (g[i].precision != g[0].precision) return false;
+    if ((g[i].flags & LBM_CELL_FIELDS) != (g[0].flags & LBM_CELL_FIELDS)) return false;
+    if ((g[i].flags & LBM_CELL_FIELDS) && (int64_t(pitch_of(g[i].nx)) * g[i].ny * 22 >= (int64_t(1) << 31)))
+      return false;  // 32-bit element offsets with the field rows
   }
   return true;
 }
@@ -44,6 +49,8 @@ bool batch_geometry_ok(const lbm_geometry* g, int n) {
 BatchLayout make_batch_layout(const lbm_geometry* g, int n) {
   BatchLayout L;
   L.esize = g[0].precision == 64 ? 8 : 4;
+  L.fields = (g[0].flags & LBM_CELL_FIELDS) != 0;
+  L.rows = L.fields ? kFieldRow + 3 : 19;
   int64_t e = 0;
   L.state_off[0].resize(n);
   L.state_off[1].resize(n);
@@ -51,7 +58,7 @@ BatchLayout make_batch_layout(const lbm_geometry* g, int n) {
     const int64_t plane = plane_elems(int64_t(pitch_of(g[i].nx)) * g[i].ny);
     for (int s = 0; s < 2; ++s) {
       L.state_off[s][i] = e;
-      e += (19 * plane + 63) / 64 * 64;  // 256-byte aligned per buffer
+      e += (L.rows * plane + 63) / 64 * 64;  // 256-byte aligned per buffer
     }
     L.max_tiles += int((int64_t(pitch_of(g[i].nx)) * g[i].ny + kMinTileCells - 1) / kMinTileCells);
     L.max_obs_blocks = std::max(L.max_obs_blocks, ((g[i].nx + kBlock - 1) / kBlock) * g[i].ny);
@@ -62,7 +69,7 @@ BatchLayout make_batch_layout(const lbm_geometry* g, int n) {
   L.off_pool = o;
   o += align_up(size_t(e) * L.esize);
   L.off_backup = o;  // one state per case, for autotuning trials
-  o += align_up(size_t(e) * L.esize / 2 + size_t(n) * 256);
+  o += align_up(size_t(e) * L.esize / 2 + size_t(n) * 256);  // half the pool: one of the two buffers
   L.off_cases = o;
   o += align_up(size_t(n) * (L.esize == 8 ? sizeof(BatchCase<double>) : sizeof(BatchCase<float>)));
   L.off_tiles = o;
@@ -105,6 +112,11 @@ struct lbm_batch {
   R* pool() { return reinterpret_cast<R*>(ws + L.off_pool); }
   template <typename R>
   BatchCase<R>* cases() { return reinterpret_cast<BatchCase<R>*>(ws + L.off_cases); }
+  // porosity row of case i (1/K and D_eff one and two row lengths further)
+  template <typename R>
+  R* field_rows(int i) { return pool<R>() + L.state_off[0][i] + int64_t(kFieldRow) * pitch_of(g[i].nx); }
+  // elements of one state buffer of case i
+  size_t state_elems(int i) const { return size_t(L.rows) * plane_elems(int64_t(pitch_of(g[i].nx)) * g[i].ny); }
   Tile* tiles() { return reinterpret_cast<Tile*>(ws + L.off_tiles); }
   double* partial() { return reinterpret_cast<double*>(ws + L.off_partial); }
   double* prof() { return reinterpret_cast<double*>(ws + L.off_prof); }
@@ -126,6 +138,83 @@ template <>
 const Consts<float>& bconsts<float>(const lbm_batch* b, int i) { return b->kf[i]; }
 template <>
 const Consts<double>& bconsts<double>(const lbm_batch* b, int i) { return b->kd[i]; }
+
+// Fill the field rows of case i that were not given (have_* = 0) from its
+// layers and porosity, as lbm_set_params does for a context with
+// independent_fields = 1.
+template <typename R>
+lbm_status derive_case_fields(lbm_batch* b, int i, int have_phi, int have_invk, int have_d) {
+  R* f = b->field_rows<R>(i);
+  const int64_t L = pitch_of(b->g[i].nx);
+  const dim3 grid((b->g[i].nx + kBlock - 1) / kBlock, b->g[i].ny);
+  hipLaunchKernelGGL(k_derive_fields<R>, grid, dim3(kBlock), 0, b->stream, f, f + L, f + 2 * L, bconsts<R>(b, i),
+                     have_phi, have_invk, have_d);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LBM_OK : bfail(b, LBM_ERR_DEVICE, std::string("field derivation: ") + hipGetErrorString(e));
+}
+
+// Smallest and largest value of a dense device array of n elements (lo =
+// -1e300 if any is not finite).  Synchronous.
+template <typename R>
+bool device_range(hipStream_t stream, const void* dev, size_t n, double& lo, double& hi) {
+  std::vector<R> h(n);
+  if (hipMemcpyAsync(h.data(), dev, n * sizeof(R), hipMemcpyDeviceToHost, stream) != hipSuccess) return false;
+  if (hipStreamSynchronize(stream) != hipSuccess) return false;
+  for (size_t j = 0; j < n; ++j) {
+    const double v = double(h[j]);
+    if (!std::isfinite(v)) {
+      lo = -1e300;
+      return true;
+    }
+    lo = std::min(lo, v);
+    hi = std::max(hi, v);
+  }
+  return true;
+}
+
+// Per-cell fields of case i: the given arrays are checked as lbm_set_params
+// checks them, copied into the case's field rows, and the missing ones
+// derived.
+template <typename R>
+lbm_status set_fields_t(lbm_batch* b, int i, const void* phi, const void* inv_k, const void* d_eff) {
+  const lbm_geometry& g = b->g[i];
+  const lbm_params& p = b->p[i];
+  const Derived& dv = b->d[i];
+  const size_t n = size_t(g.nx) * g.ny;
+  const std::string which = "case " + std::to_string(i) + ": ";
+  double phi_lo = p.phi_gdl, phi_hi = 1.0, d_lo = std::min(dv.d_gdl, p.D_f_lat), d_hi = std::max(dv.d_gdl, p.D_f_lat);
+  double k_lo = dv.invk_gdl, k_hi = dv.invk_gdl;
+  if (phi && !device_range<R>(b->stream, phi, n, phi_lo, phi_hi))
+    return bfail(b, LBM_ERR_DEVICE, which + "reading porosity failed");
+  if (inv_k && !device_range<R>(b->stream, inv_k, n, k_lo, k_hi))
+    return bfail(b, LBM_ERR_DEVICE, which + "reading 1/K failed");
+  if (d_eff) {
+    if (!device_range<R>(b->stream, d_eff, n, d_lo, d_hi)) return bfail(b, LBM_ERR_DEVICE, which + "reading D_eff failed");
+  } else if (phi) {
+    const double dl = p.deff_ratio_gdl > 0 ? p.deff_ratio_gdl * p.D_f_lat : std::pow(phi_lo, 1.5) * p.D_f_lat;
+    d_lo = std::min(dl, p.D_f_lat);
+  }
+  if (!(phi_lo > 0) || phi_hi > 1.0) return bfail(b, LBM_ERR_UNSTABLE_PARAMS, which + "porosity outside (0, 1]");
+  if (!(k_lo >= 0)) return bfail(b, LBM_ERR_UNSTABLE_PARAMS, which + "negative or non-finite 1/K");
+  if (!(d_lo > 0) || d_hi > kMaxDiff)
+    return bfail(b, LBM_ERR_UNSTABLE_PARAMS, which + "O2 diffusivity outside (0, 1/(4 sqrt 3)]");
+  const double a1 = alpha_lat(p, phi_lo, dv.alpha_scale), a2 = alpha_lat(p, phi_hi, dv.alpha_scale);
+  const double a3 = alpha_lat(p, 1.0, dv.alpha_scale);
+  if (std::max({a1, a2, a3}) > kMaxDiff || !(std::min({a1, a2, a3}) > 0))
+    return bfail(b, LBM_ERR_UNSTABLE_PARAMS, which + "thermal diffusivity outside (0, 1/(4 sqrt 3)]");
+  R* f = b->field_rows<R>(i);
+  const int64_t L = pitch_of(g.nx);
+  const int pitch = bconsts<R>(b, i).pitch;
+  const dim3 grid((g.nx + kBlock - 1) / kBlock, g.ny);
+  const void* src[3] = {phi, inv_k, d_eff};
+  for (int c = 0; c < 3; ++c)
+    if (src[c])
+      hipLaunchKernelGGL(k_pitch_copy<R>, grid, dim3(kBlock), 0, b->stream, static_cast<const R*>(src[c]),
+                         f + c * L, g.nx, pitch);
+  if (lbm_status st = derive_case_fields<R>(b, i, phi ? 1 : 0, inv_k ? 1 : 0, d_eff ? 1 : 0); st != LBM_OK) return st;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, LBM_ERR_DEVICE, which + "field copy failed");
+  return LBM_OK;
+}
 
 template <typename R>
 lbm_status upload_cases(lbm_batch* b) {
@@ -165,9 +254,9 @@ lbm_status build_tiles(lbm_batch* b, int tx, int ty) {
 // are within what the PersistentWaves the kernel is compiled for allow
 // (the compiler's guarantee), and the kernel uses no LDS beyond a word.
 // With LBM_LOG set, both figures go to stderr.
-template <typename R>
+template <typename R, int MAT>
 lbm_status persistent_grid(lbm_batch* b, int* grid_out) {
-  const void* fn = reinterpret_cast<const void*>(&k_batch_persistent<R>);
+  const void* fn = reinterpret_cast<const void*>(&k_batch_persistent<R, MAT>);
   int dev = 0, ncu = 0, query = 0;
   hipFuncAttributes a{};
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -204,8 +293,8 @@ lbm_status barrier_status(lbm_batch* b) {
   return LBM_OK;
 }
 
-template <typename R>
-lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
+template <typename R, int MAT>
+lbm_status launch_steps_mat(lbm_batch* b, int64_t nsteps) {
   R* pool = b->pool<R>();
   const BatchCase<R>* cases = b->cases<R>();
   const Tile* tiles = b->tiles();
@@ -220,7 +309,7 @@ lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
       hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(64), 0, b->stream, gb.count, gb.failed, 0);
       void* args[] = {&pool, &cases, &tiles, &ntiles, &chunk, &par, const_cast<int*>(&tx), const_cast<int*>(&ty),
                       &gb};
-      const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch_persistent<R>),
+      const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch_persistent<R, MAT>),
                                                       dim3(grid), dim3(kBlock), args, 0, b->stream);
       if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
       b->parity = (b->parity + chunk) & 1;
@@ -238,30 +327,30 @@ lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
     for (int64_t s = 0; s < nsteps; ++s) {
       if (bs == 64) {
         if (uniform)
-          hipLaunchKernelGGL((k_batch_step<R, true, true, 64>), grid, dim3(64), 0, b->stream, pool, cases, tiles,
+          hipLaunchKernelGGL((k_batch_step<R, MAT, true, true, 64>), grid, dim3(64), 0, b->stream, pool, cases, tiles,
                              b->ntiles, b->parity, tx, ty);
         else
-          hipLaunchKernelGGL((k_batch_step<R, true, false, 64>), grid, dim3(64), 0, b->stream, pool, cases, tiles,
+          hipLaunchKernelGGL((k_batch_step<R, MAT, true, false, 64>), grid, dim3(64), 0, b->stream, pool, cases, tiles,
                              b->ntiles, b->parity, tx, ty);
       } else if (bs == 128) {
         if (uniform)
-          hipLaunchKernelGGL((k_batch_step<R, true, true, 128>), grid, dim3(128), 0, b->stream, pool, cases, tiles,
+          hipLaunchKernelGGL((k_batch_step<R, MAT, true, true, 128>), grid, dim3(128), 0, b->stream, pool, cases, tiles,
                              b->ntiles, b->parity, tx, ty);
         else
-          hipLaunchKernelGGL((k_batch_step<R, true, false, 128>), grid, dim3(128), 0, b->stream, pool, cases, tiles,
+          hipLaunchKernelGGL((k_batch_step<R, MAT, true, false, 128>), grid, dim3(128), 0, b->stream, pool, cases, tiles,
                              b->ntiles, b->parity, tx, ty);
       } else if (cells == kBlock) {
         if (uniform)
-          hipLaunchKernelGGL((k_batch_step<R, true, true>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
+          hipLaunchKernelGGL((k_batch_step<R, MAT, true, true>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
                              b->ntiles, b->parity, tx, ty);
         else
-          hipLaunchKernelGGL((k_batch_step<R, true, false>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
+          hipLaunchKernelGGL((k_batch_step<R, MAT, true, false>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
                              b->ntiles, b->parity, tx, ty);
       } else if (uniform) {
-        hipLaunchKernelGGL((k_batch_step<R, false, true>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
+        hipLaunchKernelGGL((k_batch_step<R, MAT, false, true>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
                            b->ntiles, b->parity, tx, ty);
       } else {
-        hipLaunchKernelGGL((k_batch_step<R, false, false>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
+        hipLaunchKernelGGL((k_batch_step<R, MAT, false, false>), grid, dim3(kBlock), 0, b->stream, pool, cases, tiles,
                            b->ntiles, b->parity, tx, ty);
       }
       b->parity ^= 1;
@@ -274,6 +363,11 @@ lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
 }
 
 template <typename R>
+lbm_status launch_steps(lbm_batch* b, int64_t nsteps) {
+  return b->L.fields ? launch_steps_mat<R, MAT_FULL>(b, nsteps) : launch_steps_mat<R, MAT_LAYERED>(b, nsteps);
+}
+
+template <typename R>
 lbm_status set_schedule_t(lbm_batch* b, const lbm_schedule& s) {
   if (s.tile_x < 1 || s.tile_y < 1 || s.tile_x * s.tile_y < kMinTileCells || s.tile_x * s.tile_y > 1 << 16)
     return bfail(b, LBM_ERR_INVALID_ARG, "tile shape out of range");
@@ -282,7 +376,9 @@ lbm_status set_schedule_t(lbm_batch* b, const lbm_schedule& s) {
     return bfail(b, LBM_ERR_INVALID_ARG, "workgroup size: 0 or 256, or 64 / 128 for a per-step tile of as many cells");
   b->sched = s;
   if (lbm_status st = build_tiles(b, s.tile_x, s.tile_y); st != LBM_OK) return st;
-  if (s.persistent) return persistent_grid<R>(b, &b->persistent_grid);
+  if (s.persistent)
+    return b->L.fields ? persistent_grid<R, MAT_FULL>(b, &b->persistent_grid)
+                       : persistent_grid<R, MAT_LAYERED>(b, &b->persistent_grid);
   return LBM_OK;
 }
 
@@ -290,8 +386,16 @@ template <typename R>
 lbm_status init_t(lbm_batch* b) {
   for (int i = 0; i < b->n; ++i) {
     const dim3 grid((b->g[i].nx + kBlock - 1) / kBlock, b->g[i].ny);
-    hipLaunchKernelGGL((k_init<R, MAT_LAYERED>), grid, dim3(kBlock), 0, b->stream,
-                       b->pool<R>() + b->L.state_off[0][i], nullptr, nullptr, nullptr, bconsts<R>(b, i));
+    R* dst = b->pool<R>() + b->L.state_off[0][i];
+    if (b->L.fields) {
+      const R* f = b->field_rows<R>(i);
+      const int64_t L = pitch_of(b->g[i].nx);
+      hipLaunchKernelGGL((k_init<R, MAT_FULL>), grid, dim3(kBlock), 0, b->stream, dst, f, f + L, f + 2 * L,
+                         bconsts<R>(b, i));
+    } else {
+      hipLaunchKernelGGL((k_init<R, MAT_LAYERED>), grid, dim3(kBlock), 0, b->stream, dst, nullptr, nullptr, nullptr,
+                         bconsts<R>(b, i));
+    }
   }
   hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(64), 0, b->stream, b->barrier_count(), b->barrier_failed(), 1);
   b->parity = 0;
@@ -309,8 +413,14 @@ lbm_status observables_t(lbm_batch* b, lbm_obs* out) {
     const Consts<R>& k = bconsts<R>(b, i);
     const R* src = b->pool<R>() + b->L.state_off[b->parity][i];
     const dim3 grid((g.nx + kBlock - 1) / kBlock, g.ny);
-    hipLaunchKernelGGL((k_obs_cells<R, MAT_LAYERED>), grid, dim3(kBlock), 0, b->stream, src, nullptr, nullptr,
-                       nullptr, k, b->partial());
+    if (b->L.fields) {
+      const R* f = b->field_rows<R>(i);
+      hipLaunchKernelGGL((k_obs_cells<R, MAT_FULL>), grid, dim3(kBlock), 0, b->stream, src, f, f + k.plane,
+                         f + 2 * k.plane, k, b->partial());
+    } else {
+      hipLaunchKernelGGL((k_obs_cells<R, MAT_LAYERED>), grid, dim3(kBlock), 0, b->stream, src, nullptr, nullptr,
+                         nullptr, k, b->partial());
+    }
     hipLaunchKernelGGL(k_obs_final<kObsQ>, dim3(kObsQ), dim3(kBlock), 0, b->stream, b->partial(),
                        int(grid.x * grid.y), b->out());
     double h[kObsQ];
@@ -349,7 +459,7 @@ lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double*
   std::vector<size_t> boff(b->n);
   size_t o = 0;
   for (int i = 0; i < b->n; ++i) {
-    const size_t sz = size_t(19) * plane_elems(int64_t(pitch_of(b->g[i].nx)) * b->g[i].ny) * sizeof(R);
+    const size_t sz = b->state_elems(i) * sizeof(R);
     boff[i] = o;
     if (hipMemcpyAsync(backup + o, pool + b->L.state_off[b->parity][i] * sizeof(R), sz, hipMemcpyDeviceToDevice,
                        b->stream) != hipSuccess)
@@ -406,7 +516,7 @@ lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double*
   (void)hipEventDestroy(e1);
   // Restore the saved state into the original buffers.
   for (int i = 0; i < b->n; ++i) {
-    const size_t sz = size_t(19) * plane_elems(int64_t(pitch_of(b->g[i].nx)) * b->g[i].ny) * sizeof(R);
+    const size_t sz = b->state_elems(i) * sizeof(R);
     if (hipMemcpyAsync(pool + b->L.state_off[parity0][i] * sizeof(R), backup + boff[i], sz, hipMemcpyDeviceToDevice,
                        b->stream) != hipSuccess)
       return bfail(b, LBM_ERR_DEVICE, "autotune restore failed");
@@ -463,15 +573,19 @@ lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t 
     fill_consts(b->kd[i], g[i], p[i], b->d[i], pitch_of(g[i].nx));
     // Row-interleaved state: the 19 population rows of lattice row y are
     // contiguous (element q * plane + y * pitch + x with plane = the row
-    // length and pitch = 19 row lengths), so that a tile's loads and stores
-    // stay within a few DRAM pages instead of 19 planes apart.  A layered
-    // case has no per-cell fields, so only the populations use these
-    // strides.  64-case sweep: 174.5 -> 157.7 us per step.
+    // length and pitch = 19 row lengths, 22 with the three field rows), so
+    // that a tile's loads and stores stay within a few DRAM pages instead of
+    // 19 planes apart.  64-case sweep: 174.5 -> 157.7 us per step.
     b->kf[i].plane = b->kd[i].plane = pitch_of(g[i].nx);
-    b->kf[i].pitch = b->kd[i].pitch = 19 * pitch_of(g[i].nx);
+    b->kf[i].pitch = b->kd[i].pitch = b->L.rows * pitch_of(g[i].nx);
   }
   const bool dbl = g[0].precision == 64;
   if (lbm_status st = dbl ? upload_cases<double>(b) : upload_cases<float>(b); st != LBM_OK) return st;
+  if (b->L.fields)
+    for (int i = 0; i < ncases; ++i)
+      if (lbm_status st = dbl ? derive_case_fields<double>(b, i, 0, 0, 0) : derive_case_fields<float>(b, i, 0, 0, 0);
+          st != LBM_OK)
+        return st;
   hipLaunchKernelGGL(k_clear_barrier, dim3(1), dim3(64), 0, b->stream, b->barrier_count(), b->barrier_failed(), 1);
   lbm_schedule s{256, 1, 0, 0};
   return dbl ? set_schedule_t<double>(b, s) : set_schedule_t<float>(b, s);
@@ -497,6 +611,13 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_schedule* b
   if (!b || trial_steps < 1) return LBM_ERR_INVALID_ARG;
   return b->g[0].precision == 64 ? autotune_t<double>(b, trial_steps, best, best_ms_per_step)
                                  : autotune_t<float>(b, trial_steps, best, best_ms_per_step);
+}
+
+lbm_status lbm_batch_set_fields(lbm_batch* b, int32_t i, const void* phi, const void* inv_k, const void* d_eff) {
+  if (!b || i < 0 || i >= b->n) return LBM_ERR_INVALID_ARG;
+  if (!b->L.fields) return bfail(b, LBM_ERR_STATE, "the batch's cases do not carry LBM_CELL_FIELDS");
+  return b->g[0].precision == 64 ? set_fields_t<double>(b, i, phi, inv_k, d_eff)
+                                 : set_fields_t<float>(b, i, phi, inv_k, d_eff);
 }
 
 lbm_status lbm_batch_set_barrier_timeout(lbm_batch* b, double seconds) {

@@ -40,7 +40,7 @@ inline bool geometry_ok(const lbm_geometry* g) {
   if (g->ny_channel + g->ny_gdl + g->ny_cl != g->ny) return false;
   if (g->precision != 32 && g->precision != 64) return false;
   if (g->flags & ~(LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_BODY_FORCE | LBM_NO_REACTION | LBM_PRESSURE_INLET |
-                   LBM_THIN_CL | LBM_BUOYANCY | LBM_SIGMA_ENERGY | LBM_PHYSICAL_HEAT))
+                   LBM_THIN_CL | LBM_BUOYANCY | LBM_SIGMA_ENERGY | LBM_PHYSICAL_HEAT | LBM_CELL_FIELDS))
     return false;
   if ((g->flags & LBM_THIN_CL) && (g->ny_cl != 0 || g->ny_gdl < 1 || (g->flags & LBM_PERIODIC_Y)))
     return false;  // the film lies under the GDL, at a wall

@@ -28,6 +28,7 @@ LBM_THIN_CL = 64
 LBM_BUOYANCY = 128
 LBM_SIGMA_ENERGY = 256
 LBM_PHYSICAL_HEAT = 512
+LBM_CELL_FIELDS = 1024
 LBM_KINETICS_TAFEL = 0
 LBM_KINETICS_BUTLER_VOLMER = 1
 
@@ -78,7 +79,8 @@ EXPORTED = ["lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_set_
             "lbm_set_populations",
             "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count", "lbm_synchronize",
             "lbm_destroy", "lbm_status_string", "lbm_last_error",
-            "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_init_equilibrium", "lbm_batch_set_schedule",
+            "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_init_equilibrium", "lbm_batch_set_fields",
+            "lbm_batch_set_schedule",
             "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_set_barrier_timeout", "lbm_batch_step",
             "lbm_batch_observables",
             "lbm_batch_get_populations", "lbm_batch_step_count", "lbm_batch_synchronize", "lbm_batch_destroy",
@@ -123,6 +125,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_batch_workspace_bytes": (sz, [P(Geometry), ctypes.c_int32]),
         "lbm_batch_create": (ctypes.c_int, [P(Geometry), P(Params), ctypes.c_int32, vp, sz, vp, P(vp)]),
         "lbm_batch_init_equilibrium": (ctypes.c_int, [vp]),
+        "lbm_batch_set_fields": (ctypes.c_int, [vp, ctypes.c_int32, vp, vp, vp]),
         "lbm_batch_set_schedule": (ctypes.c_int, [vp, P(Schedule)]),
         "lbm_batch_get_schedule": (ctypes.c_int, [vp, P(Schedule)]),
         "lbm_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int32, P(Schedule), P(ctypes.c_double)]),
@@ -548,9 +551,13 @@ class BatchedSweep:
     lbm_batch_*).  ``cases``: workload dictionaries (see ``workloads``), all
     of one precision.  The schedule (tile shape, per-step or persistent
     launch) is picked by ``autotune`` and cached in a JSON file keyed by GPU
-    architecture, precision and the case lattice sizes."""
+    architecture, precision and the case lattice sizes.  ``fields``: None
+    (layered cases), or one entry per case, None or a dict with any of
+    ``phi``, ``inv_k``, ``d_eff`` ([ny, nx] arrays): the cases then carry
+    per-cell fields (missing ones derived from the layers) and each steps
+    as a single ``Cathode`` with ``independent_fields=1``."""
 
-    def __init__(self, cases: list, device=None):
+    def __init__(self, cases: list, device=None, fields=None):
         if not torch.cuda.is_available():
             raise LbmError("no GPU: the solver runs only on the HIP device")
         self.lib = load_library()
@@ -561,8 +568,11 @@ class BatchedSweep:
         prec = cases[0].get("precision", 32)
         self.dtype = torch.float64 if prec == 64 else torch.float32
         self.shapes = [(w["nx"], w["ny"]) for w in cases]
+        if fields is not None and len(fields) != n:
+            raise ValueError("fields needs one entry (None or a dict) per case")
+        cell = LBM_CELL_FIELDS if fields is not None else 0
         self.geoms = (Geometry * n)(*[Geometry(w["nx"], w["ny"], w["ny_channel"], w["ny_gdl"], w["ny_cl"],
-                                               w.get("precision", 32), workload_flags(w)) for w in cases])
+                                               w.get("precision", 32), workload_flags(w) | cell) for w in cases])
         self.params = (Params * n)(*[params_from_workload(w) for w in cases])
         self.n = n
         nbytes = self.lib.lbm_batch_workspace_bytes(self.geoms, n)
@@ -575,7 +585,25 @@ class BatchedSweep:
         st = self.lib.lbm_batch_create(self.geoms, self.params, n, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.h))
         self._check(st)
+        for i, f in enumerate(fields or []):
+            if f:
+                self.set_fields(i, **f)
         self._check(self.lib.lbm_batch_init_equilibrium(self.h))
+
+    def set_fields(self, i: int, phi=None, inv_k=None, d_eff=None):
+        """Per-cell fields of case i (lbm_batch_set_fields); call
+        ``init_equilibrium`` afterwards to start from their equilibrium."""
+        nx, ny = self.shapes[i]
+        arrs = []
+        for a in (phi, inv_k, d_eff):
+            if a is None:
+                arrs.append(None)
+                continue
+            t = torch.as_tensor(a).to(device=self.device, dtype=self.dtype).contiguous()
+            if tuple(t.shape) != (ny, nx):
+                raise ValueError(f"per-cell array of case {i} must be [{ny}, {nx}]")
+            arrs.append(t)
+        self._check(self.lib.lbm_batch_set_fields(self.h, int(i), *[_ptr(a) for a in arrs]))
 
     def _check(self, st):
         if st != 0:

@@ -89,13 +89,23 @@ def test_workspace_size_and_geometry_checks(lib):
     for bad in (lbm.Geometry(2, 40, 20, 18, 2, 64, 0),      # nx < 3
                 lbm.Geometry(200, 40, 20, 18, 3, 64, 0),    # layers do not sum to ny
                 lbm.Geometry(200, 40, 20, 18, 2, 16, 0),    # precision
-                lbm.Geometry(200, 40, 20, 18, 2, 32, 1024),  # unknown flag
+                lbm.Geometry(200, 40, 20, 18, 2, 32, 2048),  # unknown flag
                 lbm.Geometry(200, 40, 20, 18, 2, 32, 64),   # thin-film CL with CL rows
                 lbm.Geometry(200, 40, 40, 0, 0, 32, 64),    # thin-film CL without a GDL
                 lbm.Geometry(200, 40, 20, 20, 0, 32, 64 | 2),  # thin-film CL with periodic y
                 lbm.Geometry(1 << 16, 1 << 12, 1 << 11, 1 << 11, 0, 32, 0)):  # 32-bit offsets
         assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
     assert lib.lbm_workspace_bytes(ctypes.byref(lbm.Geometry(200, 40, 20, 20, 0, 32, 64))) > 0
+    # batches: per-cell field rows (LBM_CELL_FIELDS) widen every case's state rows from 19 to 22; the cases
+    # of one batch must agree on the flag
+    two = (lbm.Geometry * 2)(lbm.Geometry(256, 64, 32, 29, 3, 32, 0), lbm.Geometry(512, 64, 32, 29, 3, 32, 0))
+    two_f = (lbm.Geometry * 2)(lbm.Geometry(256, 64, 32, 29, 3, 32, lbm.LBM_CELL_FIELDS),
+                               lbm.Geometry(512, 64, 32, 29, 3, 32, lbm.LBM_CELL_FIELDS))
+    mixed = (lbm.Geometry * 2)(lbm.Geometry(256, 64, 32, 29, 3, 32, lbm.LBM_CELL_FIELDS),
+                               lbm.Geometry(512, 64, 32, 29, 3, 32, 0))
+    n, n_f = lib.lbm_batch_workspace_bytes(two, 2), lib.lbm_batch_workspace_bytes(two_f, 2)
+    assert n > 0 and n_f - n >= 3 * 2 * (256 + 512) * 64 * 4 * 3 // 2
+    assert lib.lbm_batch_workspace_bytes(mixed, 2) == 0
     ctx = ctypes.c_void_p()
     assert lib.lbm_create(ctypes.byref(lbm.Geometry(2, 40, 20, 18, 2, 64, 0)), ctypes.c_void_p(256), 1 << 30,
                           None, ctypes.byref(ctx)) == 1

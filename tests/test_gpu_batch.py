@@ -134,3 +134,65 @@ def test_full_sweep_64_cases_launch_shape():
         single = lbm.Cathode.from_workload(cases[i])
         single.step(20)
         assert torch.equal(b.populations(i), single.populations()), i
+
+
+def _perturbed_fields(lbm, w, gen, which):
+    """Per-cell fields for a case: its layer-derived ones (as a context with
+    independent_fields = 1 holds them) scaled by seeded factors in the porous
+    rows; `which` names the ones returned."""
+    base = {k: v.double().cpu() for k, v in lbm.Cathode.from_workload(w, independent_fields=1).material().items()}
+    ny, nx = w["ny"], w["nx"]
+    porous = torch.zeros(ny, nx, dtype=torch.bool)
+    porous[w["ny_channel"]:] = True
+
+    def factor(lo, hi):
+        return lo + (hi - lo) * torch.rand(ny, nx, generator=gen, dtype=torch.float64)
+
+    out = {"phi": torch.where(porous, (base["phi"] * factor(0.85, 1.15)).clamp(0.3, 0.95), base["phi"]),
+           "inv_k": torch.where(porous, base["inv_k"] * factor(0.5, 2.0), base["inv_k"]),
+           "d_eff": torch.where(porous, base["d_eff"] * factor(0.8, 1.0), base["d_eff"])}
+    return {k: out[k] for k in which}
+
+
+@pytest.mark.parametrize("sched", [(128, 1, 0, 0), (256, 1, 1, 0), (64, 4, 0, 0)])
+def test_cases_with_per_cell_fields_equal_single_contexts_bitwise(sched):
+    """A batch whose cases carry per-cell fields (LBM_CELL_FIELDS): case 0
+    gets porosity, 1/K and D_eff, case 1 porosity only, case 2 none (derived
+    from its layers).  Each equals a single context with independent_fields
+    = 1 given the same arrays, bit for bit, under per-step and persistent
+    schedules."""
+    lbm = _lbm()
+    cases = _cases(3)
+    gen = torch.Generator().manual_seed(2103)
+    fields = [_perturbed_fields(lbm, cases[0], gen, ("phi", "inv_k", "d_eff")),
+              _perturbed_fields(lbm, cases[1], gen, ("phi",)), None]
+    b = lbm.BatchedSweep(cases, fields=fields)
+    b.set_schedule(*sched)
+    b.step(60)
+    obs = b.observables()
+    for i, w in enumerate(cases):
+        single = lbm.Cathode.from_workload(w, independent_fields=1, **(fields[i] or {}))
+        single.step(60)
+        assert torch.equal(b.populations(i), single.populations()), (sched, w["name"])
+        o = single.observables()
+        assert obs[i]["current_density"] == o["current_density"], (sched, w["name"])
+        assert obs[i]["heat_rate"] == o["heat_rate"], (sched, w["name"])
+        single.close()
+    b.close()
+
+
+def test_per_cell_fields_need_the_flag_and_valid_values():
+    """lbm_batch_set_fields refuses a layered batch (LBM_ERR_STATE) and a
+    porosity outside (0, 1] (LBM_ERR_UNSTABLE_PARAMS)."""
+    lbm = _lbm()
+    cases = _cases(2)
+    layered = lbm.BatchedSweep(cases)
+    with pytest.raises(lbm.LbmError, match="LBM_CELL_FIELDS"):
+        layered.set_fields(0, phi=torch.full((cases[0]["ny"], cases[0]["nx"]), 0.5))
+    layered.close()
+    b = lbm.BatchedSweep(cases, fields=[None, None])
+    bad = torch.full((cases[1]["ny"], cases[1]["nx"]), 0.5)
+    bad[-1, 3] = 1.5
+    with pytest.raises(lbm.LbmError, match="porosity"):
+        b.set_fields(1, phi=bad)
+    b.close()
