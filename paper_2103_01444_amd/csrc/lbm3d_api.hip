@@ -405,6 +405,7 @@ lbm_status lbm3d_init_equilibrium(lbm3d_ctx* c) {
 }
 
 lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
+  const lbm::TraceRange range("lbm3d_step");
   if (!c || n < 0) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
   if (c->g.precision == 64) launch_step3<double>(c, n); else launch_step3<float>(c, n);
@@ -413,6 +414,7 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
 }
 
 lbm_status lbm3d_observables(lbm3d_ctx* c, lbm_obs* out) {
+  const lbm::TraceRange range("lbm3d_observables");
   if (!c) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
   return c->g.precision == 64 ? observables3_t<double>(c, out) : observables3_t<float>(c, out);
@@ -633,6 +635,7 @@ size_t lbm3d_adjoint_workspace_bytes(const lbm3d_ctx* c, int64_t nsteps, int32_t
 
 lbm_status lbm3d_forward_checkpointed(lbm3d_ctx* c, int64_t nsteps, int32_t every, void* dev_ws, size_t ws_bytes,
                                       double* J_out) {
+  const lbm::TraceRange range("lbm3d_forward_checkpointed");
   if (!c || nsteps < 1 || every < 1 || !dev_ws) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
   if (c->mat != MAT_FULL)
@@ -666,6 +669,7 @@ lbm_status lbm3d_forward_checkpointed(lbm3d_ctx* c, int64_t nsteps, int32_t ever
 }
 
 lbm_status lbm3d_backward(lbm3d_ctx* c, double dJ, void* grad_inv_k, void* grad_phi, void* grad_d_eff) {
+  const lbm::TraceRange range("lbm3d_backward");
   if (!c) return LBM_ERR_INVALID_ARG;
   if (!c->adj_ready || c->adj_step != c->step)
     return fail3(c, LBM_ERR_STATE, "lbm3d_backward needs a preceding lbm3d_forward_checkpointed on the same state");

@@ -480,6 +480,7 @@ lbm_status lbm_init_equilibrium(lbm_ctx* c) {
 }
 
 lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  const TraceRange range("lbm_step");
   if (!c || n < 0) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
   if (c->g.precision == 64) launch_step<double>(c, n); else launch_step<float>(c, n);
@@ -488,6 +489,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
 }
 
 lbm_status lbm_observables(lbm_ctx* c, lbm_obs* out, double* pi, double* pc, double* pT) {
+  const TraceRange range("lbm_observables");
   if (!c) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
   const ObsBuffers b{c->partial(), c->out(), c->prof()};
@@ -762,6 +764,7 @@ size_t lbm_adjoint_workspace_bytes(const lbm_ctx* c, int64_t nsteps, int32_t eve
 
 lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, void* dev_ws, size_t ws_bytes,
                                     double* J_out) {
+  const TraceRange range("lbm_forward_checkpointed");
   if (!c || nsteps < 1 || every < 1 || !dev_ws) return LBM_ERR_INVALID_ARG;
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
   if (c->mat != MAT_FULL)
@@ -801,6 +804,7 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, v
 }
 
 lbm_status lbm_backward(lbm_ctx* c, double dJ, void* grad_inv_k, void* grad_phi, void* grad_d_eff) {
+  const TraceRange range("lbm_backward");
   if (!c) return LBM_ERR_INVALID_ARG;
   if (!c->adj_ready || c->adj_step != c->step)
     return fail(c, LBM_ERR_STATE, "lbm_backward needs a preceding lbm_forward_checkpointed on the same state");

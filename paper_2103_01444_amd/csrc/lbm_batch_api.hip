@@ -559,12 +559,6 @@ lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t 
   b->stream = static_cast<hipStream_t>(hip_stream);
   for (int i = 0; i < ncases; ++i) b->cells += int64_t(g[i].nx) * g[i].ny;
   *out = b;
-  int dev = 0, wall_khz = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
-    return bfail(b, LBM_ERR_DEVICE, "device wall-clock rate unavailable");
-  b->wall_khz = wall_khz;
-  b->barrier_limit = 4000LL * wall_khz;  // 4 s
   for (int i = 0; i < ncases; ++i) {
     std::string msg;
     if (lbm_status st = derive(g[i], p[i], b->d[i], msg); st != LBM_OK)
@@ -579,6 +573,12 @@ lbm_status lbm_batch_create(const lbm_geometry* g, const lbm_params* p, int32_t 
     b->kf[i].plane = b->kd[i].plane = pitch_of(g[i].nx);
     b->kf[i].pitch = b->kd[i].pitch = b->L.rows * pitch_of(g[i].nx);
   }
+  int dev = 0, wall_khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+    return bfail(b, LBM_ERR_DEVICE, "device wall-clock rate unavailable");
+  b->wall_khz = wall_khz;
+  b->barrier_limit = 4000LL * wall_khz;  // 4 s
   const bool dbl = g[0].precision == 64;
   if (lbm_status st = dbl ? upload_cases<double>(b) : upload_cases<float>(b); st != LBM_OK) return st;
   if (b->L.fields)
@@ -608,6 +608,7 @@ lbm_status lbm_batch_get_schedule(const lbm_batch* b, lbm_schedule* s) {
 }
 
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_schedule* best, double* best_ms_per_step) {
+  const TraceRange range("lbm_batch_autotune");
   if (!b || trial_steps < 1) return LBM_ERR_INVALID_ARG;
   return b->g[0].precision == 64 ? autotune_t<double>(b, trial_steps, best, best_ms_per_step)
                                  : autotune_t<float>(b, trial_steps, best, best_ms_per_step);
@@ -627,11 +628,13 @@ lbm_status lbm_batch_set_barrier_timeout(lbm_batch* b, double seconds) {
 }
 
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  const TraceRange range("lbm_batch_step");
   if (!b || nsteps < 0) return LBM_ERR_INVALID_ARG;
   return b->g[0].precision == 64 ? launch_steps<double>(b, nsteps) : launch_steps<float>(b, nsteps);
 }
 
 lbm_status lbm_batch_observables(lbm_batch* b, lbm_obs* out) {
+  const TraceRange range("lbm_batch_observables");
   if (!b || !out) return LBM_ERR_INVALID_ARG;
   return b->g[0].precision == 64 ? observables_t<double>(b, out) : observables_t<float>(b, out);
 }

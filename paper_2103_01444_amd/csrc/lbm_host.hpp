@@ -5,10 +5,21 @@
 #include <cmath>
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "lbm_device.hpp"
 #include "lbm_pem.h"
 
 namespace lbm {
+
+// A named range in profiler traces (roctx; rocprofv3 --marker-trace) over
+// one library call, for the calls that launch the hot path's kernels.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 constexpr double kMaxDiff = 0.14433756729740643;  // 1/(4 sqrt 3): b <= 1 keeps g0_eq >= 0
 
