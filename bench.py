@@ -131,7 +131,7 @@ def bench_batched(steps: int, seq_steps: int) -> dict:
     cells = sum(w["nx"] * w["ny"] for w in cases)
     b = BatchedSweep(cases)
     tune = b.autotune(trial_steps=10, cache_path=os.environ.get(
-        "LBMPEM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lbmpem_tune.json")))
+        "LBMPEM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lbmpem_batch_schedules.json")))
     b.step(20)
     wall, ev = _timed(b.stream, lambda: b.step(steps))
     obs = b.observables()
@@ -282,7 +282,7 @@ def bench_polarisation(steps: int, block: int = 500000, tol: float = 1e-4) -> di
     cells = sum(w["nx"] * w["ny"] for w in cases)
     b = BatchedSweep(cases)
     tune = b.autotune(trial_steps=10, cache_path=os.environ.get(
-        "LBMPEM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lbmpem_tune.json")))
+        "LBMPEM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lbmpem_batch_schedules.json")))
     first = min(block, steps)
     wall, ev = _timed(b.stream, lambda: b.step(first))
     done, drift = first, float("inf")

@@ -360,13 +360,20 @@ lbm_status lbm_batch_set_fields(lbm_batch* b, int32_t i, const void* phi, const 
 lbm_status lbm_batch_set_schedule(lbm_batch* b, const lbm_schedule* s);
 lbm_status lbm_batch_get_schedule(const lbm_batch* b, lbm_schedule* s);
 /* Time every candidate schedule for trial_steps steps from the current
- * state; keep the fastest, restore the state.  Synchronous.  The library
- * keeps no cache of its own: a caller that wants to skip the trials next
- * time stores *best (the Python binding keeps a JSON file keyed by GPU
- * architecture, precision and the case lattice sizes) and sets it with
- * lbm_batch_set_schedule.  A persistent candidate whose grid barrier times
- * out (lbm_batch_step) is skipped. */
+ * state; keep the fastest, restore the state.  Synchronous.  A persistent
+ * candidate whose grid barrier times out (lbm_batch_step) is skipped. */
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_schedule* best, double* best_ms_per_step);
+/* lbm_batch_autotune with a tuner cache file at cache_path (NULL: none): a
+ * JSON object holding one schedule per line, keyed by GPU architecture,
+ * precision and the case lattice sizes ("gfx950|fp32|256x64,512x128").  A
+ * usable entry for this batch is set without trials (*from_cache = 1);
+ * otherwise the trials run and the entry is added or replaced (the file is
+ * rewritten through a temporary file; concurrent writers are not
+ * coordinated).  A file in any other form is left alone and not used
+ * (lbm_batch_last_error says so; the status is that of the trials).
+ * Synchronous. */
+lbm_status lbm_batch_autotune_cached(lbm_batch* b, int32_t trial_steps, const char* cache_path, lbm_schedule* best,
+                                     double* best_ms_per_step, int32_t* from_cache);
 /* Advance every case nsteps steps.  Async.  With a persistent schedule the
  * grid is sized so that every workgroup is resident (the smaller of the
  * runtime's occupancy figure and the kernel's register budget); its

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -530,6 +531,74 @@ lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double*
   return hipStreamSynchronize(b->stream) == hipSuccess ? LBM_OK : bfail(b, LBM_ERR_DEVICE, "autotune sync failed");
 }
 
+// Tuner cache file: a JSON object with one schedule per line,
+//   "gfx950|fp32|256x64,512x128": {"tile_x": 128, "tile_y": 1, "persistent": 0, "block": 0, "ms_per_step": 0.158}
+// keyed by the GPU architecture, the precision and the case lattice sizes in
+// case order.
+std::string tune_key(const lbm_batch* b) {
+  std::string arch = "unknown";
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+  }
+  std::string k = arch + "|fp" + std::to_string(b->g[0].precision) + "|";
+  for (int i = 0; i < b->n; ++i) k += (i ? "," : "") + std::to_string(b->g[i].nx) + "x" + std::to_string(b->g[i].ny);
+  return k;
+}
+
+struct CacheEntry {
+  std::string key;
+  lbm_schedule s{};
+  double ms = 0;
+};
+
+// Entries of a cache file; false if the file exists and holds anything else
+// than the braces and entry lines (it is then neither used nor rewritten).
+bool read_cache(const char* path, std::vector<CacheEntry>& out) {
+  std::ifstream f(path);
+  if (!f) return true;  // no file yet
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t a = line.find_first_not_of(" \t\r");
+    if (a == std::string::npos) continue;
+    const std::string t = line.substr(a);
+    if (t == "{" || t == "}") continue;
+    if (t[0] != '"') return false;
+    const size_t q = t.find('"', 1);
+    if (q == std::string::npos) return false;
+    CacheEntry e;
+    e.key = t.substr(1, q - 1);
+    if (std::sscanf(t.c_str() + q + 1,
+                    ": {\"tile_x\": %d, \"tile_y\": %d, \"persistent\": %d, \"block\": %d, \"ms_per_step\": %lf}",
+                    &e.s.tile_x, &e.s.tile_y, &e.s.persistent, &e.s.block, &e.ms) != 5)
+      return false;
+    out.push_back(e);
+  }
+  return true;
+}
+
+bool write_cache(const char* path, const std::vector<CacheEntry>& entries) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return false;
+    f << "{\n";
+    for (size_t i = 0; i < entries.size(); ++i) {
+      const CacheEntry& e = entries[i];
+      char buf[256];
+      std::snprintf(buf, sizeof(buf),
+                    ": {\"tile_x\": %d, \"tile_y\": %d, \"persistent\": %d, \"block\": %d, \"ms_per_step\": %.6g}",
+                    e.s.tile_x, e.s.tile_y, e.s.persistent, e.s.block, e.ms);
+      f << '"' << e.key << '"' << buf << (i + 1 < entries.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+    if (!f) return false;
+  }
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -624,6 +693,47 @@ lbm_status lbm_batch_set_fields(lbm_batch* b, int32_t i, const void* phi, const 
 lbm_status lbm_batch_set_barrier_timeout(lbm_batch* b, double seconds) {
   if (!b || !(seconds >= 0.0) || seconds > 3600.0) return LBM_ERR_INVALID_ARG;
   b->barrier_limit = static_cast<long long>(seconds * 1000.0 * double(b->wall_khz));
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune_cached(lbm_batch* b, int32_t trial_steps, const char* cache_path, lbm_schedule* best,
+                                     double* best_ms_per_step, int32_t* from_cache) {
+  const TraceRange range("lbm_batch_autotune_cached");
+  if (!b || trial_steps < 1) return LBM_ERR_INVALID_ARG;
+  if (from_cache) *from_cache = 0;
+  if (!cache_path) return lbm_batch_autotune(b, trial_steps, best, best_ms_per_step);
+  const std::string key = tune_key(b);
+  std::vector<CacheEntry> entries;
+  const bool usable = read_cache(cache_path, entries);
+  if (usable)
+    for (const CacheEntry& e : entries)
+      if (e.key == key) {
+        const bool dbl = b->g[0].precision == 64;
+        if (lbm_status st = dbl ? set_schedule_t<double>(b, e.s) : set_schedule_t<float>(b, e.s); st != LBM_OK)
+          break;  // not usable here: tune again
+        if (best) *best = e.s;
+        if (best_ms_per_step) *best_ms_per_step = e.ms;
+        if (from_cache) *from_cache = 1;
+        return LBM_OK;
+      }
+  lbm_schedule s{};
+  double ms = 0;
+  if (lbm_status st = lbm_batch_autotune(b, trial_steps, &s, &ms); st != LBM_OK) return st;
+  if (best) *best = s;
+  if (best_ms_per_step) *best_ms_per_step = ms;
+  if (!usable) {
+    b->err = std::string("tune cache ") + cache_path + " is not in the library's format: not rewritten";
+    return LBM_OK;
+  }
+  bool found = false;
+  for (CacheEntry& e : entries)
+    if (e.key == key) {
+      e.s = s;
+      e.ms = ms;
+      found = true;
+    }
+  if (!found) entries.push_back({key, s, ms});
+  if (!write_cache(cache_path, entries)) b->err = std::string("tune cache ") + cache_path + " could not be written";
   return LBM_OK;
 }
 

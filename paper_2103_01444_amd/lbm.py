@@ -81,7 +81,8 @@ EXPORTED = ["lbm_default_params", "lbm_workspace_bytes", "lbm_create", "lbm_set_
             "lbm_destroy", "lbm_status_string", "lbm_last_error",
             "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_init_equilibrium", "lbm_batch_set_fields",
             "lbm_batch_set_schedule",
-            "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_set_barrier_timeout", "lbm_batch_step",
+            "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_autotune_cached", "lbm_batch_set_barrier_timeout",
+            "lbm_batch_step",
             "lbm_batch_observables",
             "lbm_batch_get_populations", "lbm_batch_step_count", "lbm_batch_synchronize", "lbm_batch_destroy",
             "lbm_batch_last_error", "lbm_adjoint_workspace_bytes", "lbm_forward_checkpointed", "lbm_backward",
@@ -129,6 +130,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_batch_set_schedule": (ctypes.c_int, [vp, P(Schedule)]),
         "lbm_batch_get_schedule": (ctypes.c_int, [vp, P(Schedule)]),
         "lbm_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int32, P(Schedule), P(ctypes.c_double)]),
+        "lbm_batch_autotune_cached": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_char_p, P(Schedule),
+                                                     P(ctypes.c_double), P(ctypes.c_int32)]),
         "lbm_batch_set_barrier_timeout": (ctypes.c_int, [vp, ctypes.c_double]),
         "lbm_batch_step": (ctypes.c_int, [vp, i64]),
         "lbm_batch_observables": (ctypes.c_int, [vp, P(Obs)]),
@@ -539,19 +542,12 @@ class Cathode3D:
             pass
 
 
-def _arch_name() -> str:
-    try:
-        return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
-    except Exception:
-        return "unknown"
-
-
 class BatchedSweep:
-    """Many independent layered cathode cases advanced together (C ABI
+    """Many independent cathode cases advanced together (C ABI
     lbm_batch_*).  ``cases``: workload dictionaries (see ``workloads``), all
     of one precision.  The schedule (tile shape, per-step or persistent
-    launch) is picked by ``autotune`` and cached in a JSON file keyed by GPU
-    architecture, precision and the case lattice sizes.  ``fields``: None
+    launch) is picked by ``autotune``, which the library caches in a JSON
+    file keyed by GPU architecture, precision and the case lattice sizes.  ``fields``: None
     (layered cases), or one entry per case, None or a dict with any of
     ``phi``, ``inv_k``, ``d_eff`` ([ny, nx] arrays): the cases then carry
     per-cell fields (missing ones derived from the layers) and each steps
@@ -610,10 +606,6 @@ class BatchedSweep:
             msg = self.lib.lbm_batch_last_error(self.h).decode() if self.h else ""
             raise LbmError(f"{STATUS.get(st, st)}: {msg}")
 
-    def cache_key(self) -> str:
-        prec = 64 if self.dtype == torch.float64 else 32
-        return f"{_arch_name()}|fp{prec}|" + ",".join(f"{nx}x{ny}" for nx, ny in self.shapes)
-
     @property
     def schedule(self) -> dict:
         s = Schedule()
@@ -625,28 +617,20 @@ class BatchedSweep:
         self._check(self.lib.lbm_batch_set_schedule(self.h, ctypes.byref(s)))
 
     def autotune(self, trial_steps: int = 20, cache_path: str | None = None) -> dict:
-        """Pick the fastest schedule (from the cache when present)."""
-        import json
-        key = self.cache_key()
-        cache = {}
-        if cache_path and os.path.exists(cache_path):
-            with open(cache_path) as f:
-                cache = json.load(f)
-        if key in cache:
-            c = cache[key]
-            self.set_schedule(c["tile_x"], c["tile_y"], c["persistent"], c.get("block", 0))
-            return dict(c, cached=True)
+        """Pick the fastest schedule (lbm_batch_autotune_cached: from the
+        library's tuner cache file at ``cache_path`` when it holds one for
+        this GPU, precision and set of lattice sizes)."""
         best = Schedule()
         ms = ctypes.c_double()
-        self._check(self.lib.lbm_batch_autotune(self.h, int(trial_steps), ctypes.byref(best), ctypes.byref(ms)))
-        res = dict(tile_x=best.tile_x, tile_y=best.tile_y, persistent=best.persistent, block=best.block,
-                   ms_per_step=ms.value)
+        hit = ctypes.c_int32()
+        path = None
         if cache_path:
-            cache[key] = res
             os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
-            with open(cache_path, "w") as f:
-                json.dump(cache, f, indent=1)
-        return dict(res, cached=False)
+            path = os.fsencode(cache_path)
+        self._check(self.lib.lbm_batch_autotune_cached(self.h, int(trial_steps), path, ctypes.byref(best),
+                                                       ctypes.byref(ms), ctypes.byref(hit)))
+        return dict(tile_x=best.tile_x, tile_y=best.tile_y, persistent=best.persistent, block=best.block,
+                    ms_per_step=ms.value, cached=bool(hit.value))
 
     def step(self, n: int = 1):
         self._check(self.lib.lbm_batch_step(self.h, int(n)))

@@ -63,6 +63,7 @@ def test_persistent_barrier_timeout_is_an_error_then_recovers():
     b.close()
     ref.close()
 
+
 @pytest.mark.parametrize("sched", [(64, 4, 0), (512, 2, 0), (128, 2, 1), (256, 1, 1), (64, 16, 1), (128, 1, 0, 128),
                                    (32, 2, 0, 64), (128, 1, 0, 0)])
 def test_every_schedule_gives_identical_results(sched):
@@ -94,6 +95,20 @@ def test_autotune_keeps_state_and_is_cached(tmp_path):
     b2 = lbm.BatchedSweep(cases)
     res2 = b2.autotune(trial_steps=3, cache_path=str(tmp_path / "tune.json"))
     assert res2["cached"] and b2.schedule == b.schedule
+    # the library's cache file: JSON, one entry keyed by arch, precision and the case sizes
+    import json
+    tune = json.loads((tmp_path / "tune.json").read_text())
+    (key, entry), = tune.items()
+    assert key.endswith("|fp32|" + ",".join(f"{w['nx']}x{w['ny']}" for w in cases))
+    assert {k: entry[k] for k in ("tile_x", "tile_y", "persistent", "block")} == b.schedule
+    # another batch adds its own entry; a file in another form is neither used nor rewritten
+    b3 = lbm.BatchedSweep(cases[:2])
+    assert not b3.autotune(trial_steps=3, cache_path=str(tmp_path / "tune.json"))["cached"]
+    assert len(json.loads((tmp_path / "tune.json").read_text())) == 2
+    foreign = tmp_path / "other.json"
+    foreign.write_text('{"something": [1, 2, 3]}\n')
+    assert not b3.autotune(trial_steps=3, cache_path=str(foreign))["cached"]
+    assert foreign.read_text() == '{"something": [1, 2, 3]}\n'
 
 
 def test_batch_case_matches_oracle():
