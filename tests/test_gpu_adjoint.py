@@ -259,3 +259,23 @@ def test_permeability_gradient_is_the_chain_rule_of_the_inverse():
         print(f"dJ/dK at ({y}, {x}): adjoint {float(gK[y, x]):.6e}, central difference {d:.6e}, rel {e:.1e}",
               flush=True)
         assert e < 1e-4
+
+
+@pytest.mark.parametrize("nx", [14, 130])
+def test_fp64_periodic_y_adjoint_matches_oracle_gradient(nx):
+    """Open x (inlet, outlet and the columns feeding them) with periodic y:
+    the pushes and the transposed boundary columns wrap across the y ends.
+    FP64 gradient against the oracle's exact discrete gradient."""
+    lbm = _lbm()
+    w = W.adjoint2d(nx, 10)
+    w.update(ny_channel=5, ny_gdl=4, ny_cl=1, Re=0.8, V_op=0.45, precision=64)
+    phi = W.porosity_field(w)
+    sim = lbm.Cathode.from_workload(w, phi=phi, independent_fields=1, flags=lbm.LBM_PERIODIC_Y)
+    J = sim.forward_checkpointed(40, 15)
+    g = sim.backward(1.0)
+    fields = _oracle_fields(w, phi)
+    geo = L.Geometry(nx, 10, 5, 4, 1, periodic_y=True)
+    Jo, gphi, gk, gd = A.gradient(geo, L.Params.from_workload(w), *fields, nsteps=40, every=15)
+    print(f"periodic-y {nx}x10 J gpu {J:.15e} oracle {float(Jo):.15e}", flush=True)
+    assert abs(J / float(Jo) - 1) < 1e-12
+    _compare(g, (gphi, gk, gd), w["ny_channel"], 1e-9, f"periodic-y {nx}x10 fp64")
