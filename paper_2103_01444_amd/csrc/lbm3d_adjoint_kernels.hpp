@@ -28,15 +28,92 @@ __device__ __forceinline__ void seed_mu(const R (&pre)[33], const Mat3<R>& mt, c
   }
 }
 
+// Shares of the boundary columns left for the next reverse step (open x).
+// The boundary pass of a step computes, for the column xp_s feeding each
+// boundary node (s = 0: column 1, inlet rows; s = 1: column nx - 2, every
+// row), the share of the adjoint of every element that column pulled, and
+// of the column's gradient.  The 33 shares of node (xp_s - 1 + dx, row) are
+// contiguous (padded to kPendQ) at pend[((s * nrows + row) * 3 + dx) *
+// kPendQ], so that a node near a boundary takes them in a few 16-byte
+// loads; the gradient shares c of row `row` at pend[kPendLam * nrows +
+// (s * nrows + row) * 4 + c].  Each element receives at most one share (a
+// link of the column either crosses a wall or it does not), so the
+// boundary pass writes them and every node adds its own when it loads its
+// adjoint in the next step; the last step's are added by an apply pass.
+// Slots that never receive a share hold zero.
+constexpr int kPendQ = 36;
+constexpr int kPendLam = 2 * 3 * kPendQ;
+constexpr int kPendVals = kPendLam + 2 * 4;
+
+__device__ __forceinline__ int pend_slot(int nrows, int s, int q, int dx, int row) {
+  return ((s * nrows + row) * 3 + dx) * kPendQ + q;
+}
+__device__ __forceinline__ int pend_grad(int nrows, int s, int c, int row) {
+  return kPendLam * nrows + (s * nrows + row) * 4 + c;
+}
+
+template <typename R>
+struct Vec16;  // 16 bytes of R
+template <>
+struct Vec16<float> {
+  using T = float __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using T = double __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+
+// Add the shares of node (x, row) to the adjoint la it loaded (a node near
+// both ends when nx <= 5 takes both sides').
+template <typename R>
+__device__ __forceinline__ void add_pending(R (&la)[33], const Consts3<R>& k, const R* __restrict__ pend, int x,
+                                            int row) {
+  const int nrows = k.ny * k.nz;
+  constexpr int n = Vec16<R>::n;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int dx = x - (s == 0 ? 0 : k.nx - 3);
+    if ((unsigned)dx <= 2u) {
+      const auto* v = reinterpret_cast<const typename Vec16<R>::T*>(pend + pend_slot(nrows, s, 0, dx, row));
+#pragma unroll
+      for (int i = 0; i < (33 + n - 1) / n; ++i) {
+        const typename Vec16<R>::T w = v[i];
+#pragma unroll
+        for (int j = 0; j < n; ++j)
+          if (i * n + j < 33) la[i * n + j] += w[j];
+      }
+    }
+  }
+}
+
+// The gradient shares of the feeding column at node (x, row).
+template <typename R>
+__device__ __forceinline__ void add_pending_grad(R& g0, R& g1, R& g2, const Consts3<R>& k, const R* __restrict__ pend,
+                                                 int x, int row) {
+  const int nrows = k.ny * k.nz;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (x == (s == 0 ? 1 : k.nx - 2)) {
+      g0 += pend[pend_grad(nrows, s, 0, row)];
+      g1 += pend[pend_grad(nrows, s, 1, row)];
+      g2 += pend[pend_grad(nrows, s, 2, row)];
+    }
+  }
+}
+
 template <typename R, bool SEED>
 __device__ __forceinline__ void node_mu(const R (&pre)[33], const Mat3<R>& mt, const Consts3<R>& k, bool cl,
-                                        const R* __restrict__ lam_in, int o, R w, R (&mu)[33], MatAdj3<R>& ma) {
+                                        const R* __restrict__ lam_in, const R* __restrict__ pend, int o, int x,
+                                        int row, R w, R (&mu)[33], MatAdj3<R>& ma) {
   if constexpr (SEED) {
     seed_mu(pre, mt, k, cl, w, mu);
   } else {
     R la[33];
 #pragma unroll
     for (int q = 0; q < 33; ++q) la[q] = lbm::buffer_load<R, 0>(lam_in + int64_t(q) * k.plane, uint32_t(o) * uint32_t(sizeof(R)));
+    if (pend) add_pending(la, k, pend, x, row);
     collide_adj(pre, mt, k, cl, la, mu, ma);
   }
 }
@@ -77,6 +154,7 @@ __device__ __forceinline__ void push(R* __restrict__ lam_out, const Consts3<R>& 
 template <typename R, bool SEED>
 __global__ __launch_bounds__(kBlock3) void k3_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
                                                        R* __restrict__ lam_out, R* __restrict__ grad,
+                                                       const R* __restrict__ pend,
                                                        const R* __restrict__ phi_f, const R* __restrict__ invk_f,
                                                        const R* __restrict__ d_f, Consts3<R> k, R w) {
   int x, y, z;
@@ -95,9 +173,10 @@ __global__ __launch_bounds__(kBlock3) void k3_adj_step(const R* __restrict__ S, 
     pull<R, true>(S, k, x, y, z, p);
     const Mat3<R> mt = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y, z);
     MatAdj3<R> ma{};
-    node_mu<R, SEED>(p, mt, k, cl, lam_in, o, w, mu, ma);
+    node_mu<R, SEED>(p, mt, k, cl, lam_in, pend, o, x, z * k.ny + y, w, mu, ma);
     R g0 = R(0), g1 = R(0), g2 = R(0);
     material_adj(k, mt, ma, g0, g1, g2);
+    if (pend) add_pending_grad(g0, g1, g2, k, pend, x, z * k.ny + y);
     grad[o] += g0;
     grad[k.plane + o] += g1;
     grad[2 * k.plane + o] += g2;
@@ -105,19 +184,16 @@ __global__ __launch_bounds__(kBlock3) void k3_adj_step(const R* __restrict__ S, 
   push<R, false>(lam_out, k, x, y, z, mu);
 }
 
-// Values per boundary slot in the side buffer: the feeding column's share of
-// the adjoint (33) and of its gradient (3).  Slots are [side][row], side 0
-// the inlet node of the row, side 1 the outlet node; stored plane by plane.
-constexpr int kSideVals = 36;
-
 // One reverse step, boundary pass (open x only; reads what the interior
-// pass reads, writes only the boundary nodes' gradient and the side buffer,
-// so it may run concurrently with the interior pass): one thread per
-// boundary node b fed by column xp computes b's collision adjoint on b's
-// pre-collision populations and the transposed extrapolation.
+// pass reads, writes only the boundary nodes' gradient and the shares
+// pend_out, so it may run concurrently with the interior pass): one thread
+// per boundary node b fed by column xp computes b's collision adjoint on b's
+// pre-collision populations and the transposed extrapolation.  pend_in: the
+// previous step's shares (null for the first).
 template <typename R, bool SEED>
 __global__ __launch_bounds__(64) void k3_adj_bnd(const R* __restrict__ S, const R* __restrict__ lam_in,
-                                                 R* __restrict__ grad, R* __restrict__ side,
+                                                 R* __restrict__ grad, const R* __restrict__ pend_in,
+                                                 R* __restrict__ pend_out,
                                                  const R* __restrict__ phi_f, const R* __restrict__ invk_f,
                                                  const R* __restrict__ d_f, Consts3<R> k, R w) {
   // This pass runs beside the interior pass on the same CUs and is the
@@ -149,7 +225,7 @@ __global__ __launch_bounds__(64) void k3_adj_bnd(const R* __restrict__ S, const 
 #pragma unroll
     for (int q = 0; q < 33; ++q) pre[q] = p[q];
     boundary_column(pre, k, y, z, inlet, mxp, mb);
-    node_mu<R, SEED>(pre, mb, k, cl, lam_in, row + xb, w, mub, mab);
+    node_mu<R, SEED>(pre, mb, k, cl, lam_in, pend_in, row + xb, xb, r, w, mub, mab);
   }
   R dmu[33];
 #pragma unroll
@@ -168,63 +244,44 @@ __global__ __launch_bounds__(64) void k3_adj_bnd(const R* __restrict__ S, const 
   grad[2 * k.plane + row + xb] += g2;
   g0 = g1 = g2 = R(0);
   material_adj(k, mxp, maxp, g0, g1, g2);
-  const int slots = 2 * nrows;
-#pragma unroll
-  for (int q = 0; q < 33; ++q) side[q * slots + t] = dmu[q];
-  side[33 * slots + t] = g0;
-  side[34 * slots + t] = g1;
-  side[35 * slots + t] = g2;
-}
-
-// One reverse step, apply pass (after both): one thread per (row,
-// population) adds the inlet and the outlet slot to the elements the feeding
-// columns pushed, and one thread per (row, gradient component) adds the
-// gradient shares.  For nx > 3 the two targets of a thread differ (columns 1
-// and nx - 2), so both are loaded before either is stored; for nx = 3, where
-// both feed column 1, they are added one after the other.
-template <typename R>
-__device__ __forceinline__ int apply_target(const Consts3<R>& k, int q, int xp, int y, int z) {
+  // The share of element (q, xp - e_q) of the column's pull, or across a
+  // wall of (opp q, xp) (as the pull reads them).
+  const int s = inlet ? 0 : 1;
   const bool py = k.flags & F_PERIODIC_Y, pz = k.flags & F_PERIODIC_Z;
-  const int rowp = k.pitch * k.ny;
-  const int xs = xp - EX[q];  // in [0, nx - 1]: x is open here
-  int ys = y - EY[q], zs = z - EZ[q];
-  if (py) ys = ys < 0 ? ys + k.ny : (ys >= k.ny ? ys - k.ny : ys);
-  if (pz) zs = zs < 0 ? zs + k.nz : (zs >= k.nz ? zs - k.nz : zs);
-  const bool in = (unsigned)ys < (unsigned)k.ny && (unsigned)zs < (unsigned)k.nz;
-  return in ? (q * k.plane + zs * rowp + ys * k.pitch + xs) : (OPP[q] * k.plane + z * rowp + y * k.pitch + xp);
+#pragma unroll
+  for (int q = 0; q < 33; ++q) {
+    int ys = y - EY[q], zs = z - EZ[q];
+    if (py) ys = ys < 0 ? ys + k.ny : (ys >= k.ny ? ys - k.ny : ys);
+    if (pz) zs = zs < 0 ? zs + k.nz : (zs >= k.nz ? zs - k.nz : zs);
+    const bool in = (unsigned)ys < (unsigned)k.ny && (unsigned)zs < (unsigned)k.nz;
+    const int slot = in ? pend_slot(nrows, s, q, 1 - EX[q], zs * k.ny + ys) : pend_slot(nrows, s, OPP[q], 1, r);
+    pend_out[slot] = dmu[q];
+  }
+  pend_out[pend_grad(nrows, s, 0, r)] = g0;
+  pend_out[pend_grad(nrows, s, 1, r)] = g1;
+  pend_out[pend_grad(nrows, s, 2, r)] = g2;
 }
 
+// After the last reverse step: its boundary shares added to the adjoint of
+// the initial state and to the gradient.  One thread per (population or the
+// gradient slot, row) adds both sides in turn (for nx <= 5 they reach the
+// same nodes).
 template <typename R>
-__global__ __launch_bounds__(kBlock3) void k3_adj_apply(const R* __restrict__ side, R* __restrict__ lam_out,
+__global__ __launch_bounds__(kBlock3) void k3_adj_apply(const R* __restrict__ pend, R* __restrict__ lam,
                                                         R* __restrict__ grad, Consts3<R> k) {
   const int nrows = k.ny * k.nz;
   const int t = blockIdx.x * kBlock3 + threadIdx.x;
-  if (t >= 36 * nrows) return;
-  const int q = t / nrows, r = t - q * nrows;
-  const int z = r / k.ny, y = r - z * k.ny;
-  const int slots = 2 * nrows;
-  const bool in_row = z < k.nz_ch;  // the row has an inlet node
-  const R a_in = in_row ? side[q * slots + r] : R(0);
-  const R a_out = side[q * slots + nrows + r];
-  int o_in, o_out;
-  R* base;
-  if (q < 33) {
-    base = lam_out;
-    o_in = apply_target(k, q, 1, y, z);
-    o_out = apply_target(k, q, k.nx - 2, y, z);
-  } else {
-    base = grad + int64_t(q - 33) * k.plane;
-    const int rowp = k.pitch * k.ny;
-    o_in = z * rowp + y * k.pitch + 1;
-    o_out = z * rowp + y * k.pitch + k.nx - 2;
-  }
-  if (k.nx > 3 && in_row) {
-    const R v_in = base[o_in], v_out = base[o_out];
-    base[o_in] = v_in + a_in;
-    base[o_out] = v_out + a_out;
-  } else {
-    if (in_row) base[o_in] += a_in;
-    base[o_out] += a_out;
+  if (t >= 34 * nrows) return;
+  const int q = t / nrows, row = t - q * nrows;
+  const int z = row / k.ny, y = row - z * k.ny;
+  const int o = z * k.pitch * k.ny + y * k.pitch;
+  for (int s = 0; s < 2; ++s) {
+    const int x0 = s == 0 ? 0 : k.nx - 3;
+    if (q < 33) {
+      for (int dx = 0; dx < 3; ++dx) lam[q * k.plane + o + x0 + dx] += pend[pend_slot(nrows, s, q, dx, row)];
+    } else {
+      for (int c = 0; c < 3; ++c) grad[c * k.plane + o + x0 + 1] += pend[pend_grad(nrows, s, c, row)];
+    }
   }
 }
 

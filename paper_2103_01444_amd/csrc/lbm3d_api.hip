@@ -515,7 +515,7 @@ namespace {
 struct AdjLayout3 {
   size_t state = 0;
   int nck = 0;
-  size_t off_ck = 0, off_replay = 0, off_lam = 0, off_grad = 0, off_side = 0, total = 0;
+  size_t off_ck = 0, off_replay = 0, off_lam = 0, off_grad = 0, off_pend = 0, total = 0;
 };
 
 AdjLayout3 adj_layout3(const lbm3d_ctx* c, int64_t nsteps, int32_t every) {
@@ -531,17 +531,19 @@ AdjLayout3 adj_layout3(const lbm3d_ctx* c, int64_t nsteps, int32_t every) {
   o += 2 * A.state;
   A.off_grad = o;
   o += align3(size_t(3) * c->L.plane * c->L.esize);
-  A.off_side = o;
-  o += align3(size_t(kSideVals) * 2 * c->g.ny * c->g.nz * c->L.esize);
+  A.off_pend = o;  // two buffers of boundary shares (written by one step, added by the next)
+  o += 2 * align3(size_t(kPendVals) * c->g.ny * c->g.nz * c->L.esize);
   A.total = o;
   return A;
 }
 
 // One reverse step: interior pass on the context stream and, for an open
 // channel, the boundary pass on the second stream at the same time (both
-// wait for what precedes on the context stream), then the apply pass.
+// wait for what precedes on the context stream); the context stream then
+// waits for the boundary pass, whose shares pend_out the next step adds.
 template <typename R, bool SEED>
-lbm_status reverse_step3(lbm3d_ctx* c, const R* S, const R* lam_in, R* lam_out, R* grad, R* side, R w) {
+lbm_status reverse_step3(lbm3d_ctx* c, const R* S, const R* lam_in, R* lam_out, R* grad, const R* pend_in,
+                         R* pend_out, R w) {
   const Mat3Ptrs<R> m = mat3_ptrs<R>(c);
   const Consts3<R>& k = consts3<R>(c);
   const bool open = !(c->g.flags & LBM_PERIODIC_X);
@@ -550,17 +552,13 @@ lbm_status reverse_step3(lbm3d_ctx* c, const R* S, const R* lam_in, R* lam_out, 
     if (hipEventRecord(c->ev_in, c->stream) != hipSuccess || hipStreamWaitEvent(c->aux, c->ev_in, 0) != hipSuccess)
       return fail3(c, LBM_ERR_DEVICE, "boundary pass ordering failed");
     hipLaunchKernelGGL((k3_adj_bnd<R, SEED>), dim3(unsigned((2 * nrows + 63) / 64)), dim3(64), 0, c->aux, S, lam_in,
-                       grad, side, m.phi, m.invk, m.d, k, w);
+                       grad, pend_in, pend_out, m.phi, m.invk, m.d, k, w);
     if (hipEventRecord(c->ev_bnd, c->aux) != hipSuccess) return fail3(c, LBM_ERR_DEVICE, "boundary pass event failed");
   }
   hipLaunchKernelGGL((k3_adj_step<R, SEED>), dim3(unsigned(c->L.nblocks_obs)), dim3(kBlock3), 0, c->stream, S, lam_in,
-                     lam_out, grad, m.phi, m.invk, m.d, k, w);
-  if (open) {
-    if (hipStreamWaitEvent(c->stream, c->ev_bnd, 0) != hipSuccess)
-      return fail3(c, LBM_ERR_DEVICE, "boundary pass join failed");
-    hipLaunchKernelGGL(k3_adj_apply<R>, dim3(unsigned((36 * int64_t(nrows) + kBlock3 - 1) / kBlock3)), dim3(kBlock3), 0,
-                       c->stream, side, lam_out, grad, k);
-  }
+                     lam_out, grad, open ? pend_in : nullptr, m.phi, m.invk, m.d, k, w);
+  if (open && hipStreamWaitEvent(c->stream, c->ev_bnd, 0) != hipSuccess)
+    return fail3(c, LBM_ERR_DEVICE, "boundary pass join failed");
   return LBM_OK;
 }
 
@@ -572,7 +570,10 @@ lbm_status backward3_t(lbm3d_ctx* c, double dJ, void* g_invk, void* g_phi, void*
   const Consts3<R> k = consts3<R>(c);
   const dim3 grid(unsigned(c->L.nblocks_obs));
   R* grad = reinterpret_cast<R*>(ws + A.off_grad);
-  R* side = reinterpret_cast<R*>(ws + A.off_side);
+  const bool open = !(c->g.flags & LBM_PERIODIC_X);
+  const int64_t npend = int64_t(kPendVals) * c->g.ny * c->g.nz;
+  R* pend[2] = {reinterpret_cast<R*>(ws + A.off_pend),
+                reinterpret_cast<R*>(ws + A.off_pend + align3(size_t(npend) * c->L.esize))};
   R* lam[2] = {reinterpret_cast<R*>(ws + A.off_lam), reinterpret_cast<R*>(ws + A.off_lam + A.state)};
   if (!c->aux) {
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
@@ -586,14 +587,18 @@ lbm_status backward3_t(lbm3d_ctx* c, double dJ, void* g_invk, void* g_phi, void*
   const int64_t ngrad = int64_t(3) * c->L.plane;
   hipLaunchKernelGGL(k3_fill<R>, dim3(unsigned((ngrad + kBlock3 - 1) / kBlock3)), dim3(kBlock3), 0, c->stream, grad,
                      ngrad, R(0));
+  if (open)  // shares never written (rows without an inlet, ...) stay zero
+    for (R* b : pend)
+      hipLaunchKernelGGL(k3_fill<R>, dim3(unsigned((npend + kBlock3 - 1) / kBlock3)), dim3(kBlock3), 0, c->stream, b,
+                         npend, R(0));
   // Seed: adjoint of J = mean over (x, y) of sum_CL 4 F C_ref s_c / dt * dx.
   const lbm_params& p = c->p;
   const double w = dJ * c->d.dx / (double(c->g.nx) * c->g.ny) * 4.0 * p.faraday * p.C_ref / c->d.dt;
-  if (lbm_status st = reverse_step3<R, true>(c, static_cast<const R*>(c->state(c->cur)), nullptr, lam[0], grad, side,
-                                             R(w));
+  if (lbm_status st = reverse_step3<R, true>(c, static_cast<const R*>(c->state(c->cur)), nullptr, lam[0], grad,
+                                             nullptr, pend[0], R(w));
       st != LBM_OK)
     return st;
-  int cur = 0;
+  int cur = 0, pc = 0;  // pend[pc]: the shares the next reverse step adds
   for (int seg = A.nck - 1; seg >= 0; --seg) {
     const int64_t start = int64_t(seg) * c->adj_every;
     const int len = int(std::min<int64_t>(c->adj_every, c->adj_nsteps - start));
@@ -607,12 +612,16 @@ lbm_status backward3_t(lbm3d_ctx* c, double dJ, void* g_invk, void* g_phi, void*
                          reinterpret_cast<R*>(replay + size_t(j) * A.state), m.phi, m.invk, m.d, k);
     for (int j = len - 1; j >= 0; --j) {
       if (lbm_status st = reverse_step3<R, false>(c, reinterpret_cast<const R*>(replay + size_t(j) * A.state),
-                                                  lam[cur], lam[cur ^ 1], grad, side, R(0));
+                                                  lam[cur], lam[cur ^ 1], grad, pend[pc], pend[pc ^ 1], R(0));
           st != LBM_OK)
         return st;
       cur ^= 1;
+      pc ^= 1;
     }
   }
+  if (open)  // the last reverse step's boundary shares
+    hipLaunchKernelGGL(k3_adj_apply<R>, dim3(unsigned((34 * int64_t(c->g.ny) * c->g.nz + kBlock3 - 1) / kBlock3)),
+                       dim3(kBlock3), 0, c->stream, pend[pc], lam[cur], grad, k);
   hipLaunchKernelGGL(k3_adj_init<R>, c->grid3(), dim3(kBlock3), 0, c->stream, lam[cur], grad, k);
   void* outs[3] = {g_phi, g_invk, g_d};
   for (int i = 0; i < 3; ++i)
