@@ -182,8 +182,10 @@ def test_cases_with_per_cell_fields_equal_single_contexts_bitwise(sched):
     fields = [_perturbed_fields(lbm, cases[0], gen, ("phi", "inv_k", "d_eff")),
               _perturbed_fields(lbm, cases[1], gen, ("phi",)), None]
     b = lbm.BatchedSweep(cases, fields=fields)
+    b.step(10)
+    b.autotune(trial_steps=2)  # trials from the live state, restored after (fields untouched)
     b.set_schedule(*sched)
-    b.step(60)
+    b.step(50)
     obs = b.observables()
     for i, w in enumerate(cases):
         single = lbm.Cathode.from_workload(w, independent_fields=1, **(fields[i] or {}))
