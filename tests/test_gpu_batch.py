@@ -169,15 +169,16 @@ def _perturbed_fields(lbm, w, gen, which):
     return {k: out[k] for k in which}
 
 
-@pytest.mark.parametrize("sched", [(128, 1, 0, 0), (256, 1, 1, 0), (64, 4, 0, 0)])
-def test_cases_with_per_cell_fields_equal_single_contexts_bitwise(sched):
+@pytest.mark.parametrize("sched,precision", [((128, 1, 0, 0), 32), ((256, 1, 1, 0), 32), ((64, 4, 0, 0), 32),
+                                             ((256, 1, 0, 0), 64), ((128, 2, 1, 0), 64)])
+def test_cases_with_per_cell_fields_equal_single_contexts_bitwise(sched, precision):
     """A batch whose cases carry per-cell fields (LBM_CELL_FIELDS): case 0
     gets porosity, 1/K and D_eff, case 1 porosity only, case 2 none (derived
     from its layers).  Each equals a single context with independent_fields
     = 1 given the same arrays, bit for bit, under per-step and persistent
     schedules."""
     lbm = _lbm()
-    cases = _cases(3)
+    cases = [dict(w, precision=precision) for w in _cases(3)]
     gen = torch.Generator().manual_seed(2103)
     fields = [_perturbed_fields(lbm, cases[0], gen, ("phi", "inv_k", "d_eff")),
               _perturbed_fields(lbm, cases[1], gen, ("phi",)), None]
@@ -190,10 +191,10 @@ def test_cases_with_per_cell_fields_equal_single_contexts_bitwise(sched):
     for i, w in enumerate(cases):
         single = lbm.Cathode.from_workload(w, independent_fields=1, **(fields[i] or {}))
         single.step(60)
-        assert torch.equal(b.populations(i), single.populations()), (sched, w["name"])
+        assert torch.equal(b.populations(i), single.populations()), (sched, precision, w["name"])
         o = single.observables()
-        assert obs[i]["current_density"] == o["current_density"], (sched, w["name"])
-        assert obs[i]["heat_rate"] == o["heat_rate"], (sched, w["name"])
+        assert obs[i]["current_density"] == o["current_density"], (sched, precision, w["name"])
+        assert obs[i]["heat_rate"] == o["heat_rate"], (sched, precision, w["name"])
         single.close()
     b.close()
 
