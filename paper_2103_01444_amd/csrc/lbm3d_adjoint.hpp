@@ -254,6 +254,7 @@ __device__ __forceinline__ void collide_adj(const R (&f)[33], const Mat3<R>& mt,
     ma.rhocp += -rx.S_T * irc * lsrc[0];
     lX[1] += rx.dsc_dc * lsc;
     lX[0] += rx.dsc_dth * lsc;
+    if (k.flags & lbm::F_PHYSICAL_HEAT) lX[0] += k.four_f_cref * rx.s_c * R(2) * k.U0_slope * irc * lsrc[0];
   }
 #pragma unroll
   for (int q = 0; q < 7; ++q) {

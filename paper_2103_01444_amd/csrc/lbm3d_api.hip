@@ -649,10 +649,6 @@ lbm_status lbm3d_forward_checkpointed(lbm3d_ctx* c, int64_t nsteps, int32_t ever
   if (!c->params_set) return fail3(c, LBM_ERR_STATE, "lbm3d_set_params first");
   if (c->mat != MAT_FULL)
     return fail3(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
-  if (c->p.kinetics != LBM_KINETICS_TAFEL)
-    return fail3(c, LBM_ERR_STATE, "the adjoint covers the Tafel kinetics only (kinetics = LBM_KINETICS_TAFEL)");
-  if (c->g.flags & LBM_PHYSICAL_HEAT)
-    return fail3(c, LBM_ERR_STATE, "the adjoint covers Eq. 15's printed heat, not LBM_PHYSICAL_HEAT");
   const AdjLayout3 A = adj_layout3(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign3 != 0)
     return fail3(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

@@ -207,6 +207,14 @@ struct ReactAdj {
   R s_c, S_T, ehs, dsc_dc, dsc_dth;
 };
 
+// Tape of the CL reaction (Eqs. 12-17 as the forward step computes them,
+// Tafel or Butler-Volmer, printed or physical heat) and its derivatives:
+// s_c = -(c - c_eq) expm1(-kappa), c_eq = exp(alpha_sum F eta / (R T)) with
+// Butler-Volmer (0 with Tafel), S_T = 4 F C_ref s_c ehs / (rho c_p).  With
+// the printed heat ehs = eta + T dU0/dT = V - U0(0) does not depend on T;
+// with the physical heat ehs = -eta + T dU0/dT has dehs/dT = 2 dU0/dT, which
+// the callers add to the temperature adjoint.
+
 template <typename R, typename K>
 __device__ __forceinline__ ReactAdj<R> reaction_tape(R theta, R c, R rhocp, const K& k) {
   const R T = k.T_in + theta;
@@ -214,15 +222,17 @@ __device__ __forceinline__ ReactAdj<R> reaction_tape(R theta, R c, R rhocp, cons
   const R eta = k.V_op - (k.U0_slope * T + k.U0_icept);
   const R kappa = exp(k.ln_k0 - k.E_over_R * (iT - k.inv_T_arrh) - k.aF_over_R * eta * iT);
   const R em = expm1(-kappa);
+  const R ceq = k.bv ? exp(k.aFsum_over_R * eta * iT) : R(0);
   ReactAdj<R> r;
-  r.s_c = -c * em;
-  r.ehs = eta + T * k.U0_slope;
+  r.s_c = -(c - ceq) * em;
+  r.ehs = ((k.flags & F_PHYSICAL_HEAT) ? -eta : eta) + T * k.U0_slope;
   r.S_T = k.four_f_cref * r.s_c * r.ehs / rhocp;
   // dE/dT of the exponent E = ln_k0 - E/R (1/T - 1/T0) - aF/R eta / T, with
-  // deta/dT = -U0_slope.
+  // deta/dT = -U0_slope; dc_eq/dT = -c_eq alpha_sum F/R (U0_slope / T + eta / T^2).
   const R dE = k.E_over_R * iT * iT + k.aF_over_R * k.U0_slope * iT + k.aF_over_R * eta * iT * iT;
   r.dsc_dc = -em;
-  r.dsc_dth = c * (em + R(1)) * kappa * dE;
+  r.dsc_dth = (c - ceq) * (em + R(1)) * kappa * dE;
+  if (k.bv) r.dsc_dth -= em * ceq * k.aFsum_over_R * (k.U0_slope * iT + eta * iT * iT);
   return r;
 }
 
@@ -284,6 +294,7 @@ __device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, 
     ma.rhocp += -rx.S_T * irc * lST;
     lX[1] += rx.dsc_dc * lsc;
     lX[0] += rx.dsc_dth * lsc;
+    if (k.flags & F_PHYSICAL_HEAT) lX[0] += k.four_f_cref * rx.s_c * R(2) * k.U0_slope * irc * lST;
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) {

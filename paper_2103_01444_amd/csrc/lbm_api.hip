@@ -771,14 +771,12 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, v
     return fail(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
   if (c->g.flags & LBM_PRESSURE_INLET)
     return fail(c, LBM_ERR_STATE, "the adjoint covers the velocity inlet, not LBM_PRESSURE_INLET");
-  if (c->p.kinetics != LBM_KINETICS_TAFEL)
-    return fail(c, LBM_ERR_STATE, "the adjoint covers the Tafel kinetics only (kinetics = LBM_KINETICS_TAFEL)");
   if (c->g.flags & LBM_THIN_CL)
     return fail(c, LBM_ERR_STATE, "the adjoint covers the volumetric CL, not LBM_THIN_CL");
   if (c->g.flags & LBM_BUOYANCY)
     return fail(c, LBM_ERR_STATE, "the adjoint does not cover LBM_BUOYANCY");
-  if (c->g.flags & (LBM_SIGMA_ENERGY | LBM_PHYSICAL_HEAT))
-    return fail(c, LBM_ERR_STATE, "the adjoint covers the printed energy equation and heat only");
+  if (c->g.flags & LBM_SIGMA_ENERGY)
+    return fail(c, LBM_ERR_STATE, "the adjoint covers the printed energy equation, not LBM_SIGMA_ENERGY");
   const AdjLayout A = adj_layout(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign != 0)
     return fail(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

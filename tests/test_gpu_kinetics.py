@@ -2,7 +2,8 @@
 Eq. 13 with its anodic branch) on the GPU against the FP64 oracle: one
 step of arbitrary states (2D and 3D, every material mode), FP64 runs with
 their observables near the equilibrium potential where the anodic branch
-matters, the batched solver, and the adjoint's refusal."""
+matters, and the batched solver.  The adjoint with these kinetics is
+tested with the other adjoint parity cases."""
 import numpy as np
 import pytest
 import torch
@@ -108,11 +109,3 @@ def test_butler_volmer_case_in_a_batch_equals_its_single_context():
         s = lbm.Cathode.from_workload(w)
         s.step(120)
         assert torch.equal(b.populations(i), s.populations()), w["name"]
-
-
-def test_adjoint_rejects_butler_volmer():
-    lbm = _lbm()
-    w = dict(W.cathode2d_200x40(), nx=40, ny=10, ny_channel=5, ny_gdl=4, ny_cl=1, precision=64, Re=2.0, **BV)
-    sim = lbm.Cathode.from_workload(w, independent_fields=1)
-    with pytest.raises(lbm.LbmError, match="Tafel"):
-        sim.forward_checkpointed(10, 5)
