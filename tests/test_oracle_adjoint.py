@@ -2,6 +2,7 @@
 oracle) against central finite differences of the oracle's forward map,
 which share no differentiation machinery.  CPU only."""
 import numpy as np
+import pytest
 import torch
 
 import workloads as W
@@ -11,9 +12,10 @@ from oracle import lbm2d as L
 DT = torch.float64
 
 
-def _case(nx=14, ny=10, layers=(5, 4, 1), seed=3):
+def _case(nx=14, ny=10, layers=(5, 4, 1), seed=3, **over):
     w = W.adjoint2d(nx, ny)
     w.update(ny_channel=layers[0], ny_gdl=layers[1], ny_cl=layers[2], Re=2.0, V_op=0.45)
+    w.update(over)
     rng = np.random.default_rng(seed)
     phi = np.ones((ny, nx))
     phi[layers[0]:] = rng.uniform(0.4, 0.8, size=(ny - layers[0], nx))
@@ -95,5 +97,28 @@ def test_gradient_along_a_dense_direction():
             for s in (1, -1)]
     fd = (vals[0] - vals[1]) / (2 * h)
     print(f"<grad, d> {dot:.15e}, forward mode {jvp:.15e}, central difference {fd:.15e}")
+    assert abs(dot / jvp - 1) < 1e-12
+    assert abs(dot / fd - 1) < 1e-6
+
+
+@pytest.mark.parametrize("option", [dict(butler_volmer=True, alpha_a=0.5, V_op=1.1, aj0_ref=1e5),
+                                    dict(heat_physical=True)], ids=["butler_volmer", "heat_physical"])
+def test_gradient_along_a_dense_direction_with_kinetics_or_heat_option(option):
+    """The same identity with Butler-Volmer kinetics near the equilibrium
+    potential (Eq. 13 with its anodic branch) and with the physically signed
+    reaction heat, whose reverse terms the default case does not reach."""
+    g, p, fields = _case(**option)
+    assert p.butler_volmer == option.get("butler_volmer", False)
+    assert p.heat_physical == option.get("heat_physical", False)
+    nsteps = 40
+    _, *grads = A.gradient(g, p, *fields, nsteps=nsteps, every=15)
+    dirs = _dense_direction(fields, g.ny_channel, seed=8)
+    dot = sum(float((gr * d).sum()) for gr, d in zip(grads, dirs))
+    jvp = forward_mode_derivative(g, p, fields, dirs, nsteps)
+    h = 1e-6
+    vals = [float(A.mean_current_density(g, p, *[f + s * h * d for f, d in zip(fields, dirs)], nsteps=nsteps))
+            for s in (1, -1)]
+    fd = (vals[0] - vals[1]) / (2 * h)
+    print(f"{option}: <grad, d> {dot:.15e}, forward mode {jvp:.15e}, central difference {fd:.15e}")
     assert abs(dot / jvp - 1) < 1e-12
     assert abs(dot / fd - 1) < 1e-6
