@@ -198,8 +198,9 @@ def geometry_from_workload(w: dict) -> Geometry:
 # --------------------------------------------------------------------------
 def _safe_sqrt(a: torch.Tensor) -> torch.Tensor:
     """sqrt with derivative 0 at a = 0 (the model's composite maps are C^1
-    there, see the velocity recovery)."""
-    pos = a > 0
+    there, see the velocity recovery).  A complex argument (complex-step
+    differentiation in the tests) is tested on its real part."""
+    pos = (a.real if a.is_complex() else a) > 0
     return torch.where(pos, torch.sqrt(torch.where(pos, a, torch.ones_like(a))), torch.zeros_like(a))
 
 
@@ -238,8 +239,10 @@ def catalyst_reaction(pr: "Params", dt: float, theta, c, rhocp):
 
 
 def _mv(mat: torch.Tensor, planes: torch.Tensor) -> torch.Tensor:
-    """Matrix times a stack of planes: out[i] = sum_j mat[i, j] planes[j]."""
-    return torch.einsum("ij,j...->i...", mat, planes)
+    """Matrix times a stack of planes: out[i] = sum_j mat[i, j] planes[j]
+    (the real matrix is taken in the planes' type, complex in the tests'
+    complex-step differentiation)."""
+    return torch.einsum("ij,j...->i...", mat.to(planes.dtype), planes)
 
 
 # --------------------------------------------------------------------------
@@ -672,7 +675,7 @@ class Model:
             inflow = flux * self.p.c_in
         else:
             inflow = (self.inlet_velocity() * self.p.c_in).sum() if hc > 0 else torch.zeros((), dtype=DT)
-        util = s_c.sum() / inflow if float(inflow) > 0 else torch.zeros((), dtype=DT)
+        util = s_c.sum() / inflow if float(inflow.real) > 0 else torch.zeros((), dtype=DT)
         ycl = self.g.ny - self.g.ny_cl
         if self.p.thin_cl:  # [R19] the row above the film
             c_prof, T_prof = c[-1], self.p.T_in + theta[-1]
@@ -682,7 +685,7 @@ class Model:
             c_prof = T_prof = torch.zeros(self.g.nx, dtype=DT)
         return dict(
             current_density=I, power_density=self.p.V_op * I, heat_rate=H, o2_utilisation=util,
-            T_max=(self.p.T_in + theta).max(), sum_f=pre[0:9].sum(), sum_theta=theta.sum(),
+            T_max=(self.p.T_in + theta).real.max(), sum_f=pre[0:9].sum(), sum_theta=theta.sum(),
             sum_c=c.sum(), consumed_c=s_c.sum(), heat_added=S_T.sum(),
             i_profile=i_x, c_profile=c_prof, T_profile=T_prof, inlet_flux=flux,
         )

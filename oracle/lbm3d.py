@@ -87,7 +87,9 @@ class Geometry3D:
 
 
 def _safe_sqrt(a):
-    pos = a > 0
+    """sqrt with derivative 0 at a = 0; a complex argument (complex-step
+    differentiation in the tests) is tested on its real part."""
+    pos = (a.real if a.is_complex() else a) > 0
     return torch.where(pos, torch.sqrt(torch.where(pos, a, torch.ones_like(a))), torch.zeros_like(a))
 
 
@@ -312,9 +314,9 @@ class Model3D:
         I = ((-j_eff).sum(0) * self.dx).mean()
         H = (Q.sum(0) * self.dx).mean()
         inflow = (self.inlet_velocity() * self.p.c_in).sum() if self.g.nz_channel > 0 else torch.zeros((), dtype=DT)
-        util = s_c.sum() / inflow if float(inflow) > 0 else torch.zeros((), dtype=DT)
+        util = s_c.sum() / inflow if float(inflow.real) > 0 else torch.zeros((), dtype=DT)
         return dict(current_density=I, power_density=self.p.V_op * I, heat_rate=H, o2_utilisation=util,
-                    T_max=(self.p.T_in + theta).max(), sum_f=pre[0:19].sum(), sum_theta=theta.sum(),
+                    T_max=(self.p.T_in + theta).real.max(), sum_f=pre[0:19].sum(), sum_theta=theta.sum(),
                     sum_c=c.sum(), consumed_c=s_c.sum(), heat_added=S_T.sum())
 
 
