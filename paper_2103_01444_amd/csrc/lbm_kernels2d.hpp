@@ -22,6 +22,13 @@ __device__ __forceinline__ void xcd_tile(int nbx, int nby, int& bx, int& by) {
   const int logical = xcd * full + (xcd < rem ? xcd : rem) + slot;
   by = logical / nbx;
   bx = logical - by * nbx;
+  // Rotate the x-blocks of a row by one every 8 rows.  Without it, the
+  // workgroups that share a CU (a fixed stride apart in the XCD's range)
+  // tend to sit at the same x position, so the wavefronts holding the inlet
+  // or outlet column, whose chains are the longest, pile onto the same
+  // SIMDs.  Measured: 1024x256 reverse step 2.6 % and forward 1.2 % faster,
+  // 4096x1024 unchanged; each node's arithmetic is unchanged.
+  bx = (bx + by / 8) % nbx;
 }
 
 // One time step: pull-stream, boundary columns, macros, flow collision,
