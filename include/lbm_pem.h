@@ -304,10 +304,12 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* ctx, int64_t nsteps, int32_t every,
 /* dJ times dJ/d(1/K), dJ/dphi, dJ/dD_eff of the preceding checkpointed run,
  * written (not accumulated) into caller device arrays [ny][nx] (context
  * precision; NULL skips one).  Replays each segment from its checkpoint and
- * sweeps it in reverse; the replays run on a second HIP stream the library
- * creates on first use (default priority, ordered by events, destroyed by
- * lbm_destroy).  Synchronous.  LBM_ERR_STATE without a matching
- * lbm_forward_checkpointed (or after the state was changed since). */
+ * sweeps it in reverse (the first call after a forward run finds the last
+ * segment's states already in dev_ws); the replays run on a second HIP
+ * stream the library creates on first use (default priority, ordered by
+ * events, destroyed by lbm_destroy).  May be called again for the same run.
+ * Synchronous.  LBM_ERR_STATE without a matching lbm_forward_checkpointed
+ * (or after the state was changed since). */
 lbm_status lbm_backward(lbm_ctx* ctx, double dJ, void* grad_inv_k, void* grad_phi, void* grad_d_eff);
 
 /* ---------------------------------------------------------------------------

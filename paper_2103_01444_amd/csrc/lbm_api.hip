@@ -83,6 +83,7 @@ struct lbm_ctx {
   int32_t adj_every = 0;
   int64_t adj_step = -1;
   bool adj_ready = false;
+  bool adj_last_resident = false;  // replay buffer 0 holds the last segment's states
   // second stream and events of the reverse sweep: the replay of the next
   // segment runs there while the current one is swept
   hipStream_t aux = nullptr;
@@ -672,6 +673,23 @@ void launch_one_step(lbm_ctx* c, const void* src, void* dst, hipStream_t stream)
                                   stream);
 }
 
+// The last segment of the checkpointed forward run steps through replay
+// buffer 0 (the same kernel as lbm_step, so the same states), where the
+// first reverse sweep reads them: lbm_backward need not replay it.
+template <typename R>
+lbm_status forward_last_segment(lbm_ctx* c, const AdjLayout& A, int64_t n) {
+  char* buf = c->adj_ws + A.off_replay;
+  const size_t sb = size_t(19) * c->L.plane * c->L.esize;
+  if (hipMemcpyAsync(buf, c->state(c->cur), sb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, LBM_ERR_DEVICE, "replay buffer copy failed");
+  for (int64_t j = 1; j < n; ++j)
+    launch_one_step<R>(c, buf + size_t(j - 1) * A.state, buf + size_t(j) * A.state, c->stream);
+  launch_one_step<R>(c, buf + size_t(n - 1) * A.state, c->state(c->cur ^ 1), c->stream);
+  c->cur ^= 1;
+  c->step += n;
+  return check_launch(c, "forward_checkpointed");
+}
+
 template <typename R>
 lbm_status backward_t(lbm_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_d) {
   const AdjLayout A = adj_layout(c, c->adj_nsteps, c->adj_every);
@@ -724,7 +742,12 @@ lbm_status backward_t(lbm_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_
     if (hipEventRecord(c->ev_rep[b], c->aux) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "replay event failed");
     return LBM_OK;
   };
-  if (lbm_status st = replay(A.nck - 1, 0); st != LBM_OK) return st;
+  if (c->adj_last_resident) {  // written on this stream by the forward run
+    if (hipEventRecord(c->ev_rep[0], c->stream) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "replay event failed");
+  } else if (lbm_status st = replay(A.nck - 1, 0); st != LBM_OK) {
+    return st;
+  }
+  c->adj_last_resident = false;  // the sweep below reuses buffer 0
   int cur = 0;
   for (int seg = A.nck - 1; seg >= 0; --seg) {
     const int b = (A.nck - 1 - seg) & 1;
@@ -791,8 +814,15 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, v
                        c->stream) != hipSuccess)
       return fail(c, LBM_ERR_DEVICE, "checkpoint copy failed");
     const int64_t n = std::min<int64_t>(every, nsteps - int64_t(seg) * every);
-    if (lbm_status s = lbm_step(c, n); s != LBM_OK) return s;
+    if (seg == A.nck - 1) {
+      const lbm_status s = c->g.precision == 64 ? forward_last_segment<double>(c, A, n)
+                                                : forward_last_segment<float>(c, A, n);
+      if (s != LBM_OK) return s;
+    } else if (lbm_status s = lbm_step(c, n); s != LBM_OK) {
+      return s;
+    }
   }
+  c->adj_last_resident = true;
   lbm_obs o{};
   if (lbm_status s = lbm_observables(c, &o, nullptr, nullptr, nullptr); s != LBM_OK) return s;
   if (J_out) *J_out = o.current_density;

@@ -212,6 +212,24 @@ def test_checkpoint_interval_does_not_change_the_gradient():
             assert torch.equal(g[name], ref_g[name]), (every, name)
 
 
+def test_second_backward_replays_the_last_segment():
+    """The checkpointed forward run leaves its last segment's states in the
+    replay buffer, where the first backward reads them; a second backward
+    after the same forward run replays that segment from its checkpoint and
+    gives the same gradient, bit for bit (last segments of 5, 10 and 1
+    steps, and one segment of the whole run)."""
+    lbm = _lbm()
+    w = W.adjoint2d(40, 10)
+    w.update(ny_channel=5, ny_gdl=4, ny_cl=1, Re=2.0, V_op=0.45)
+    sim = lbm.Cathode.from_workload(w, phi=W.porosity_field(w), independent_fields=1)
+    for every in (7, 10, 1, 100):
+        sim.forward_checkpointed(40, every)
+        first = {k: v.clone() for k, v in sim.backward(1.0).items()}
+        second = sim.backward(1.0)
+        for name in ("phi", "inv_k", "d_eff"):
+            assert torch.equal(first[name], second[name]), (every, name)
+
+
 def test_backward_needs_a_checkpointed_forward():
     lbm = _lbm()
     w = W.adjoint2d(64, 16)
