@@ -17,13 +17,18 @@
 
 namespace lbm {
 
+// EXT: the instances of the reverse step that also cover Boussinesq
+// buoyancy, the energy equation with the heat-capacity ratio sigma and the
+// pressure-driven inlet; the default instances leave their terms out (and
+// their registers free).
 template <typename R>
 struct MatAdj {
   R phi = R(0), invk = R(0), sqk = R(0), fphi = R(0), l0 = R(0), l1 = R(0), bT = R(0), bC = R(0), rhocp = R(0);
+  R sig = R(0);  // heat-capacity ratio (EXT only)
 };
 
 // Chain the adjoints of the derived material quantities to (phi, 1/K, D).
-template <typename R>
+template <typename R, bool EXT = false>
 __device__ __forceinline__ void material_adj(const Consts<R>& k, const Mat<R>& m, const MatAdj<R>& a, R& g_phi,
                                              R& g_invk, R& g_d) {
   const R phi = m.phi;
@@ -45,8 +50,14 @@ __device__ __forceinline__ void material_adj(const Consts<R>& k, const Mat<R>& m
   const R alpha = (m.bT + R(4)) * R(0.028867513459481288225);  // 1 / (20 sqrt 3)
   const R drc = k.rhocp_f - k.rhocp_s;
   const R lalpha = a.bT * c20s3;
-  lphi += lalpha * ((k.k_f - k.k_s) * k.alpha_scale - alpha * drc) * irc;
-  lphi += a.rhocp * drc;
+  if (EXT && (k.flags & F_SIGMA_ENERGY)) {
+    // alpha = k_eff alpha_scale / rhocp_f, sigma = rhocp / rhocp_f
+    lphi += lalpha * (k.k_f - k.k_s) * k.alpha_scale / k.rhocp_f;
+    lphi += (a.rhocp + a.sig / k.rhocp_f) * drc;
+  } else {
+    lphi += lalpha * ((k.k_f - k.k_s) * k.alpha_scale - alpha * drc) * irc;
+    lphi += a.rhocp * drc;
+  }
   g_phi += lphi;
   g_invk += linvk;
   g_d += a.bC * c20s3;
@@ -72,14 +83,39 @@ template <typename R>
 struct MacroTape {
   R vx, vy, vm, r, den, ux, uy, um, drag, s18, p, Fx, Fy;
   R iphi, iden, ir;  // 1 / phi, 1 / den, 1 / r
+  R ax, ay, thb;     // acceleration, and the temperature rise buoyancy takes it from (EXT)
 };
 
-template <typename R>
+// The acceleration a of flow_macros is on when the test-mode body force is,
+// or (EXT) Boussinesq buoyancy.
+template <typename R, bool EXT>
+__device__ __forceinline__ bool accelerated(const Consts<R>& k) {
+  return (k.flags & F_BODY_FORCE) || (EXT && (k.flags & F_BUOYANCY));
+}
+
+template <typename R, bool EXT = false>
 __device__ __forceinline__ MacroTape<R> flow_macros_tape(const R (&f)[19], const Mat<R>& m, const Consts<R>& k) {
   MacroTape<R> t;
   t.vx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
   t.vy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-  if (k.flags & F_BODY_FORCE) {
+  if constexpr (EXT) {
+    t.ax = R(0);
+    t.ay = R(0);
+    t.thb = R(0);
+    if (k.flags & F_BODY_FORCE) {
+      t.ax = k.ax;
+      t.ay = k.ay;
+    }
+    if (k.flags & F_BUOYANCY) {
+      t.thb = theta_of(f + 9, m.sig, k);
+      t.ax += k.bx * t.thb;
+      t.ay += k.by * t.thb;
+    }
+    if (accelerated<R, EXT>(k)) {
+      t.vx += R(0.5) * m.phi * t.ax;
+      t.vy += R(0.5) * m.phi * t.ay;
+    }
+  } else if (k.flags & F_BODY_FORCE) {
     t.vx += R(0.5) * m.phi * k.ax;
     t.vy += R(0.5) * m.phi * k.ay;
   }
@@ -95,7 +131,12 @@ __device__ __forceinline__ MacroTape<R> flow_macros_tape(const R (&f)[19], const
   t.drag = m.phi * (k.nu * m.invk + m.fphi * m.sqk * t.um);
   t.Fx = -t.drag * t.ux;
   t.Fy = -t.drag * t.uy;
-  if (k.flags & F_BODY_FORCE) {
+  if constexpr (EXT) {
+    if (accelerated<R, EXT>(k)) {
+      t.Fx += m.phi * t.ax;
+      t.Fy += m.phi * t.ay;
+    }
+  } else if (k.flags & F_BODY_FORCE) {
     t.Fx += m.phi * k.ax;
     t.Fy += m.phi * k.ay;
   }
@@ -106,8 +147,9 @@ __device__ __forceinline__ MacroTape<R> flow_macros_tape(const R (&f)[19], const
 }
 
 // Adjoint of flow_macros: given the adjoints of (ux, uy, p, Fx, Fy), add the
-// adjoints of the flow populations to lf[0..8] and of the material to ma.
-template <typename R>
+// adjoints of the flow populations to lf[0..8] (with buoyancy also of the
+// temperature populations, lf[9..13]) and of the material to ma.
+template <typename R, bool EXT = false>
 __device__ __forceinline__ void flow_macros_adj(const MacroTape<R>& t, const Mat<R>& m, const Consts<R>& k, R lux,
                                                 R luy, R lp, R lFx, R lFy, R* lf, MatAdj<R>& ma) {
   const R iphi = t.iphi;
@@ -117,7 +159,16 @@ __device__ __forceinline__ void flow_macros_adj(const MacroTape<R>& t, const Mat
   R lu2 = R(-0.4) * iphi * iphi * lp;
   R liphi = (R(0.6) * t.s18 - R(0.8) * u2 * iphi) * lp;
   // F = -drag u (+ phi a)
-  if (k.flags & F_BODY_FORCE) ma.phi += k.ax * lFx + k.ay * lFy;
+  R lax = R(0), lay = R(0);
+  if constexpr (EXT) {
+    if (accelerated<R, EXT>(k)) {
+      ma.phi += t.ax * lFx + t.ay * lFy;
+      lax += m.phi * lFx;
+      lay += m.phi * lFy;
+    }
+  } else if (k.flags & F_BODY_FORCE) {
+    ma.phi += k.ax * lFx + k.ay * lFy;
+  }
   const R ldrag = -(t.ux * lFx + t.uy * lFy);
   lux += -t.drag * lFx;
   luy += -t.drag * lFy;
@@ -143,7 +194,25 @@ __device__ __forceinline__ void flow_macros_adj(const MacroTape<R>& t, const Mat
     lvx += q * t.vx;
     lvy += q * t.vy;
   }
-  if (k.flags & F_BODY_FORCE) ma.phi += R(0.5) * (k.ax * lvx + k.ay * lvy);
+  if constexpr (EXT) {
+    if (accelerated<R, EXT>(k)) {
+      ma.phi += R(0.5) * (t.ax * lvx + t.ay * lvy);
+      lax += R(0.5) * m.phi * lvx;
+      lay += R(0.5) * m.phi * lvy;
+    }
+  } else if (k.flags & F_BODY_FORCE) {
+    ma.phi += R(0.5) * (k.ax * lvx + k.ay * lvy);
+  }
+  if (EXT && (k.flags & F_BUOYANCY)) {  // a = ... + b theta, theta = sum g_T (/ sigma)
+    R lth = k.bx * lax + k.by * lay;
+    if (k.flags & F_SIGMA_ENERGY) {
+      const R isg = R(1) / m.sig;
+      ma.sig += -t.thb * isg * lth;
+      lth *= isg;
+    }
+#pragma unroll
+    for (int i = 9; i < 14; ++i) lf[i] += lth;
+  }
   // v = sum e f, s18 = sum_{1..8} f
   lf[1] += lvx + ls18;
   lf[2] += lvy + ls18;
@@ -201,6 +270,22 @@ __device__ __forceinline__ void geq_adj(R X, R ux, R uy, R b, R sgn, const R* lg
   lb += sgn * X * n3;
 }
 
+// The same with the heat-capacity ratio of add_geq (rest moment sigma X,
+// energy moment (b + 4 (1 - sigma)) X); also adds the adjoint of sigma.
+template <typename R>
+__device__ __forceinline__ void geq_adj_sig(R X, R ux, R uy, R b, R sig, R sgn, const R* lg, R& lX, R& lux, R& luy,
+                                            R& lb, R& lsig) {
+  const R n0 = (lg[0] + lg[1] + lg[2] + lg[3] + lg[4]) * R(0.2);
+  const R n1 = (lg[1] - lg[3]) * R(0.5);
+  const R n2 = (lg[2] - lg[4]) * R(0.5);
+  const R n3 = (R(-4) * lg[0] + lg[1] + lg[2] + lg[3] + lg[4]) * R(0.05);
+  lX += sgn * (sig * n0 + ux * n1 + uy * n2 + (b + R(4) * (R(1) - sig)) * n3);
+  lux += sgn * X * n1;
+  luy += sgn * X * n2;
+  lb += sgn * X * n3;
+  lsig += sgn * X * (n0 - R(4) * n3);
+}
+
 // Reaction sensitivities: ds_c/dc, ds_c/dtheta, and S_T's.
 template <typename R>
 struct ReactAdj {
@@ -239,17 +324,24 @@ __device__ __forceinline__ ReactAdj<R> reaction_tape(R theta, R c, R rhocp, cons
 // Collision adjoint of one node.  In: pre-collision f, material, adjoint of
 // the post-collision populations la.  Out: adjoint of the pre-collision
 // populations mu; material adjoints accumulated in ma.
-template <typename R>
+// With the heat-capacity ratio (EXT) the temperature lattice conserves
+// sigma theta: theta = sum g_T / sigma, the rest moment takes sigma S_T, the
+// energy moment relaxes with b_T + 4 (1 - sigma); the adjoint of theta is
+// then divided by sigma onto the populations and its sigma part goes to ma.
+template <typename R, bool EXT = false>
 __device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, const Consts<R>& k, bool cl,
                                             const R (&la)[19], R (&mu)[19], MatAdj<R>& ma) {
-  const MacroTape<R> t = flow_macros_tape(f, mt, k);
+  const MacroTape<R> t = flow_macros_tape<R, EXT>(f, mt, k);
   R lux = R(0), luy = R(0);
 #pragma unroll
   for (int i = 0; i < 19; ++i) mu[i] = R(0);
 
   // ---- scalars (reverse of the D2Q5 collisions and the CL source) ----
-  const R th = f[9] + f[10] + f[11] + f[12] + f[13];
+  const bool sigma = EXT && (k.flags & F_SIGMA_ENERGY);
+  const R thsum = f[9] + f[10] + f[11] + f[12] + f[13];
+  const R th = sigma ? thsum / mt.sig : thsum;
   const R c = f[14] + f[15] + f[16] + f[17] + f[18];
+  R ln0T = R(0);  // sigma: adjoint of the conserved temperature moment, apart from theta's
   ReactAdj<R> rx{};
   if (cl) rx = reaction_tape(th, c, mt.rhocp, k);
   const R srcT = cl ? rx.S_T : R(0), srcC = cl ? -rx.s_c : R(0);
@@ -261,7 +353,7 @@ __device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, 
     const R* a = la + 9 + 5 * s;
     const R* g = f + 9 + 5 * s;
     const R X = s == 0 ? th : c;
-    const R b = s == 0 ? mt.bT : mt.bC;
+    const R b = s == 0 ? (sigma ? mt.bT + R(4) * (R(1) - mt.sig) : mt.bT) : mt.bC;
     const R src = s == 0 ? srcT : srcC;
     // g* = N^-1 n*: adjoint of n* is (N a) / (5, 2, 2, 20, 4)
     // Divided (not multiplied by fl(0.2)): the uniform component of the
@@ -271,9 +363,16 @@ __device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, 
     const R ln2 = (a[2] - a[4]) * R(0.5);
     const R ln3 = (R(-4) * a[0] + a[1] + a[2] + a[3] + a[4]) * R(0.05);
     const R ln4 = (a[1] - a[2] + a[3] - a[4]) * R(0.25);
-    lX[s] = ln0 + q1 * t.ux * ln1 + q1 * t.uy * ln2 + q3 * b * ln3;
-    lsrc[s] = ln0 + b * ln3;
     const R lb = q3 * X * ln3 + src * ln3;
+    if (sigma && s == 0) {  // n0 = sum g_T + sigma S_T; b = b_T + 4 (1 - sigma)
+      ln0T = ln0;
+      lX[s] = q1 * t.ux * ln1 + q1 * t.uy * ln2 + q3 * b * ln3;
+      lsrc[s] = mt.sig * ln0 + b * ln3;
+      ma.sig += src * ln0 - R(4) * lb;
+    } else {
+      lX[s] = ln0 + q1 * t.ux * ln1 + q1 * t.uy * ln2 + q3 * b * ln3;
+      lsrc[s] = ln0 + b * ln3;
+    }
     if (s == 0) ma.bT += lb; else ma.bC += lb;
     lux += q1 * X * ln1;
     luy += q1 * X * ln2;
@@ -295,6 +394,11 @@ __device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, 
     lX[1] += rx.dsc_dc * lsc;
     lX[0] += rx.dsc_dth * lsc;
     if (k.flags & F_PHYSICAL_HEAT) lX[0] += k.four_f_cref * rx.s_c * R(2) * k.U0_slope * irc * lST;
+  }
+  if (sigma) {  // theta = sum g_T / sigma
+    const R isg = R(1) / mt.sig;
+    ma.sig += -th * isg * lX[0];
+    lX[0] = ln0T + lX[0] * isg;
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -339,18 +443,21 @@ __device__ __forceinline__ void collide_adj(const R (&f)[19], const Mat<R>& mt, 
   mt_times(lm, lfm);
 #pragma unroll
   for (int i = 0; i < 9; ++i) mu[i] += lfm[i];
-  flow_macros_adj(t, mt, k, lux, luy, lp, lFx, lFy, mu, ma);
+  flow_macros_adj<R, EXT>(t, mt, k, lux, luy, lp, lFx, lFy, mu, ma);
 }
 
 // Adjoint of the boundary-column extrapolation of node b fed by node xp.
 // pre_xp: pulled populations of xp; mu_b: adjoint of the boundary node's
 // pre-collision populations.  Adds to mu_xp and to the material adjoints of
 // xp (maxp) and of b (mab).
-template <typename R>
+// EXT: also the pressure-driven inlet (p_in fixed, u taken from xp) and the
+// heat-capacity ratio in the inlet's temperature extrapolation.
+template <typename R, bool EXT = false>
 __device__ __forceinline__ void boundary_adj(const R (&pre_xp)[19], const Mat<R>& mxp, const Mat<R>& mb,
                                              const Consts<R>& k, bool inlet, R ubx, R uby, const R (&mu_b)[19],
                                              R (&mu_xp)[19], MatAdj<R>& maxp, MatAdj<R>& mab) {
-  const MacroTape<R> t = flow_macros_tape(pre_xp, mxp, k);
+  const MacroTape<R> t = flow_macros_tape<R, EXT>(pre_xp, mxp, k);
+  const bool pressure = EXT && inlet && (k.flags & F_PRESSURE_INLET);
 #pragma unroll
   for (int i = 0; i < 19; ++i) mu_xp[i] += mu_b[i];  // identity part (scalars at the outlet: a copy)
   R ldm[9];
@@ -362,7 +469,10 @@ __device__ __forceinline__ void boundary_adj(const R (&pre_xp)[19], const Mat<R>
   R lp1 = R(0), lux1 = R(0), luy1 = R(0);
   // + meq(pb, ub; phi_b): inlet pb = p1 (ub fixed); outlet pb = p_out, ub = u1.
   R dumx = R(0), dumy = R(0);
-  if (inlet) {
+  if (pressure) {  // pb = p_in, ub = u1
+    R dp = R(0);
+    meq_adj(k.p_in, t.ux, t.uy, mb.phi, iphi_b, ldm, dp, lux1, luy1, mab.phi);
+  } else if (inlet) {
     meq_adj(t.p, ubx, uby, mb.phi, iphi_b, ldm, lp1, dumx, dumy, mab.phi);
   } else {
     R dp = R(0);
@@ -374,13 +484,25 @@ __device__ __forceinline__ void boundary_adj(const R (&pre_xp)[19], const Mat<R>
   for (int i = 0; i < 9; ++i) nldm[i] = -ldm[i];
   meq_adj(t.p, t.ux, t.uy, mxp.phi, t.iphi, nldm, lp1, lux1, luy1, maxp.phi);
   if (inlet) {
-    const R th1 = pre_xp[9] + pre_xp[10] + pre_xp[11] + pre_xp[12] + pre_xp[13];
+    const bool sigma = EXT && (k.flags & F_SIGMA_ENERGY);
+    const R th1sum = pre_xp[9] + pre_xp[10] + pre_xp[11] + pre_xp[12] + pre_xp[13];
+    const R th1 = sigma ? th1sum / mxp.sig : th1sum;
     const R c1 = pre_xp[14] + pre_xp[15] + pre_xp[16] + pre_xp[17] + pre_xp[18];
     R lth1 = R(0), lc1 = R(0), dX = R(0);
     // + geq(0, ub; bT_b): no dependence.  - geq(theta1, u1; bT_xp)
-    geq_adj(th1, t.ux, t.uy, mxp.bT, R(-1), mu_b + 9, lth1, lux1, luy1, maxp.bT);
-    // + geq(c_in, ub; bC_b)
-    geq_adj(k.c_in, ubx, uby, mb.bC, R(1), mu_b + 14, dX, dumx, dumy, mab.bC);
+    if (sigma) {
+      geq_adj_sig(th1, t.ux, t.uy, mxp.bT, mxp.sig, R(-1), mu_b + 9, lth1, lux1, luy1, maxp.bT, maxp.sig);
+      const R isg = R(1) / mxp.sig;  // theta1 = sum g_T / sigma
+      maxp.sig += -th1 * isg * lth1;
+      lth1 *= isg;
+    } else {
+      geq_adj(th1, t.ux, t.uy, mxp.bT, R(-1), mu_b + 9, lth1, lux1, luy1, maxp.bT);
+    }
+    // + geq(c_in, ub; bC_b): ub = u1 with the pressure-driven inlet
+    if (pressure)
+      geq_adj(k.c_in, t.ux, t.uy, mb.bC, R(1), mu_b + 14, dX, lux1, luy1, mab.bC);
+    else
+      geq_adj(k.c_in, ubx, uby, mb.bC, R(1), mu_b + 14, dX, dumx, dumy, mab.bC);
     // - geq(c1, u1; bC_xp)
     geq_adj(c1, t.ux, t.uy, mxp.bC, R(-1), mu_b + 14, lc1, lux1, luy1, maxp.bC);
 #pragma unroll
@@ -389,7 +511,7 @@ __device__ __forceinline__ void boundary_adj(const R (&pre_xp)[19], const Mat<R>
       mu_xp[14 + i] += lc1;
     }
   }
-  flow_macros_adj(t, mxp, k, lux1, luy1, lp1, R(0), R(0), mu_xp, maxp);
+  flow_macros_adj<R, EXT>(t, mxp, k, lux1, luy1, lp1, R(0), R(0), mu_xp, maxp);
 }
 
 }  // namespace lbm

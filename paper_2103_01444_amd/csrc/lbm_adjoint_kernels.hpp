@@ -8,18 +8,27 @@ namespace lbm {
 
 // Adjoint of the observable J = mean current density on the pre-collision
 // populations: for CL nodes dJ/dc and dJ/dtheta on every scalar population.
-template <typename R>
+// With the heat-capacity ratio (EXT) theta = sum g_T / sigma.
+template <typename R, bool EXT>
 __device__ __forceinline__ void seed_mu(const R (&pre)[19], const Mat<R>& mt, const Consts<R>& k, bool cl, R w,
-                                        R (&mu)[19]) {
+                                        R (&mu)[19], MatAdj<R>& ma) {
 #pragma unroll
   for (int i = 0; i < 19; ++i) mu[i] = R(0);
   if (!cl) return;
-  const R th = pre[9] + pre[10] + pre[11] + pre[12] + pre[13];
+  const bool sigma = EXT && (k.flags & F_SIGMA_ENERGY);
+  const R thsum = pre[9] + pre[10] + pre[11] + pre[12] + pre[13];
+  const R th = sigma ? thsum / mt.sig : thsum;
   const R c = pre[14] + pre[15] + pre[16] + pre[17] + pre[18];
   const ReactAdj<R> r = reaction_tape(th, c, mt.rhocp, k);
+  R lth = w * r.dsc_dth;
+  if (sigma) {
+    const R isg = R(1) / mt.sig;
+    ma.sig += -th * isg * lth;
+    lth *= isg;
+  }
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    mu[9 + i] = w * r.dsc_dth;
+    mu[9 + i] = lth;
     mu[14 + i] = w * r.dsc_dc;
   }
 }
@@ -37,6 +46,7 @@ __device__ __forceinline__ void add_mat_adj(MatAdj<R>& a, bool first, const MatA
   a.bT += first ? b1.bT : b2.bT;
   a.bC += first ? b1.bC : b2.bC;
   a.rhocp += first ? b1.rhocp : b2.rhocp;
+  a.sig += first ? b1.sig : b2.sig;
 }
 
 template <typename R>
@@ -47,16 +57,16 @@ __device__ __forceinline__ void load_node(const R* __restrict__ a, const Consts<
 }
 
 // Adjoint of node b's collision (or of J when SEED) given b's pre-collision populations.
-template <typename R, bool SEED>
+template <typename R, bool SEED, bool EXT>
 __device__ __forceinline__ void node_mu(const R (&pre)[19], const Mat<R>& mt, const Consts<R>& k, bool cl,
                                         const R* __restrict__ lam_in, int x, int y, R w, R (&mu)[19],
                                         MatAdj<R>& ma) {
   if constexpr (SEED) {
-    seed_mu(pre, mt, k, cl, w, mu);
+    seed_mu<R, EXT>(pre, mt, k, cl, w, mu, ma);
   } else {
     R la[19];
     load_node(lam_in, k, x, y, la);
-    collide_adj(pre, mt, k, cl, la, mu, ma);
+    collide_adj<R, EXT>(pre, mt, k, cl, la, mu, ma);
   }
 }
 
@@ -73,7 +83,7 @@ __device__ __forceinline__ void node_mu(const R (&pre)[19], const Mat<R>& mt, co
 // three; 29.3-29.9 us when the feeding lane recomputed the boundary node's
 // collision adjoint, 34.4 us when the boundary and feeding lanes took
 // separate divergent passes.
-template <typename R, bool SEED>
+template <typename R, bool SEED, bool EXT = false>
 __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
                                                      R* __restrict__ lam_out, R* __restrict__ grad,
                                                      const R* __restrict__ phi_f, const R* __restrict__ invk_f,
@@ -107,7 +117,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
       boundary_column(p, k, y, inlet, mxp, mc);
       if (outlet) outlet_scalar_material(mc, mxp);
     }
-    node_mu<R, SEED>(p, mc, k, cl, lam_in, x, y, w, mu, ma);
+    node_mu<R, SEED, EXT>(p, mc, k, cl, lam_in, x, y, w, mu, ma);
   }
   if (bnode) pull<R, true, false>(S, k, xp, y, p);  // the column's own populations again
 
@@ -123,7 +133,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
     if (x <= 1) {
       const Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, 0, y);
       MatAdj<R> axp{}, ab{};
-      boundary_adj(p, mxp, mb, k, true, inlet_velocity(k, y), R(0), mub, mu, axp, ab);
+      boundary_adj<R, EXT>(p, mxp, mb, k, true, inlet_velocity(k, y), R(0), mub, mu, axp, ab);
       add_mat_adj(ma, x == 0, ab, axp);
     }
   }
@@ -136,6 +146,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
 #pragma unroll
         for (int q = 0; q < 19; ++q) mub[q] = __shfl(mu[q], src, 64);
         const R sbT = __shfl(ma.bT, src, 64), sbC = __shfl(ma.bC, src, 64), src_p = __shfl(ma.rhocp, src, 64);
+        const R ssg = EXT ? __shfl(ma.sig, src, 64) : R(0);
         if (x >= xo - 1) {
           Mat<R> mb = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xo, y);
           outlet_scalar_material(mb, mxp);
@@ -143,9 +154,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
             ma.bT += sbT;
             ma.bC += sbC;
             ma.rhocp += src_p;
+            if (EXT) ma.sig += ssg;
           }
           MatAdj<R> axp{}, ab{};
-          boundary_adj(p, mxp, mb, k, false, R(0), R(0), mub, mu, axp, ab);
+          boundary_adj<R, EXT>(p, mxp, mb, k, false, R(0), R(0), mub, mu, axp, ab);
           add_mat_adj(ma, outlet, ab, axp);
         }
       }
@@ -163,13 +175,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
         boundary_column(pre, k, y, false, mxp, mb);
         outlet_scalar_material(mb, mxp);
         MatAdj<R> mab{};
-        node_mu<R, SEED>(pre, mb, k, cl, lam_in, xo, y, w, mub, mab);
+        node_mu<R, SEED, EXT>(pre, mb, k, cl, lam_in, xo, y, w, mub, mab);
         ma.bT += mab.bT;
         ma.bC += mab.bC;
         ma.rhocp += mab.rhocp;
+        if (EXT) ma.sig += mab.sig;
       }
       MatAdj<R> axp{}, ab{};
-      boundary_adj(p, mxp, mb, k, false, R(0), R(0), mub, mu, axp, ab);
+      boundary_adj<R, EXT>(p, mxp, mb, k, false, R(0), R(0), mub, mu, axp, ab);
       add_mat_adj(ma, outlet, ab, axp);
     }
   }
@@ -177,6 +190,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
     ma.bT = R(0);
     ma.bC = R(0);
     ma.rhocp = R(0);
+    ma.sig = R(0);
   }
   if (bnode) {  // its pulled sources were never read: their adjoint is 0
 #pragma unroll
@@ -186,7 +200,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
   // again; its scalar-material terms are zero, so the outlet's copy of
   // column nx - 2's scalar material does not enter).
   R g0 = R(0), g1 = R(0), g2 = R(0);
-  material_adj(k, bnode ? material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y) : mxp, ma, g0, g1, g2);
+  material_adj<R, EXT>(k, bnode ? material<R, MAT_FULL>(k, phi_f, invk_f, d_f, x, y) : mxp, ma, g0, g1, g2);
   grad[o] += g0;
   grad[k.plane + o] += g1;
   grad[2 * k.plane + o] += g2;

@@ -705,9 +705,16 @@ lbm_status backward_t(lbm_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_
   // Seed: adjoint of J = current density on the final state.
   const lbm_params& p = c->p;
   const double w = dJ * c->d.dx / c->g.nx * 4.0 * p.faraday * p.C_ref / c->d.dt;
-  hipLaunchKernelGGL((k_adj_step<R, true>), grid, dim3(kBlock), 0, c->stream,
-                     static_cast<const R*>(c->state(c->cur)), static_cast<const R*>(nullptr), lam[0], grad, m.phi,
-                     m.invk, m.d, k, R(w));
+  // Buoyancy, the heat-capacity ratio and the pressure-driven inlet take the
+  // reverse-step instances that carry their terms.
+  const bool ext = c->g.flags & (LBM_BUOYANCY | LBM_SIGMA_ENERGY | LBM_PRESSURE_INLET);
+  const R* S_final = static_cast<const R*>(c->state(c->cur));
+  if (ext)
+    hipLaunchKernelGGL((k_adj_step<R, true, true>), grid, dim3(kBlock), 0, c->stream, S_final,
+                       static_cast<const R*>(nullptr), lam[0], grad, m.phi, m.invk, m.d, k, R(w));
+  else
+    hipLaunchKernelGGL((k_adj_step<R, true>), grid, dim3(kBlock), 0, c->stream, S_final,
+                       static_cast<const R*>(nullptr), lam[0], grad, m.phi, m.invk, m.d, k, R(w));
   // Segments are swept from the last to the first.  Segment s - 1 is
   // replayed from its checkpoint into one replay buffer on the second
   // stream while segment s is swept in reverse from the other on the
@@ -757,9 +764,13 @@ lbm_status backward_t(lbm_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_
       return fail(c, LBM_ERR_DEVICE, "replay join failed");
     const char* buf = ws + A.off_replay + size_t(b) * rbuf;
     for (int j = seg_len(seg) - 1; j >= 0; --j) {
-      hipLaunchKernelGGL((k_adj_step<R, false>), grid, dim3(kBlock), 0, c->stream,
-                         reinterpret_cast<const R*>(buf + size_t(j) * A.state), lam[cur], lam[cur ^ 1], grad, m.phi,
-                         m.invk, m.d, k, R(0));
+      const R* S = reinterpret_cast<const R*>(buf + size_t(j) * A.state);
+      if (ext)
+        hipLaunchKernelGGL((k_adj_step<R, false, true>), grid, dim3(kBlock), 0, c->stream, S, lam[cur],
+                           lam[cur ^ 1], grad, m.phi, m.invk, m.d, k, R(0));
+      else
+        hipLaunchKernelGGL((k_adj_step<R, false>), grid, dim3(kBlock), 0, c->stream, S, lam[cur], lam[cur ^ 1], grad,
+                           m.phi, m.invk, m.d, k, R(0));
       cur ^= 1;
     }
     if (hipEventRecord(c->ev_rev[b], c->stream) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "sweep event failed");
@@ -792,14 +803,8 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, v
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
   if (c->mat != MAT_FULL)
     return fail(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
-  if (c->g.flags & LBM_PRESSURE_INLET)
-    return fail(c, LBM_ERR_STATE, "the adjoint covers the velocity inlet, not LBM_PRESSURE_INLET");
   if (c->g.flags & LBM_THIN_CL)
     return fail(c, LBM_ERR_STATE, "the adjoint covers the volumetric CL, not LBM_THIN_CL");
-  if (c->g.flags & LBM_BUOYANCY)
-    return fail(c, LBM_ERR_STATE, "the adjoint does not cover LBM_BUOYANCY");
-  if (c->g.flags & LBM_SIGMA_ENERGY)
-    return fail(c, LBM_ERR_STATE, "the adjoint covers the printed energy equation, not LBM_SIGMA_ENERGY");
   const AdjLayout A = adj_layout(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign != 0)
     return fail(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

@@ -1,7 +1,8 @@
 """Boussinesq buoyancy (LBM_BUOYANCY) on the GPU against the FP64 oracle and
 the closed-form buoyant shear wave: one step of arbitrary states in every
 material mode (also with the test-mode body force), a buoyant cathode run
-with its observables, the batched solver, and the adjoint's refusal."""
+with its observables, and the batched solver.  The adjoint with buoyancy
+is tested with the other adjoint parity cases."""
 import math
 
 import numpy as np
@@ -138,12 +139,3 @@ def test_buoyant_case_in_a_batch_equals_its_single_context():
         s = lbm.Cathode.from_workload(w)
         s.step(120)
         assert torch.equal(b.populations(i), s.populations()), w["name"]
-
-
-def test_adjoint_rejects_buoyancy():
-    lbm = _lbm()
-    w = dict(W.cathode2d_200x40(), nx=40, ny=10, ny_channel=5, ny_gdl=4, ny_cl=1, precision=64, Re=2.0,
-             buoyancy=(0.0, 1e-5))
-    sim = lbm.Cathode.from_workload(w, independent_fields=1)
-    with pytest.raises(lbm.LbmError, match="BUOYANCY"):
-        sim.forward_checkpointed(10, 5)

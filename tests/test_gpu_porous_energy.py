@@ -1,8 +1,9 @@
 """Porous energy equation with the heat-capacity ratio (LBM_SIGMA_ENERGY)
 and the physically signed reaction heat (LBM_PHYSICAL_HEAT) on the GPU
 against the FP64 oracle: one step of arbitrary states in every material
-mode, an FP64 cathode run with its observables, the 3D heat sign, the
-batched solver, and the adjoint's refusal of LBM_SIGMA_ENERGY."""
+mode, an FP64 cathode run with its observables, the 3D heat sign and
+the batched solver.  The adjoint with these options is tested with the other
+adjoint parity cases."""
 import numpy as np
 import pytest
 import torch
@@ -108,12 +109,3 @@ def test_sigma_case_in_a_batch_equals_its_single_context():
         s = lbm.Cathode.from_workload(w)
         s.step(120)
         assert torch.equal(b.populations(i), s.populations()), w["name"]
-
-
-def test_adjoint_rejects_sigma_energy():
-    lbm = _lbm()
-    w = dict(W.cathode2d_200x40(), nx=40, ny=10, ny_channel=5, ny_gdl=4, ny_cl=1, precision=64, Re=2.0,
-             sigma_energy=True)
-    sim = lbm.Cathode.from_workload(w, independent_fields=1)
-    with pytest.raises(lbm.LbmError, match="LBM_SIGMA_ENERGY"):
-        sim.forward_checkpointed(10, 5)

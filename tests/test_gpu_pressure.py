@@ -118,14 +118,6 @@ def test_pressure_and_velocity_cases_in_one_batch_equal_single_contexts():
         assert o["inlet_flux"] == obs[i]["inlet_flux"] and o["o2_utilisation"] == obs[i]["o2_utilisation"]
 
 
-def test_adjoint_rejects_the_pressure_inlet():
-    lbm = _lbm()
-    w = _case(64, nx=40, ny=10, ny_channel=5, ny_gdl=4, ny_cl=1)
-    sim = lbm.Cathode.from_workload(w, independent_fields=1)
-    with pytest.raises(lbm.LbmError, match="PRESSURE_INLET"):
-        sim.forward_checkpointed(10, 5)
-
-
 def test_polarisation_sweep_trends():
     """Section 5 trends on the 39-case sweep after 30000 steps: from 0.6 V up
     the current density falls with the voltage (kinetic region); below it

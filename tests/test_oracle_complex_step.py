@@ -30,6 +30,9 @@ OPTIONS_2D = {
     "periodic_x_body_force": (dict(Re=0.0), dict(periodic_x=True)),
     "periodic_y": (dict(Re=0.8), dict(periodic_y=True)),
     "outlet_pressure": (dict(p_out=3e-3), {}),
+    "buoyancy": (dict(buoyancy=(3e-3, -5e-3)), {}),
+    "sigma_energy": (dict(sigma_energy=True, heat_physical=True), {}),
+    "pressure_inlet": (dict(pressure_inlet=True, p_in=4e-3), {}),
 }
 
 
