@@ -293,11 +293,11 @@ size_t lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int64_t nsteps, int32_t e
 /* Initialise to equilibrium, run nsteps steps storing a checkpoint every
  * `every` steps in dev_ws (caller-owned, kept until lbm_backward), and
  * return J in *J_out.  Synchronous.  LBM_ERR_STATE if the context does not
- * hold independent per-cell fields or uses LBM_THIN_CL: the adjoint covers
- * the volumetric CL, with the velocity or the pressure-driven inlet, Tafel or
- * Butler-Volmer kinetics, either sign of the reaction heat
- * (LBM_PHYSICAL_HEAT), buoyancy (LBM_BUOYANCY) and the heat-capacity ratio
- * (LBM_SIGMA_ENERGY). */
+ * hold independent per-cell fields.  The adjoint covers every option of the
+ * 2D solver: the volumetric or the thin-film CL (LBM_THIN_CL), the velocity
+ * or the pressure-driven inlet, Tafel or Butler-Volmer kinetics, either sign
+ * of the reaction heat (LBM_PHYSICAL_HEAT), buoyancy (LBM_BUOYANCY) and the
+ * heat-capacity ratio (LBM_SIGMA_ENERGY). */
 lbm_status lbm_forward_checkpointed(lbm_ctx* ctx, int64_t nsteps, int32_t every, void* dev_ws, size_t ws_bytes,
                                     double* J_out);
 

@@ -321,6 +321,64 @@ __device__ __forceinline__ ReactAdj<R> reaction_tape(R theta, R c, R rhocp, cons
   return r;
 }
 
+// Tape of the thin-film reaction (surface_reaction: the populations g_t, g_c
+// that cross the reactive wall, wall values g / a with a = (4 + b) / 20)
+// and its derivatives with respect to the wall temperature T, g_c and a_c.
+template <typename R>
+struct FilmTape {
+  R a_t, T, s, S_T, ehs, em, ds_dT, ds_dac, dehs_dT;
+};
+
+template <typename R>
+__device__ __forceinline__ FilmTape<R> film_tape(R g_t, R g_c, const Mat<R>& m, const Consts<R>& k) {
+  FilmTape<R> f;
+  f.a_t = (R(4) + m.bT) / R(20);
+  const R a_c = (R(4) + m.bC) / R(20);
+  f.T = k.T_in + g_t / f.a_t;
+  const R iT = R(1) / f.T;
+  const R eta = k.V_op - (k.U0_slope * f.T + k.U0_icept);
+  const R kappa_a =
+      exp(k.ln_k0 + k.ln_thin - k.E_over_R * (iT - k.inv_T_arrh) - k.aF_over_R * eta * iT) / a_c;
+  const R ceq = k.bv ? exp(k.aFsum_over_R * eta * iT) : R(0);
+  f.em = expm1(-kappa_a);
+  f.s = -(g_c - a_c * ceq) * f.em;
+  const bool phys = k.flags & F_PHYSICAL_HEAT;
+  f.ehs = (phys ? -eta : eta) + f.T * k.U0_slope;
+  f.S_T = k.four_f_cref * f.s * f.ehs / m.rhocp;
+  // ds/dkappa = (g_c - a_c c_eq)(em + 1); dkappa/dT = kappa dE/dT as in the
+  // volumetric tape; ds/dc_eq = a_c em with dc_eq/dT as there
+  const R dE = k.E_over_R * iT * iT + k.aF_over_R * k.U0_slope * iT + k.aF_over_R * eta * iT * iT;
+  const R ds_dk = (g_c - a_c * ceq) * (f.em + R(1));
+  f.ds_dT = ds_dk * kappa_a * dE;
+  if (k.bv) f.ds_dT -= a_c * f.em * ceq * k.aFsum_over_R * (k.U0_slope * iT + eta * iT * iT);
+  f.ds_dac = -ds_dk * kappa_a / a_c + ceq * f.em;
+  f.dehs_dT = phys ? R(2) * k.U0_slope : R(0);
+  return f;
+}
+
+// Transpose of the film's update of the two populations, g_t += sigma S_T
+// and g_c -= s: given the adjoints l13, l18 of the updated values, returns
+// those of the incoming ones in place and adds the material adjoints.
+// ls, le: adjoints of s and of the heat factor from other uses (the seed
+// of J takes ls = its weight).
+template <typename R>
+__device__ __forceinline__ void film_adj(const FilmTape<R>& f, const Mat<R>& m, const Consts<R>& k, R ls, R& l13,
+                                         R& l18, MatAdj<R>& ma) {
+  const R sg = (k.flags & F_SIGMA_ENERGY) ? m.sig : R(1);
+  const R irc = R(1) / m.rhocp;
+  const R lST = sg * l13;
+  if (k.flags & F_SIGMA_ENERGY) ma.sig += f.S_T * l13;
+  ls += lST * k.four_f_cref * f.ehs * irc - l18;
+  const R lehs = lST * k.four_f_cref * f.s * irc;
+  ma.rhocp += -lST * f.S_T * irc;
+  const R lT = ls * f.ds_dT + lehs * f.dehs_dT;
+  l13 += lT / f.a_t;
+  l18 += -ls * f.em;
+  // T = T_in + g_t / a_t, a = (4 + b) / 20
+  ma.bT += -lT * (f.T - k.T_in) / f.a_t * R(0.05);
+  ma.bC += ls * f.ds_dac * R(0.05);
+}
+
 // Collision adjoint of one node.  In: pre-collision f, material, adjoint of
 // the post-collision populations la.  Out: adjoint of the pre-collision
 // populations mu; material adjoints accumulated in ma.

@@ -103,6 +103,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
   R p[19];
   pull<R, true, true>(S, k, xp, y, p);
   const Mat<R> mxp = material<R, MAT_FULL>(k, phi_f, invk_f, d_f, xp, y);
+  // Thin-film CL (EXT): the bottom row's wall-crossing populations react as
+  // the forward pull left them (column nx - 2's film for the outlet).
+  const bool film = EXT && (k.flags & F_THIN_CL) && react && y == k.ny - 1;
+  FilmTape<R> ft{};
+  if (film) {
+    ft = film_tape(p[13], p[18], mxp, k);
+    p[13] += ft.S_T * mxp.sig;
+    p[18] -= ft.s;
+  }
   MatAdj<R> ma{};
   R mu[19];
   const int o = y * k.pitch + x;
@@ -119,7 +128,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
     }
     node_mu<R, SEED, EXT>(p, mc, k, cl, lam_in, x, y, w, mu, ma);
   }
-  if (bnode) pull<R, true, false>(S, k, xp, y, p);  // the column's own populations again
+  if (bnode) {  // the column's own populations again
+    pull<R, true, false>(S, k, xp, y, p);
+    if (film) {
+      p[13] += ft.S_T * mxp.sig;
+      p[18] -= ft.s;
+    }
+  }
 
   // Transpose of the extrapolation of a boundary node from the column next
   // to it: the boundary node needs it for its own material, the feeding
@@ -185,6 +200,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S,
       boundary_adj<R, EXT>(p, mxp, mb, k, false, R(0), R(0), mub, mu, axp, ab);
       add_mat_adj(ma, outlet, ab, axp);
     }
+  }
+  // Transpose of the film's update in the column that pulled it (the
+  // outlet's copy came back through the boundary transpose above); the seed
+  // adds J's dependence on the film, which counts column nx - 2 twice (the
+  // outlet carries its film).
+  if (film && !bnode) {
+    const R ls = SEED ? ((open && x == k.nx - 2) ? R(2) * w : w) : R(0);
+    film_adj(ft, mxp, k, ls, mu[13], mu[18], ma);
   }
   if (outlet) {  // its scalar material terms belong to column nx - 2
     ma.bT = R(0);

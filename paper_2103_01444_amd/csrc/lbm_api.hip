@@ -705,9 +705,9 @@ lbm_status backward_t(lbm_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_
   // Seed: adjoint of J = current density on the final state.
   const lbm_params& p = c->p;
   const double w = dJ * c->d.dx / c->g.nx * 4.0 * p.faraday * p.C_ref / c->d.dt;
-  // Buoyancy, the heat-capacity ratio and the pressure-driven inlet take the
-  // reverse-step instances that carry their terms.
-  const bool ext = c->g.flags & (LBM_BUOYANCY | LBM_SIGMA_ENERGY | LBM_PRESSURE_INLET);
+  // Buoyancy, the heat-capacity ratio, the pressure-driven inlet and the
+  // thin-film CL take the reverse-step instances that carry their terms.
+  const bool ext = c->g.flags & (LBM_BUOYANCY | LBM_SIGMA_ENERGY | LBM_PRESSURE_INLET | LBM_THIN_CL);
   const R* S_final = static_cast<const R*>(c->state(c->cur));
   if (ext)
     hipLaunchKernelGGL((k_adj_step<R, true, true>), grid, dim3(kBlock), 0, c->stream, S_final,
@@ -803,8 +803,6 @@ lbm_status lbm_forward_checkpointed(lbm_ctx* c, int64_t nsteps, int32_t every, v
   if (!c->params_set) return fail(c, LBM_ERR_STATE, "lbm_set_params first");
   if (c->mat != MAT_FULL)
     return fail(c, LBM_ERR_STATE, "the adjoint needs the three per-cell fields (independent_fields or all arrays)");
-  if (c->g.flags & LBM_THIN_CL)
-    return fail(c, LBM_ERR_STATE, "the adjoint covers the volumetric CL, not LBM_THIN_CL");
   const AdjLayout A = adj_layout(c, nsteps, every);
   if (ws_bytes < A.total || reinterpret_cast<uintptr_t>(dev_ws) % kAlign != 0)
     return fail(c, LBM_ERR_INVALID_ARG, "adjoint workspace too small or misaligned");

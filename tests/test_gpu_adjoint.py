@@ -309,6 +309,10 @@ OPTIONS = {
     "all": (dict(butler_volmer=True, alpha_a=0.5, V_op=1.1, aj0_ref=1e5, heat_physical=True, buoyancy=(3e-3, -5e-3),
                  sigma_energy=True, pressure_inlet=True, p_in=4e-3),
             ("butler_volmer", "heat_physical", "buoyancy", "sigma_energy", "pressure_inlet", "p_in")),
+    "thin_cl": (dict(thin_cl=True, ny_gdl=5, ny_cl=0), ("thin_cl",)),
+    "thin_cl_all": (dict(thin_cl=True, ny_gdl=5, ny_cl=0, butler_volmer=True, alpha_a=0.5, V_op=1.1, aj0_ref=1e5,
+                         heat_physical=True, buoyancy=(3e-3, -5e-3), sigma_energy=True, pressure_inlet=True, p_in=4e-3),
+                    ("butler_volmer", "heat_physical", "buoyancy", "sigma_energy", "pressure_inlet", "p_in")),
 }
 
 
@@ -318,7 +322,9 @@ def test_fp64_adjoint_with_model_option_matches_oracle_gradient(option):
     equilibrium potential where that branch is as large as the cathodic
     one), the physically signed reaction heat, Boussinesq buoyancy, the
     energy equation with the heat-capacity ratio, the pressure-driven inlet,
-    and all of them at once: FP64 gradient against the oracle's exact
+    the thin-film CL (the film's update transposed in the bottom row, the
+    seed of J on the film's consumption), and all of them at once with the
+    volumetric and with the thin-film CL: FP64 gradient against the oracle's exact
     discrete gradient.  The oracle's gradient without the option differs
     from it by more than 1e-5 of its maximum in every field, so the option's
     own reverse terms are what the 1e-9 bar tests."""

@@ -1,8 +1,8 @@
 """Thin-film catalyst layer (LBM_THIN_CL: a reactive wall under the GDL, the
 paper's CL of negligible thickness) on the GPU against the FP64 oracle:
 one step of arbitrary states in every material mode, FP64 runs with every
-observable and the CL profiles, the batched solver, and the adjoint's
-refusal."""
+observable and the CL profiles, and the batched solver.  The adjoint with
+the film is tested with the other adjoint parity cases."""
 import numpy as np
 import pytest
 import torch
@@ -108,11 +108,3 @@ def test_thin_cl_case_in_a_batch_equals_its_single_context():
         s.step(120)
         assert torch.equal(b.populations(i), s.populations()), w["name"]
         assert s.observables()["current_density"] == obs[i]["current_density"]
-
-
-def test_adjoint_rejects_the_thin_cl():
-    lbm = _lbm()
-    w = _thin(dict(W.cathode2d_200x40(), nx=40, ny=10, ny_channel=5, ny_gdl=4, ny_cl=1, precision=64, Re=2.0))
-    sim = lbm.Cathode.from_workload(w, independent_fields=1)
-    with pytest.raises(lbm.LbmError, match="THIN_CL"):
-        sim.forward_checkpointed(10, 5)

@@ -33,6 +33,10 @@ OPTIONS_2D = {
     "buoyancy": (dict(buoyancy=(3e-3, -5e-3)), {}),
     "sigma_energy": (dict(sigma_energy=True, heat_physical=True), {}),
     "pressure_inlet": (dict(pressure_inlet=True, p_in=4e-3), {}),
+    "thin_cl": (dict(thin_cl=True, ny_gdl=5, ny_cl=0), {}),
+    "thin_cl_all": (dict(thin_cl=True, ny_gdl=5, ny_cl=0, butler_volmer=True, alpha_a=0.5, V_op=1.1, aj0_ref=1e5,
+                         heat_physical=True, buoyancy=(3e-3, -5e-3), sigma_energy=True, pressure_inlet=True,
+                         p_in=4e-3), {}),
 }
 
 
@@ -43,7 +47,7 @@ def _case2d(over, geo_flags):
     p = L.Params.from_workload(w)
     if geo_flags.get("periodic_x"):
         p.body_force = (2e-5, 0.0)
-    g = L.Geometry(14, 10, 5, 4, 1, **geo_flags)
+    g = L.Geometry(14, 10, w["ny_channel"], w["ny_gdl"], w["ny_cl"], **geo_flags)
     phi = torch.as_tensor(W.porosity_field(w), dtype=DT)
     m = L.Model(g, p, phi=phi)
     return g, p, [phi, m.inv_k.detach().clone(), m.d_eff.detach().clone()]
