@@ -83,8 +83,19 @@ __device__ __forceinline__ void node_mu(const R (&pre)[19], const Mat<R>& mt, co
 // three; 29.3-29.9 us when the feeding lane recomputed the boundary node's
 // collision adjoint, 34.4 us when the boundary and feeding lanes took
 // separate divergent passes.
+// Registers: the instances are held to four waves per SIMD (the default
+// FP32 one at 128 VGPRs with 64 bytes per lane spilled), except the FP32
+// instances with the model options (EXT), which are left to the registers
+// they need (162 VGPRs, three waves per SIMD, no spill).  Compiled for four
+// waves, that instance spilled 100 bytes per lane and its gradients with the
+// thin-film CL and Butler-Volmer kinetics varied from run to run on
+// identical inputs (some runs NaN); unspilled it gives the same bits in
+// every run.  The FP64 EXT instances stay at four waves: left free, the
+// compiler moved part of their state into accumulation registers and their
+// gradients departed from the oracle by 1e-6 to 2e-5, while at four waves
+// (scratch spills) they match it within 1e-12 in every run.
 template <typename R, bool SEED, bool EXT = false>
-__global__ __launch_bounds__(kBlock, 4) void k_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT && sizeof(R) == 4 ? 1 : 4))) void k_adj_step(const R* __restrict__ S, const R* __restrict__ lam_in,
                                                      R* __restrict__ lam_out, R* __restrict__ grad,
                                                      const R* __restrict__ phi_f, const R* __restrict__ invk_f,
                                                      const R* __restrict__ d_f, Consts<R> k, R w) {

@@ -347,3 +347,54 @@ def test_fp64_adjoint_with_model_option_matches_oracle_gradient(option):
     _, *g0 = A.gradient(L.geometry_from_workload(base), L.Params.from_workload(base), *fields, nsteps=40, every=15)
     for ref, other in zip((gphi, gk, gd), g0):
         assert float((ref - other)[w["ny_channel"]:].abs().max()) > 1e-5 * float(ref[w["ny_channel"]:].abs().max())
+
+
+@pytest.mark.parametrize("option", ["all", "thin_cl_all"])
+def test_fp32_adjoint_with_every_option_follows_fp64(option):
+    """The FP32 instances of the reverse step that carry the model options
+    (buoyancy, sigma, the pressure-driven inlet, the thin-film CL, with
+    Butler-Volmer kinetics and the physical heat) against the FP64 GPU
+    gradient of the same case: 40 steps of FP32 rounding stay within 1e-3 of
+    each field's maximum."""
+    lbm = _lbm()
+    extra, _ = OPTIONS[option]
+    grads = {}
+    for precision in (32, 64):
+        w = W.adjoint2d(14, 10)
+        w.update(ny_channel=5, ny_gdl=4, ny_cl=1, Re=2.0, V_op=0.45, precision=precision)
+        w.update(extra)
+        sim = lbm.Cathode.from_workload(w, phi=W.porosity_field(w), independent_fields=1)
+        sim.forward_checkpointed(40, 15)
+        grads[precision] = {k: v.double().cpu() for k, v in sim.backward(1.0).items()}
+        sim.close()
+    for name in ("phi", "inv_k", "d_eff"):
+        ref, got = grads[64][name], grads[32][name]
+        err = float((got - ref).abs().max()) / float(ref.abs().max())
+        print(f"{option} fp32 d/d{name}: rel err {err:.2e}", flush=True)
+        assert torch.isfinite(got).all()
+        assert err < 1e-3, (name, err)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_option_instances_give_the_same_bits_every_run(precision):
+    """Repeated backward passes after one forward run (three segments, each
+    replayed on the second stream) with every model option and the
+    thin-film CL return the same gradient bit for bit, also from a second
+    context of the same case."""
+    lbm = _lbm()
+    extra, _ = OPTIONS["thin_cl_all"]
+    runs = []
+    for _ in range(2):
+        w = W.adjoint2d(14, 10)
+        w.update(ny_channel=5, ny_gdl=4, ny_cl=1, Re=2.0, V_op=0.45, precision=precision)
+        w.update(extra)
+        sim = lbm.Cathode.from_workload(w, phi=W.porosity_field(w), independent_fields=1)
+        sim.forward_checkpointed(40, 15)
+        for _ in range(3):
+            g = sim.backward(1.0, permeability=False)
+            runs.append({k: v.clone() for k, v in g.items()})
+        sim.close()
+    for r in runs[1:]:
+        for name in ("phi", "inv_k", "d_eff"):
+            assert torch.isfinite(r[name]).all(), name
+            assert torch.equal(r[name], runs[0][name]), name
