@@ -118,7 +118,7 @@ typedef struct lbm_geometry {
  * adds the anodic branch, j = -a j0(T) [(C/C_ref) exp(-alpha_c F eta / (R T))
  * - exp(alpha_a F eta / (R T))]; the O2 in a CL cell then relaxes over a step
  * toward exp((alpha_a + alpha_c) F eta / (R T)) instead of 0.  The adjoint
- * entry points accept the Tafel form only.
+ * entry points (2D and 3D) cover both forms.
  */
 #define LBM_KINETICS_TAFEL 0
 #define LBM_KINETICS_BUTLER_VOLMER 1
