@@ -398,3 +398,35 @@ def test_option_instances_give_the_same_bits_every_run(precision):
         for name in ("phi", "inv_k", "d_eff"):
             assert torch.isfinite(r[name]).all(), name
             assert torch.equal(r[name], runs[0][name]), name
+
+
+@pytest.mark.parametrize("case", ["periodic_x", "periodic_y"])
+def test_fp64_adjoint_with_options_on_periodic_lattices_matches_oracle_gradient(case):
+    """The option terms on periodic lattices: periodic in x with a body force
+    (no boundary columns), the thin-film CL, buoyancy, sigma and the
+    physical heat; periodic in y with the pressure-driven inlet, sigma and
+    Butler-Volmer kinetics.  FP64 gradient against the oracle's exact
+    discrete gradient."""
+    lbm = _lbm()
+    w = W.adjoint2d(14, 10)
+    if case == "periodic_x":
+        w.update(ny_channel=5, ny_gdl=5, ny_cl=0, Re=0.0, V_op=0.45, precision=64, thin_cl=True,
+                 buoyancy=(3e-3, -5e-3), sigma_energy=True, heat_physical=True)
+        flags, geo = lbm.LBM_PERIODIC_X | lbm.LBM_BODY_FORCE, dict(periodic_x=True)
+    else:
+        w.update(ny_channel=5, ny_gdl=4, ny_cl=1, Re=0.8, V_op=1.1, precision=64, pressure_inlet=True, p_in=4e-3,
+                 sigma_energy=True, butler_volmer=True, alpha_a=0.5, aj0_ref=1e5)
+        flags, geo = lbm.LBM_PERIODIC_Y, dict(periodic_y=True)
+    phi = W.porosity_field(w)
+    bf = 2e-5 if case == "periodic_x" else 0.0
+    sim = lbm.Cathode.from_workload(w, phi=phi, independent_fields=1, flags=flags, body_force_x=bf)
+    J = sim.forward_checkpointed(40, 15)
+    g = sim.backward(1.0)
+    fields = _oracle_fields(w, phi)
+    p = L.Params.from_workload(w)
+    p.body_force = (bf, 0.0)
+    g_oracle = L.Geometry(14, 10, w["ny_channel"], w["ny_gdl"], w["ny_cl"], **geo)
+    Jo, gphi, gk, gd = A.gradient(g_oracle, p, *fields, nsteps=40, every=15)
+    print(f"{case} options J gpu {J:.15e} oracle {float(Jo):.15e}", flush=True)
+    assert abs(J / float(Jo) - 1) < 1e-12
+    _compare(g, (gphi, gk, gd), w["ny_channel"], 1e-9, f"{case} options fp64")
