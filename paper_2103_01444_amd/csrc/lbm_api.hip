@@ -168,10 +168,39 @@ void launch_step_kernel(lbm_ctx* c, const R* src, R* dst, const MatPtrs<R>& m, c
     hipLaunchKernelGGL((k_step<R, MAT, false>), grid, dim3(kBlock), 0, stream, src, dst, m.phi, m.invk, m.d, k);
 }
 
+// Lattices of at least kTwoStepMinCells nodes with walls and inlet / outlet
+// columns advance two steps per launch (k_step2: the same states, bit for
+// bit, as two single steps).  Measured per step against single steps,
+// 4096x1024: FP32 99.6 -> 89.6 us, FP64 247.6 -> 177.7 us; 1024x512 5 %
+// faster in both precisions.  Smaller lattices, whose launches are bound by
+// each wavefront's own chain rather than by HBM, run slower in pairs
+// (1024x256 FP32 8.9 -> 12.5 us) and keep single steps.
+constexpr int64_t kTwoStepMinCells = int64_t(1) << 19;
+bool two_steps_per_launch(const lbm_ctx* c) {
+  return int64_t(c->g.nx) * c->g.ny >= kTwoStepMinCells &&
+         !(c->g.flags & (LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_THIN_CL));
+}
+
+// Two steps src -> (mid) -> dst; mid may be null (the middle state is not
+// stored).
+template <typename R, int MAT>
+void launch_step_pair(lbm_ctx* c, const R* src, R* mid, R* dst, const MatPtrs<R>& m, const Consts<R>& k,
+                      hipStream_t stream) {
+  const dim3 grid((c->g.nx + kT2X - 1) / kT2X, (c->g.ny + kT2Y - 1) / kT2Y);
+  hipLaunchKernelGGL((k_step2<R, MAT>), grid, dim3(kT2Threads), 0, stream, src, mid, dst, m.phi, m.invk, m.d, k);
+}
+
 template <typename R, int MAT>
 void launch_step_mat(lbm_ctx* c, int64_t n) {
   const MatPtrs<R> m = mat_ptrs<R>(c);
   const Consts<R> k = consts<R>(c);
+  if (two_steps_per_launch(c)) {
+    for (; n >= 2; n -= 2) {
+      launch_step_pair<R, MAT>(c, static_cast<const R*>(c->state(c->cur)), nullptr,
+                               static_cast<R*>(c->state(c->cur ^ 1)), m, k, c->stream);
+      c->cur ^= 1;
+    }
+  }
   for (int64_t i = 0; i < n; ++i) {
     launch_step_kernel<R, MAT>(c, static_cast<const R*>(c->state(c->cur)), static_cast<R*>(c->state(c->cur ^ 1)), m,
                                k, c->stream);
@@ -667,10 +696,19 @@ AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int32_t every) {
   return A;
 }
 
-template <typename R>
-void launch_one_step(lbm_ctx* c, const void* src, void* dst, hipStream_t stream) {
-  launch_step_kernel<R, MAT_FULL>(c, static_cast<const R*>(src), static_cast<R*>(dst), mat_ptrs<R>(c), consts<R>(c),
-                                  stream);
+// Steps from state(0) to state(n) of a chain of states, storing each: a
+// pair per launch where the lattice allows it, single steps otherwise.
+template <typename R, typename Slot>
+void launch_step_chain(lbm_ctx* c, Slot state, int n, hipStream_t stream) {
+  const MatPtrs<R> m = mat_ptrs<R>(c);
+  const Consts<R> k = consts<R>(c);
+  int j = 1;
+  if (two_steps_per_launch(c))
+    for (; j + 1 <= n; j += 2)
+      launch_step_pair<R, MAT_FULL>(c, static_cast<const R*>(state(j - 1)), static_cast<R*>(state(j)),
+                                    static_cast<R*>(state(j + 1)), m, k, stream);
+  for (; j <= n; ++j)
+    launch_step_kernel<R, MAT_FULL>(c, static_cast<const R*>(state(j - 1)), static_cast<R*>(state(j)), m, k, stream);
 }
 
 // The last segment of the checkpointed forward run steps through replay
@@ -682,9 +720,9 @@ lbm_status forward_last_segment(lbm_ctx* c, const AdjLayout& A, int64_t n) {
   const size_t sb = size_t(19) * c->L.plane * c->L.esize;
   if (hipMemcpyAsync(buf, c->state(c->cur), sb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return fail(c, LBM_ERR_DEVICE, "replay buffer copy failed");
-  for (int64_t j = 1; j < n; ++j)
-    launch_one_step<R>(c, buf + size_t(j - 1) * A.state, buf + size_t(j) * A.state, c->stream);
-  launch_one_step<R>(c, buf + size_t(n - 1) * A.state, c->state(c->cur ^ 1), c->stream);
+  void* last = c->state(c->cur ^ 1);
+  launch_step_chain<R>(c, [&](int64_t j) -> void* { return j < n ? buf + size_t(j) * A.state : last; }, int(n),
+                       c->stream);
   c->cur ^= 1;
   c->step += n;
   return check_launch(c, "forward_checkpointed");
@@ -743,9 +781,7 @@ lbm_status backward_t(lbm_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_
     if (hipMemcpyAsync(buf, ws + A.off_ck + size_t(seg) * A.state, A.state, hipMemcpyDeviceToDevice, c->aux) !=
         hipSuccess)
       return fail(c, LBM_ERR_DEVICE, "replay restore failed");
-    const int len = seg_len(seg);
-    for (int j = 1; j < len; ++j)
-      launch_one_step<R>(c, buf + size_t(j - 1) * A.state, buf + size_t(j) * A.state, c->aux);
+    launch_step_chain<R>(c, [&](int j) -> void* { return buf + size_t(j) * A.state; }, seg_len(seg) - 1, c->aux);
     if (hipEventRecord(c->ev_rep[b], c->aux) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "replay event failed");
     return LBM_OK;
   };

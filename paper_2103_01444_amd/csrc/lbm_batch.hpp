@@ -94,6 +94,26 @@ __global__ __launch_bounds__(BS) void k_batch_step(R* __restrict__ pool, const B
   batch_tile<R, MAT, ONE, UNIFORM>(pool, cases, tiles[t], parity, tx, ty);
 }
 
+// Two steps per launch: one kT2Threads workgroup per tile of kT2X x kT2Y
+// nodes (the tile list of that shape), the body of k_step2 on the tile's
+// case.  Cases with periodic axes or the thin-film CL are not scheduled so.
+template <typename R, int MAT>
+__global__ __launch_bounds__(kT2Threads) void k_batch_step2(R* __restrict__ pool,
+                                                            const BatchCase<R>* __restrict__ cases,
+                                                            const Tile* __restrict__ tiles, int ntiles, int parity) {
+  __shared__ R lds[19 * kT2N];
+  const int t = xcd_logical(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;  // the whole workgroup: no thread reaches the barrier
+  const Tile tl = tiles[t];
+  const Consts<R> k = cases[tl.c].k;
+  const R* src = pool + cases[tl.c].off[parity];
+  R* dst = pool + cases[tl.c].off[parity ^ 1];
+  const R* fields = MAT == MAT_LAYERED ? nullptr : pool + cases[tl.c].off[0] + int64_t(kFieldRow) * k.plane;
+  const R* invk_f = MAT == MAT_LAYERED ? nullptr : fields + k.plane;
+  const R* d_f = MAT == MAT_LAYERED ? nullptr : fields + 2 * k.plane;
+  step2_tile<R, MAT>(lds, src, nullptr, dst, fields, invk_f, d_f, k, tl.x0, tl.y0);
+}
+
 // Waves per SIMD the persistent kernel is compiled for (at least): the
 // compiler keeps both its vector and its scalar registers within what that
 // many waves can hold, so a grid of that many 256-lane workgroups per CU

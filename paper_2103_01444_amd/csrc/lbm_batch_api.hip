@@ -325,7 +325,15 @@ lbm_status launch_steps_mat(lbm_batch* b, int64_t nsteps) {
     const int bs = b->sched.block == 64 || b->sched.block == 128 ? b->sched.block : kBlock;
     const bool uniform = b->cells < (int64_t(1) << 20);
     const dim3 grid(b->ntiles);
-    for (int64_t s = 0; s < nsteps; ++s) {
+    int64_t s = 0;
+    if (b->sched.block == kT2Threads) {  // two steps per launch; an odd count ends with one step
+      for (; s + 2 <= nsteps; s += 2) {
+        hipLaunchKernelGGL((k_batch_step2<R, MAT>), grid, dim3(kT2Threads), 0, b->stream, pool, cases, tiles,
+                           b->ntiles, b->parity);
+        b->parity ^= 1;
+      }
+    }
+    for (; s < nsteps; ++s) {
       if (bs == 64) {
         if (uniform)
           hipLaunchKernelGGL((k_batch_step<R, MAT, true, true, 64>), grid, dim3(64), 0, b->stream, pool, cases, tiles,
@@ -373,8 +381,15 @@ lbm_status set_schedule_t(lbm_batch* b, const lbm_schedule& s) {
   if (s.tile_x < 1 || s.tile_y < 1 || s.tile_x * s.tile_y < kMinTileCells || s.tile_x * s.tile_y > 1 << 16)
     return bfail(b, LBM_ERR_INVALID_ARG, "tile shape out of range");
   if (!(s.block == 0 || s.block == kBlock ||
-        ((s.block == 64 || s.block == 128) && s.tile_x * s.tile_y == s.block && !s.persistent)))
-    return bfail(b, LBM_ERR_INVALID_ARG, "workgroup size: 0 or 256, or 64 / 128 for a per-step tile of as many cells");
+        ((s.block == 64 || s.block == 128) && s.tile_x * s.tile_y == s.block && !s.persistent) ||
+        (s.block == kT2Threads && s.tile_x == kT2X && s.tile_y == kT2Y && !s.persistent)))
+    return bfail(b, LBM_ERR_INVALID_ARG,
+                 "workgroup size: 0 or 256, 64 / 128 for a per-step tile of as many cells, or 960 for the "
+                 "two-step form of 64 x 12 tiles");
+  if (s.block == kT2Threads)
+    for (int i = 0; i < b->n; ++i)
+      if (b->g[i].flags & (LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_THIN_CL))
+        return bfail(b, LBM_ERR_INVALID_ARG, "the two-step form needs walls and inlet / outlet columns, no thin-film CL");
   b->sched = s;
   if (lbm_status st = build_tiles(b, s.tile_x, s.tile_y); st != LBM_OK) return st;
   if (s.persistent)
@@ -486,6 +501,7 @@ lbm_status autotune_t(lbm_batch* b, int trial_steps, lbm_schedule* best, double*
       const int cells = sh[0] * sh[1];
       if (!persistent && (cells == 64 || cells == 128)) cand.push_back({sh[0], sh[1], 0, cells});
     }
+  cand.push_back({kT2X, kT2Y, 0, kT2Threads});
   for (const lbm_schedule& s : cand) {
     const int persistent = s.persistent;
     if (set_schedule_t<R>(b, s) != LBM_OK) continue;  // shape not usable here

@@ -62,6 +62,96 @@ __global__ __launch_bounds__(kBlock) void k_step(const R* __restrict__ src, R* _
   }
 }
 
+// Two time steps in one launch, for lattices large enough to be bound by
+// HBM: a workgroup advances a tile of kT2X x kT2Y nodes.  Step one runs over
+// the tile and a halo (two columns on the left, where the outlet's feeding
+// column can lie, one elsewhere, and a row above and below), one node per
+// thread, from the state in memory, and keeps the post-collision
+// populations in LDS, writing the tile's own to `mid` when that is given;
+// step two pulls the tile's nodes from LDS and writes `dst`.  Every node
+// runs the same code as k_step, so the states are the bits of two single
+// steps.  HBM traffic per step halves; the halo nodes (22 % of step one)
+// are computed twice.  Twelve rows: the largest tile whose step one fits
+// one pass of a workgroup (938 nodes, 960 threads); FP64 holds 143 KB of
+// LDS, one workgroup per CU.  Walls and inlet / outlet columns only: the
+// host keeps single steps on periodic lattices and with the thin-film CL.
+constexpr int kT2X = 64, kT2Y = 12;
+constexpr int kT2W = kT2X + 3;                  // LDS row: x0 - 2 .. x0 + kT2X
+constexpr int kT2N = kT2W * (kT2Y + 2);         // LDS rows: y0 - 1 .. y0 + kT2Y
+constexpr int kT2Threads = (kT2N + 63) / 64 * 64;
+static_assert(kT2Threads <= 1024 && kT2X * kT2Y <= kT2Threads, "two-step tile");
+
+// Pull of node (x, y) from the step-one populations of the tile at (x0, y0).
+template <typename R>
+__device__ __forceinline__ void pull_tile(const R* __restrict__ lds, const Consts<R>& k, int x, int y, int x0,
+                                          int y0, R (&f)[19]) {
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const int xs = x - EX[q], ys = y - EY[q];
+    const bool in = (unsigned)xs < (unsigned)k.nx && (unsigned)ys < (unsigned)k.ny;
+    const int n = in ? (ys - y0 + 1) * kT2W + (xs - x0 + 2) : (y - y0 + 1) * kT2W + (x - x0 + 2);
+    f[q] = lds[(in ? q : OPP[q]) * kT2N + n];
+  }
+}
+
+// The two steps of the tile at (x0, y0), called by every thread of a
+// kT2Threads workgroup (it holds a workgroup barrier).
+template <typename R, int MAT>
+__device__ __forceinline__ void step2_tile(R* __restrict__ lds, const R* __restrict__ src, R* __restrict__ mid,
+                                           R* __restrict__ dst, const R* __restrict__ phi_f,
+                                           const R* __restrict__ invk_f, const R* __restrict__ d_f,
+                                           const Consts<R>& k, int x0, int y0) {
+  const bool react = !(k.flags & F_NO_REACTION);
+  {
+    const int n = threadIdx.x;
+    const int i = n % kT2W, j = n / kT2W;
+    const int x = x0 - 2 + i, y = y0 - 1 + j;
+    if (n < kT2N && (unsigned)x < (unsigned)k.nx && (unsigned)y < (unsigned)k.ny) {
+      R f[19];
+      const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);
+      collide(f, mt, k, react && y >= k.y_cl0);
+#pragma unroll
+      for (int q = 0; q < 19; ++q) lds[q * kT2N + n] = f[q];
+      if (mid && i >= 2 && i < kT2X + 2 && j >= 1 && j <= kT2Y) {
+        const int o = y * k.pitch + x;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) mid[q * k.plane + o] = f[q];
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x >= kT2X * kT2Y) return;
+  const int x = x0 + int(threadIdx.x) % kT2X, y = y0 + int(threadIdx.x) / kT2X;
+  if (x >= k.nx || y >= k.ny) return;
+  const bool inlet = x == 0 && y < k.ny_ch;
+  const bool outlet = x == k.nx - 1;
+  const int xp = inlet ? 1 : (outlet ? k.nx - 2 : x);
+  R f[19];
+  pull_tile(lds, k, xp, y, x0, y0, f);
+  Mat<R> mt = material<R, MAT>(k, phi_f, invk_f, d_f, xp, y);
+  if (inlet || outlet) {
+    Mat<R> mb = material<R, MAT>(k, phi_f, invk_f, d_f, x, y);
+    boundary_column(f, k, y, inlet, mt, mb);
+    if (outlet) outlet_scalar_material(mb, mt);
+    mt = mb;
+  }
+  collide(f, mt, k, react && y >= k.y_cl0);
+  const int o = y * k.pitch + x;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
+}
+
+template <typename R, int MAT>
+__global__ __launch_bounds__(kT2Threads) void k_step2(const R* __restrict__ src, R* __restrict__ mid,
+                                                      R* __restrict__ dst, const R* __restrict__ phi_f,
+                                                      const R* __restrict__ invk_f, const R* __restrict__ d_f,
+                                                      Consts<R> k) {
+  __shared__ R lds[19 * kT2N];
+  int bx, by;
+  xcd_tile(gridDim.x, gridDim.y, bx, by);
+  step2_tile<R, MAT>(lds, src, mid, dst, phi_f, invk_f, d_f, k, bx * kT2X, by * kT2Y);
+}
+
 // Equilibrium initial state: rest fluid at zero pressure (shifted f = 0),
 // theta = 0, O2 at c_in.
 template <typename R, int MAT>

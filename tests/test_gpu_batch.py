@@ -65,7 +65,7 @@ def test_persistent_barrier_timeout_is_an_error_then_recovers():
 
 
 @pytest.mark.parametrize("sched", [(64, 4, 0), (512, 2, 0), (128, 2, 1), (256, 1, 1), (64, 16, 1), (128, 1, 0, 128),
-                                   (32, 2, 0, 64), (128, 1, 0, 0)])
+                                   (32, 2, 0, 64), (128, 1, 0, 0), (64, 12, 0, 960)])
 def test_every_schedule_gives_identical_results(sched):
     lbm = _lbm()
     cases = _cases()
@@ -170,7 +170,8 @@ def _perturbed_fields(lbm, w, gen, which):
 
 
 @pytest.mark.parametrize("sched,precision", [((128, 1, 0, 0), 32), ((256, 1, 1, 0), 32), ((64, 4, 0, 0), 32),
-                                             ((256, 1, 0, 0), 64), ((128, 2, 1, 0), 64)])
+                                             ((256, 1, 0, 0), 64), ((128, 2, 1, 0), 64), ((64, 12, 0, 960), 32),
+                                             ((64, 12, 0, 960), 64)])
 def test_cases_with_per_cell_fields_equal_single_contexts_bitwise(sched, precision):
     """A batch whose cases carry per-cell fields (LBM_CELL_FIELDS): case 0
     gets porosity, 1/K and D_eff, case 1 porosity only, case 2 none (derived
@@ -213,4 +214,33 @@ def test_per_cell_fields_need_the_flag_and_valid_values():
     bad[-1, 3] = 1.5
     with pytest.raises(lbm.LbmError, match="porosity"):
         b.set_fields(1, phi=bad)
+    b.close()
+
+
+def test_two_step_schedule_limits():
+    """The two-step form (960-thread workgroups) takes 64 x 12 tiles and no
+    persistent launch, and is refused for a batch with a thin-film CL case; the
+    pressure-driven polarisation cases take it and equal their single
+    contexts bit for bit over an odd step count."""
+    lbm = _lbm()
+    cases = _cases(3)
+    b = lbm.BatchedSweep(cases)
+    for bad in ((64, 8, 0, 960), (128, 12, 0, 960), (64, 12, 1, 960)):
+        with pytest.raises(lbm.LbmError, match="invalid argument"):
+            b.set_schedule(*bad)
+    b.close()
+    thin = dict(cases[0], thin_cl=True, ny_gdl=cases[0]["ny_gdl"] + cases[0]["ny_cl"], ny_cl=0)
+    t = lbm.BatchedSweep([thin, cases[1]])
+    with pytest.raises(lbm.LbmError, match="invalid argument"):
+        t.set_schedule(64, 12, 0, 960)
+    t.close()
+    pol = W.polarisation_sweep(steps=200)[:4]
+    b = lbm.BatchedSweep(pol)
+    b.set_schedule(64, 12, 0, 960)
+    b.step(33)
+    for i, w in enumerate(pol):
+        single = lbm.Cathode.from_workload(w)
+        single.step(33)
+        assert torch.equal(b.populations(i), single.populations()), w["name"]
+        single.close()
     b.close()

@@ -205,7 +205,7 @@ def _full_size_case():
 
 def test_full_size_one_step_from_arbitrary_state():
     """4096x1024 FP32, porosity field: one update of an arbitrary state over
-    the whole lattice (the kernel and launch shape the benchmark times)."""
+    the whole lattice (the single-step kernel, which ends odd step counts)."""
     lbm = _gpu_mod()
     w, phi = _full_size_case()
     pops = W.random_populations(w["ny"], w["nx"], 4242).astype(np.float32).astype(np.float64)
@@ -218,6 +218,24 @@ def test_full_size_one_step_from_arbitrary_state():
     err = float((out - ref).abs().max())
     print(f"full size one step: max |df| = {err:.2e}", flush=True)
     assert err < 2e-6
+
+
+def test_full_size_two_steps_from_arbitrary_state():
+    """4096x1024 FP32, porosity field: two updates of an arbitrary state in
+    one launch of the two-step kernel over the whole lattice (the kernel and
+    launch shape the benchmark times), against two oracle steps."""
+    lbm = _gpu_mod()
+    w, phi = _full_size_case()
+    pops = W.random_populations(w["ny"], w["nx"], 4243).astype(np.float32).astype(np.float64)
+    gpu = lbm.Cathode.from_workload(w, phi=phi)
+    gpu.set_populations(torch.from_numpy(pops))
+    gpu.step(2)
+    out = gpu.populations().double().cpu()
+    m = oracle_for(w, phi=phi)
+    ref = m.step(m.step(torch.from_numpy(pops)))
+    err = float((out - ref).abs().max())
+    print(f"full size two steps: max |df| = {err:.2e}", flush=True)
+    assert err < 4e-6
 
 
 def _window_oracle(w, phi, x0, x1, n):

@@ -1,0 +1,166 @@
+"""Two steps per launch on lattices of at least 2^19 nodes: a run of n steps
+in one call (pairs of steps per launch, a single step for an odd count)
+against n calls of one step each, bit for bit.  The shapes put the outlet
+column at the first column of a tile (its feeding column then lies two
+columns into the tile's halo), leave ragged tiles in x and in y (tiles are
+64 x 12 nodes), or are exactly 2^19 nodes; each material mode, the model
+options and both precisions.  Periodic lattices and the thin-film CL keep
+single steps and must give the same bits as well.  The parity of these
+states with the oracle is checked elsewhere (the same kernels' node code at
+smaller sizes, and the full-size samples); this pins that the pairing
+changes nothing."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import lbm2d as L
+
+pytestmark = pytest.mark.gpu
+
+# nx - 1 = 1024 starts a tile, 515 = 42 * 12 + 11 rows; 1090 = 17 * 64 + 2
+# columns, 490 = 40 * 12 + 10 rows; 2048 x 256 and 8192 x 64 are 2^19 nodes
+# with 256 = 21 * 12 + 4 and 64 = 5 * 12 + 4 rows.
+SHAPES = [(1025, 515), (1090, 490), (2048, 256), (8192, 64)]
+OPTIONS = {
+    "butler_volmer_heat": dict(butler_volmer=True, alpha_a=0.5, V_op=1.1, aj0_ref=1e5, heat_physical=True),
+    "buoyancy_sigma": dict(buoyancy=(3e-7, -5e-7), sigma_energy=True, heat_physical=True),
+    "pressure_inlet_outlet": dict(pressure_inlet=True, p_in=4e-4, p_out=1e-4),
+    "no_cl": {},  # the CL rows join the GDL
+}
+
+
+def _lbm():
+    from paper_2103_01444_amd import lbm
+    return lbm
+
+
+def _workload(nx, ny, precision, opts=None):
+    w = W.cathode2d_scaled(nx, ny, precision=precision)
+    w["Re"] = min(w["Re"], 0.2 * w["ny_channel"])  # inlet peak velocity within the stable range
+    w.update(opts or {})
+    return w
+
+
+def _fields(w, mode):
+    """Per-cell arrays of a material mode: none (layered), porosity only,
+    or all three independent."""
+    phi = torch.as_tensor(W.porosity_field(w))
+    if mode == "layered":
+        return {}
+    if mode == "phi":
+        return dict(phi=phi)
+    p = L.Params.from_workload(w)
+    m = L.Model(L.Geometry(w["nx"], w["ny"], w["ny_channel"], w["ny_gdl"], w["ny_cl"]), p, phi=phi)
+    return dict(phi=phi, inv_k=m.inv_k.detach().clone(), d_eff=m.d_eff.detach().clone(), independent_fields=1)
+
+
+def _bits(t):
+    return t.contiguous().view(torch.int64 if t.dtype == torch.float64 else torch.int32)
+
+
+def _pair(w, mode, flags=0, **over):
+    lbm = _lbm()
+    f = _fields(w, mode)
+    return [lbm.Cathode.from_workload(w, flags=flags, **f, **over) for _ in range(2)]
+
+
+def _check_same(a, b, label, finite=True):
+    pa, pb = a.populations(), b.populations()
+    same = torch.equal(_bits(pa), _bits(pb))
+    print(f"{label}: {'identical' if same else 'DIFFERENT'}", flush=True)
+    assert same, label
+    assert not finite or bool(torch.isfinite(pa).all()), label
+
+
+def _run(a, b, n):
+    a.step(n)
+    for _ in range(n):
+        b.step(1)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+@pytest.mark.parametrize("mode", ["layered", "phi", "full"])
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{s[0]}x{s[1]}" for s in SHAPES])
+def test_steps_in_pairs_equal_single_steps(shape, mode, precision):
+    nx, ny = shape
+    w = _workload(nx, ny, precision)
+    a, b = _pair(w, mode)
+    _run(a, b, 40)
+    _check_same(a, b, f"{nx}x{ny} {mode} fp{precision} 40 steps")
+    # an arbitrary state, odd count (three pairs and one single step)
+    pops = torch.from_numpy(W.random_populations(ny, nx, 7 + nx))
+    a.set_populations(pops)
+    b.set_populations(pops)
+    _run(a, b, 7)
+    _check_same(a, b, f"{nx}x{ny} {mode} fp{precision} 7 steps from an arbitrary state", finite=False)
+    assert a.step_count == b.step_count == 7
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+@pytest.mark.parametrize("option", list(OPTIONS))
+def test_steps_in_pairs_equal_single_steps_with_options(option, precision):
+    w = _workload(1025, 515, precision, OPTIONS[option])
+    if option == "no_cl":
+        w.update(ny_gdl=w["ny_gdl"] + w["ny_cl"], ny_cl=0)
+    a, b = _pair(w, "full")
+    _run(a, b, 30)
+    _check_same(a, b, f"{option} fp{precision}")
+
+
+@pytest.mark.parametrize("case", ["periodic_x", "periodic_y", "thin_cl"])
+def test_single_step_lattices_unchanged(case):
+    """Configurations that keep one step per launch at any size."""
+    lbm = _lbm()
+    w = _workload(1025, 515, 64)
+    if case == "thin_cl":
+        w.update(thin_cl=True, ny_gdl=w["ny_gdl"] + w["ny_cl"], ny_cl=0)
+        a, b = _pair(w, "phi")
+    elif case == "periodic_x":
+        a, b = _pair(w, "phi", flags=lbm.LBM_PERIODIC_X | lbm.LBM_BODY_FORCE, body_force_x=1e-7)
+    else:
+        a, b = _pair(w, "phi", flags=lbm.LBM_PERIODIC_Y)
+    _run(a, b, 20)
+    _check_same(a, b, case)
+
+
+def test_below_the_size_threshold():
+    """One column short of 2^19 nodes (single steps) and at it (pairs): both
+    equal single steps."""
+    for nx in (2047, 2048):
+        w = _workload(nx, 256, 32)
+        a, b = _pair(w, "phi")
+        _run(a, b, 12)
+        _check_same(a, b, f"{nx}x256")
+
+
+def test_checkpointed_forward_ends_on_the_plain_run():
+    """The checkpointed forward run (its last segment stepped in pairs
+    through the replay buffer, storing the middle states) ends on the state
+    and the current density of the plain run."""
+    w = _workload(1025, 515, 32)
+    c, d = _pair(w, "full")
+    J = c.forward_checkpointed(45, 20)
+    d.step(45)
+    _check_same(c, d, "1025x515 checkpointed forward, 45 steps")
+    assert J == d.observables()["current_density"]
+    assert np.isfinite(J)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_adjoint_with_replayed_pairs_equals_adjoint_without_replay(precision):
+    """Checkpoints every 20 steps (segments replayed in pairs, the middle
+    states stored for the reverse sweep) against a checkpoint every step
+    (no replay, single steps only): the same gradient bits."""
+    w = _workload(1025, 515, precision)
+    a, b = _pair(w, "full")
+    Ja = a.forward_checkpointed(45, 20)
+    Jb = b.forward_checkpointed(45, 1)
+    assert Ja == Jb
+    ga = a.backward(1.0, permeability=False)
+    gb = b.backward(1.0, permeability=False)
+    for key in ("inv_k", "phi", "d_eff"):
+        same = torch.equal(_bits(ga[key]), _bits(gb[key]))
+        print(f"fp{precision} d/d{key}: {'identical' if same else 'DIFFERENT'}", flush=True)
+        assert same, key
+    assert float(ga["phi"].abs().max()) > 0
