@@ -176,6 +176,9 @@ void launch_step_kernel(lbm_ctx* c, const R* src, R* dst, const MatPtrs<R>& m, c
 // each wavefront's own chain rather than by HBM, run slower in pairs
 // (1024x256 FP32 8.9 -> 12.5 us) and keep single steps.
 constexpr int64_t kTwoStepMinCells = int64_t(1) << 19;
+// FP32 lattices of at least this many nodes take non-temporal loads in
+// step one (k_step2's NT), the others cached loads.
+constexpr int64_t kTwoStepStreamCells = int64_t(1) << 22;
 bool two_steps_per_launch(const lbm_ctx* c) {
   return int64_t(c->g.nx) * c->g.ny >= kTwoStepMinCells &&
          !(c->g.flags & (LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_THIN_CL));
@@ -187,7 +190,12 @@ template <typename R, int MAT>
 void launch_step_pair(lbm_ctx* c, const R* src, R* mid, R* dst, const MatPtrs<R>& m, const Consts<R>& k,
                       hipStream_t stream) {
   const dim3 grid((c->g.nx + kT2X - 1) / kT2X, (c->g.ny + kT2Y - 1) / kT2Y);
-  hipLaunchKernelGGL((k_step2<R, MAT>), grid, dim3(kT2Threads), 0, stream, src, mid, dst, m.phi, m.invk, m.d, k);
+  if (sizeof(R) == 4 && int64_t(c->g.nx) * c->g.ny >= kTwoStepStreamCells)
+    hipLaunchKernelGGL((k_step2<R, MAT, true>), grid, dim3(kT2Threads), 0, stream, src, mid, dst, m.phi, m.invk, m.d,
+                       k);
+  else
+    hipLaunchKernelGGL((k_step2<R, MAT, false>), grid, dim3(kT2Threads), 0, stream, src, mid, dst, m.phi, m.invk,
+                       m.d, k);
 }
 
 template <typename R, int MAT>

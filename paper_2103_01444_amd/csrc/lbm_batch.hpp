@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kT2Threads) void k_batch_step2(R* __restrict__ pool
   const R* fields = MAT == MAT_LAYERED ? nullptr : pool + cases[tl.c].off[0] + int64_t(kFieldRow) * k.plane;
   const R* invk_f = MAT == MAT_LAYERED ? nullptr : fields + k.plane;
   const R* d_f = MAT == MAT_LAYERED ? nullptr : fields + 2 * k.plane;
-  step2_tile<R, MAT>(lds, src, nullptr, dst, fields, invk_f, d_f, k, tl.x0, tl.y0);
+  step2_tile<R, MAT, false>(lds, src, nullptr, dst, fields, invk_f, d_f, k, tl.x0, tl.y0);
 }
 
 // Waves per SIMD the persistent kernel is compiled for (at least): the

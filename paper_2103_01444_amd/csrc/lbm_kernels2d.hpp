@@ -95,8 +95,13 @@ __device__ __forceinline__ void pull_tile(const R* __restrict__ lds, const Const
 }
 
 // The two steps of the tile at (x0, y0), called by every thread of a
-// kT2Threads workgroup (it holds a workgroup barrier).
-template <typename R, int MAT>
+// kT2Threads workgroup (it holds a workgroup barrier).  NT: non-temporal
+// loads in step one.  Cached loads let the L2 serve the halo lines that
+// neighbouring tiles also read; measured (µs per step, non-temporal ->
+// cached): FP64 4096x1024 176.2 -> 167.2, FP32 2048x512 24.7 -> 23.4,
+// 1024x512 14.6 -> 14.0, but FP32 4096x1024 89.0 -> 90.2, whose tile rows
+// are too long for that reuse.
+template <typename R, int MAT, bool NT>
 __device__ __forceinline__ void step2_tile(R* __restrict__ lds, const R* __restrict__ src, R* __restrict__ mid,
                                            R* __restrict__ dst, const R* __restrict__ phi_f,
                                            const R* __restrict__ invk_f, const R* __restrict__ d_f,
@@ -108,7 +113,7 @@ __device__ __forceinline__ void step2_tile(R* __restrict__ lds, const R* __restr
     const int x = x0 - 2 + i, y = y0 - 1 + j;
     if (n < kT2N && (unsigned)x < (unsigned)k.nx && (unsigned)y < (unsigned)k.ny) {
       R f[19];
-      const Mat<R> mt = pre_collision<R, MAT>(src, k, phi_f, invk_f, d_f, x, y, f);
+      const Mat<R> mt = pre_collision<R, MAT, NT>(src, k, phi_f, invk_f, d_f, x, y, f);
       collide(f, mt, k, react && y >= k.y_cl0);
 #pragma unroll
       for (int q = 0; q < 19; ++q) lds[q * kT2N + n] = f[q];
@@ -141,7 +146,7 @@ __device__ __forceinline__ void step2_tile(R* __restrict__ lds, const R* __restr
   for (int q = 0; q < 19; ++q) dst[q * k.plane + o] = f[q];
 }
 
-template <typename R, int MAT>
+template <typename R, int MAT, bool NT>
 __global__ __launch_bounds__(kT2Threads) void k_step2(const R* __restrict__ src, R* __restrict__ mid,
                                                       R* __restrict__ dst, const R* __restrict__ phi_f,
                                                       const R* __restrict__ invk_f, const R* __restrict__ d_f,
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(const R* __restrict__ src,
   __shared__ R lds[19 * kT2N];
   int bx, by;
   xcd_tile(gridDim.x, gridDim.y, bx, by);
-  step2_tile<R, MAT>(lds, src, mid, dst, phi_f, invk_f, d_f, k, bx * kT2X, by * kT2Y);
+  step2_tile<R, MAT, NT>(lds, src, mid, dst, phi_f, invk_f, d_f, k, bx * kT2X, by * kT2Y);
 }
 
 // Equilibrium initial state: rest fluid at zero pressure (shifted f = 0),
