@@ -179,9 +179,11 @@ constexpr int64_t kTwoStepMinCells = int64_t(1) << 19;
 // FP32 lattices of at least this many nodes take non-temporal loads in
 // step one (k_step2's NT), the others cached loads.
 constexpr int64_t kTwoStepStreamCells = int64_t(1) << 22;
+bool two_step_form_applies(const lbm_ctx* c) {
+  return !(c->g.flags & (LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_THIN_CL));
+}
 bool two_steps_per_launch(const lbm_ctx* c) {
-  return int64_t(c->g.nx) * c->g.ny >= kTwoStepMinCells &&
-         !(c->g.flags & (LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_THIN_CL));
+  return int64_t(c->g.nx) * c->g.ny >= kTwoStepMinCells && two_step_form_applies(c);
 }
 
 // Two steps src -> (mid) -> dst; mid may be null (the middle state is not
@@ -706,12 +708,17 @@ AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int32_t every) {
 
 // Steps from state(0) to state(n) of a chain of states, storing each: a
 // pair per launch where the lattice allows it, single steps otherwise.
+// overlapped: the chain runs beside other work (the adjoint's replay, on
+// the second stream during a reverse sweep), where pairs pay at any size:
+// they store three states per two steps instead of four, and the latency
+// of a launch is hidden (1024x256 FP32 adjoint 10.28 -> 10.55 GLUPS, the
+// same gradient bits; run alone, pairs at that size are slower).
 template <typename R, typename Slot>
-void launch_step_chain(lbm_ctx* c, Slot state, int n, hipStream_t stream) {
+void launch_step_chain(lbm_ctx* c, Slot state, int n, hipStream_t stream, bool overlapped) {
   const MatPtrs<R> m = mat_ptrs<R>(c);
   const Consts<R> k = consts<R>(c);
   int j = 1;
-  if (two_steps_per_launch(c))
+  if (overlapped ? two_step_form_applies(c) : two_steps_per_launch(c))
     for (; j + 1 <= n; j += 2)
       launch_step_pair<R, MAT_FULL>(c, static_cast<const R*>(state(j - 1)), static_cast<R*>(state(j)),
                                     static_cast<R*>(state(j + 1)), m, k, stream);
@@ -730,7 +737,7 @@ lbm_status forward_last_segment(lbm_ctx* c, const AdjLayout& A, int64_t n) {
     return fail(c, LBM_ERR_DEVICE, "replay buffer copy failed");
   void* last = c->state(c->cur ^ 1);
   launch_step_chain<R>(c, [&](int64_t j) -> void* { return j < n ? buf + size_t(j) * A.state : last; }, int(n),
-                       c->stream);
+                       c->stream, false);
   c->cur ^= 1;
   c->step += n;
   return check_launch(c, "forward_checkpointed");
@@ -789,7 +796,8 @@ lbm_status backward_t(lbm_ctx* c, double dJ, void* g_invk, void* g_phi, void* g_
     if (hipMemcpyAsync(buf, ws + A.off_ck + size_t(seg) * A.state, A.state, hipMemcpyDeviceToDevice, c->aux) !=
         hipSuccess)
       return fail(c, LBM_ERR_DEVICE, "replay restore failed");
-    launch_step_chain<R>(c, [&](int j) -> void* { return buf + size_t(j) * A.state; }, seg_len(seg) - 1, c->aux);
+    launch_step_chain<R>(c, [&](int j) -> void* { return buf + size_t(j) * A.state; }, seg_len(seg) - 1, c->aux,
+                         true);
     if (hipEventRecord(c->ev_rep[b], c->aux) != hipSuccess) return fail(c, LBM_ERR_DEVICE, "replay event failed");
     return LBM_OK;
   };

@@ -148,11 +148,13 @@ def test_checkpointed_forward_ends_on_the_plain_run():
 
 
 @pytest.mark.parametrize("precision", [32, 64])
-def test_adjoint_with_replayed_pairs_equals_adjoint_without_replay(precision):
+@pytest.mark.parametrize("shape", [(1025, 515), (65, 13), (130, 23)], ids=["1025x515", "65x13", "130x23"])
+def test_adjoint_with_replayed_pairs_equals_adjoint_without_replay(shape, precision):
     """Checkpoints every 20 steps (segments replayed in pairs, the middle
-    states stored for the reverse sweep) against a checkpoint every step
-    (no replay, single steps only): the same gradient bits."""
-    w = _workload(1025, 515, precision)
+    states stored for the reverse sweep; the replay runs beside the reverse
+    sweep and takes pairs at any lattice size) against a checkpoint every
+    step (no replay, single steps only): the same gradient bits."""
+    w = _workload(*shape, precision)
     a, b = _pair(w, "full")
     Ja = a.forward_checkpointed(45, 20)
     Jb = b.forward_checkpointed(45, 1)
