@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_LU_POPS = 19 * 4 * 2  # 19 FP32 populations read and written per lattice update
 BYTES_PER_LU_PHI = 4            # per-cell porosity read
 # The library advances lattices of at least this many nodes (with walls and
-# inlet / outlet columns, no thin-film CL) two steps per launch (k_step2).
+# inlet / outlet columns: no periodic axis) two steps per launch (k_step2).
 TWO_STEP_MIN_CELLS = 1 << 19
 # Committed rocprofv3 counter summaries (HBM bytes per launch) and the
 # sources of the kernel each one measured.

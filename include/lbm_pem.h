@@ -213,9 +213,9 @@ lbm_status lbm_set_params(lbm_ctx* ctx, const lbm_params* p, const void* phi, co
 lbm_status lbm_init_equilibrium(lbm_ctx* ctx);
 
 /* Advance nsteps time steps (Eq. 1 and the scalar equation of Eq. 10 with
- * the CL source).  Lattices of 2^19 nodes or more without periodic axes or
- * the thin-film CL advance two steps per kernel launch (an odd count ends
- * with a single step); the states are bit-identical to single steps.
+ * the CL source).  Lattices of 2^19 nodes or more without periodic axes
+ * advance two steps per kernel launch (an odd count ends with a single
+ * step); the states are bit-identical to single steps.
  * Async; never synchronizes. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
@@ -341,7 +341,7 @@ typedef struct lbm_schedule {
                             * exactly that many cells (one per thread); the persistent form uses 256.
                             * 960 with 64 x 12 tiles and persistent = 0: two steps per launch (a tile and
                             * its halo in LDS; an odd count ends with one step), for batches without
-                            * periodic axes or the thin-film CL */
+                            * periodic axes */
 } lbm_schedule;
 
 /* Device workspace for ncases lattices (state pool, autotuning backup,

@@ -180,7 +180,7 @@ constexpr int64_t kTwoStepMinCells = int64_t(1) << 19;
 // step one (k_step2's NT), the others cached loads.
 constexpr int64_t kTwoStepStreamCells = int64_t(1) << 22;
 bool two_step_form_applies(const lbm_ctx* c) {
-  return !(c->g.flags & (LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_THIN_CL));
+  return !(c->g.flags & (LBM_PERIODIC_X | LBM_PERIODIC_Y));
 }
 bool two_steps_per_launch(const lbm_ctx* c) {
   return int64_t(c->g.nx) * c->g.ny >= kTwoStepMinCells && two_step_form_applies(c);

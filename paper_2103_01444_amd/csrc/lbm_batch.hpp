@@ -96,7 +96,7 @@ __global__ __launch_bounds__(BS) void k_batch_step(R* __restrict__ pool, const B
 
 // Two steps per launch: one kT2Threads workgroup per tile of kT2X x kT2Y
 // nodes (the tile list of that shape), the body of k_step2 on the tile's
-// case.  Cases with periodic axes or the thin-film CL are not scheduled so.
+// case.  Cases with periodic axes are not scheduled so.
 template <typename R, int MAT>
 __global__ __launch_bounds__(kT2Threads) void k_batch_step2(R* __restrict__ pool,
                                                             const BatchCase<R>* __restrict__ cases,

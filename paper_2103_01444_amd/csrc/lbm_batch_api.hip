@@ -388,8 +388,8 @@ lbm_status set_schedule_t(lbm_batch* b, const lbm_schedule& s) {
                  "two-step form of 64 x 12 tiles");
   if (s.block == kT2Threads)
     for (int i = 0; i < b->n; ++i)
-      if (b->g[i].flags & (LBM_PERIODIC_X | LBM_PERIODIC_Y | LBM_THIN_CL))
-        return bfail(b, LBM_ERR_INVALID_ARG, "the two-step form needs walls and inlet / outlet columns, no thin-film CL");
+      if (b->g[i].flags & (LBM_PERIODIC_X | LBM_PERIODIC_Y))
+        return bfail(b, LBM_ERR_INVALID_ARG, "the two-step form needs walls and inlet / outlet columns (no periodic axis)");
   b->sched = s;
   if (lbm_status st = build_tiles(b, s.tile_x, s.tile_y); st != LBM_OK) return st;
   if (s.persistent)

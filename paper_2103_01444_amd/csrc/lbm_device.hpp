@@ -339,6 +339,19 @@ struct React;
 template <typename R>
 __device__ __forceinline__ React<R> surface_reaction(R g_t, R g_c, const Mat<R>& m, const Consts<R>& k);
 
+// Thin-film CL (Section 1): on the row above the reactive wall, planes 13
+// and 18 hold the bounced-back populations that crossed the wall; the
+// surface reaction adds its heat (sigma theta with the heat-capacity ratio)
+// and removes its O2.  mp: the material of the pulled column.
+template <typename R>
+__device__ __forceinline__ void thin_film(R (&f)[19], const Mat<R>& mp, const Consts<R>& k, int y) {
+  if ((k.flags & F_THIN_CL) && !(k.flags & F_NO_REACTION) && y == k.ny - 1) {
+    const React<R> r = surface_reaction(f[13], f[18], mp, k);
+    f[13] += r.S_T * mp.sig;
+    f[18] -= r.s_c;
+  }
+}
+
 template <typename R, int MAT, bool NT = true, bool UNIFORM = false>
 __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const Consts<R>& k,
                                                 const R* __restrict__ phi_f,
@@ -351,13 +364,7 @@ __device__ __forceinline__ Mat<R> pre_collision(const R* __restrict__ src, const
   const int xp = inlet ? 1 : (outlet ? k.nx - 2 : x);
   pull<R, NT, UNIFORM>(src, k, xp, y, f);
   Mat<R> mp = material<R, MAT>(k, phi_f, invk_f, d_f, xp, y);
-  if ((k.flags & F_THIN_CL) && !(k.flags & F_NO_REACTION) && y == k.ny - 1) {
-    // thin-film CL: planes 13 and 18 hold the bounced-back populations that
-    // crossed the reactive wall below this row
-    const React<R> r = surface_reaction(f[13], f[18], mp, k);
-    f[13] += r.S_T * mp.sig;  // energy sigma theta with the heat-capacity ratio
-    f[18] -= r.s_c;
-  }
+  thin_film(f, mp, k, y);
   if (!(inlet || outlet)) return mp;
   Mat<R> mb = material<R, MAT>(k, phi_f, invk_f, d_f, x, y);
   boundary_column(f, k, y, inlet, mp, mb);

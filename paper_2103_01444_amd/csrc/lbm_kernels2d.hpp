@@ -73,8 +73,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const R* __restrict__ src, R* _
 // steps.  HBM traffic per step halves; the halo nodes (22 % of step one)
 // are computed twice.  Twelve rows: the largest tile whose step one fits
 // one pass of a workgroup (938 nodes, 960 threads); FP64 holds 143 KB of
-// LDS, one workgroup per CU.  Walls and inlet / outlet columns only: the
-// host keeps single steps on periodic lattices and with the thin-film CL.
+// LDS, one workgroup per CU.  Walls and inlet / outlet columns only (the
+// thin-film CL's reactive wall included): the host keeps single steps on
+// periodic lattices.
 constexpr int kT2X = 64, kT2Y = 12;
 constexpr int kT2W = kT2X + 3;                  // LDS row: x0 - 2 .. x0 + kT2X
 constexpr int kT2N = kT2W * (kT2Y + 2);         // LDS rows: y0 - 1 .. y0 + kT2Y
@@ -134,6 +135,7 @@ __device__ __forceinline__ void step2_tile(R* __restrict__ lds, const R* __restr
   R f[19];
   pull_tile(lds, k, xp, y, x0, y0, f);
   Mat<R> mt = material<R, MAT>(k, phi_f, invk_f, d_f, xp, y);
+  thin_film(f, mt, k, y);
   if (inlet || outlet) {
     Mat<R> mb = material<R, MAT>(k, phi_f, invk_f, d_f, x, y);
     boundary_column(f, k, y, inlet, mt, mb);

@@ -219,9 +219,9 @@ def test_per_cell_fields_need_the_flag_and_valid_values():
 
 def test_two_step_schedule_limits():
     """The two-step form (960-thread workgroups) takes 64 x 12 tiles and no
-    persistent launch, and is refused for a batch with a thin-film CL case; the
+    persistent launch; a batch with a thin-film CL case and the
     pressure-driven polarisation cases take it and equal their single
-    contexts bit for bit over an odd step count."""
+    contexts bit for bit over odd step counts."""
     lbm = _lbm()
     cases = _cases(3)
     b = lbm.BatchedSweep(cases)
@@ -231,8 +231,13 @@ def test_two_step_schedule_limits():
     b.close()
     thin = dict(cases[0], thin_cl=True, ny_gdl=cases[0]["ny_gdl"] + cases[0]["ny_cl"], ny_cl=0)
     t = lbm.BatchedSweep([thin, cases[1]])
-    with pytest.raises(lbm.LbmError, match="invalid argument"):
-        t.set_schedule(64, 12, 0, 960)
+    t.set_schedule(64, 12, 0, 960)
+    t.step(21)
+    for i, w in enumerate((thin, cases[1])):
+        single = lbm.Cathode.from_workload(w)
+        single.step(21)
+        assert torch.equal(t.populations(i), single.populations()), w["name"]
+        single.close()
     t.close()
     pol = W.polarisation_sweep(steps=200)[:4]
     b = lbm.BatchedSweep(pol)
