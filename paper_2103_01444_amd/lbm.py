@@ -613,6 +613,10 @@ class BatchedSweep:
         return dict(tile_x=s.tile_x, tile_y=s.tile_y, persistent=s.persistent, block=s.block)
 
     def set_schedule(self, tile_x: int, tile_y: int, persistent: int, block: int = 0):
+        """Tiles of tile_x x tile_y nodes, one launch per step (persistent
+        = 0) or one cooperative launch (1); block: workgroup size of the
+        per-step form (0 or 256; 64 / 128 for tiles of that many cells; 960
+        with 64 x 12 tiles: two steps per launch)."""
         s = Schedule(tile_x, tile_y, persistent, block)
         self._check(self.lib.lbm_batch_set_schedule(self.h, ctypes.byref(s)))
 
