@@ -493,7 +493,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "traffic_frac": None if traffic is None else round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)},
+                     "traffic_frac": None if traffic is None else round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "note": ("achieved prices each lattice update at the single-step pull scheme's "
+                              f"{bpu} B; the kernel advances {spl} step(s) per launch and moves `traffic` "
+                              "bytes per launch (counters)")},
         "kernel": {"name": "k_step2<float, MAT_PHI>" if spl == 2 else "k_step<float, MAT_PHI>",
                    "steps_per_launch": spl, "launches": launches, "avg_launch_us": round(launch_s * 1e6, 3),
                    "us_per_step": round(ev_ms * 1e3 / args.steps, 3),
