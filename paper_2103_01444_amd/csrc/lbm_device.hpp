@@ -132,7 +132,7 @@ __device__ __forceinline__ Mat<R> material(const Consts<R>& k, const R* __restri
 // from 118.6 us to 112.6 us with it (streamed lines stop displacing the
 // x +- 1 neighbour lines that adjacent wavefronts still need from L2), and
 // it is 9 % slower with plain loads in the final kernel (119.1 against
-// 109.3 us on one box).  The batched sweep of many narrow lattices is the
+// 109.3 us on one GPU).  The batched sweep of many narrow lattices is the
 // other way round: plain loads take it from 182.5 to 175.3 us per step.
 //
 // Wave-uniform addressing: a base address that is the same for every lane
@@ -172,8 +172,8 @@ __device__ __forceinline__ void buffer_store(R* base, uint32_t byte_off, R v) {
 // neighbour shift into a wave-uniform base.  The reverse step, whose
 // register-bound collision adjoint leaves little issue slack, gains from it
 // (per reverse step of the 1024x256 adjoint 34.3 against 35.0 us, on another
-// box 33.4 against 34.9 us); the forward kernels run 0.5-1.5 % slower with
-// it (A/B on one box) and keep the per-lane form.
+// GPU 33.4 against 34.9 us); the forward kernels run 0.5-1.5 % slower with
+// it (A/B on one GPU) and keep the per-lane form.
 template <typename R, bool NT = true, bool UNIFORM = false>
 __device__ __forceinline__ void pull(const R* __restrict__ src, const Consts<R>& k, int x, int y,
                                      R (&f)[19]) {
