@@ -71,9 +71,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const R* __restrict__ src, R* _
 // step two pulls the tile's nodes from LDS and writes `dst`.  Every node
 // runs the same code as k_step, so the states are the bits of two single
 // steps.  HBM traffic per step halves; the halo nodes (22 % of step one)
-// are computed twice.  Twelve rows: the largest tile whose step one fits
-// one pass of a workgroup (938 nodes, 960 threads); FP64 holds 143 KB of
-// LDS, one workgroup per CU.  Walls and inlet / outlet columns only (the
+// are computed twice.  Twelve rows (step one: 938 nodes, 960 threads, one
+// pass) measured faster than four and eight; 13 rows, the last to fit one
+// 1024-thread pass, would save 1 % of the halo work and is not measured.
+// FP64 holds 143 KB of LDS, one workgroup per CU.  Walls and inlet / outlet columns only (the
 // thin-film CL's reactive wall included): the host keeps single steps on
 // periodic lattices.
 constexpr int kT2X = 64, kT2Y = 12;
